@@ -1,0 +1,25 @@
+"""Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False, src: str = None, out: str = None) -> str:
+    """Compile ``src`` (default oracle/oracle.c) into ``out`` (default liboracle.so)."""
+    src = src or os.path.join(HERE, "oracle.c")
+    out = out or LIB
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-I", HERE, src, "-o", out + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,448 @@
+"""Pins of the oracle's whole step: collision invariants, conservation, reductions to
+special cases, and the hydrodynamic limits the paper states (Sec. 2 and 3)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2101_01702_amd import workloads as W
+
+from oracle_cases import CI, fourier_amp, lattice_problem, moments, two_species
+
+
+def _noisy_config1(seed=3, amp_u=0.02, noise=0.01):
+    prob = W.perturb_velocity(W.config1(nx=8, ny=3, nz=2), amp_u, seed)
+    sim = orc.OracleSim(prob).init()
+    pop, T = sim.state()
+    rng = np.random.default_rng(seed)
+    pop = pop * (1.0 + noise * rng.uniform(-1, 1, pop.shape))
+    sim.set_state(pop, T)
+    return prob, sim, pop
+
+
+# --- collision invariants (eqs. finalNumericalEquations, f, g) ---------------------------
+def test_collision_invariants_mixture():
+    """rho' = rho, (rho u)' = rho u + X, (rho E)' = rho E at every node."""
+    prob, sim, pop = _noisy_config1()
+    sim.step(1)
+    post = sim.post()
+    M = prob.M
+    a, b = moments(pop, M), moments(post, M)
+    X = sim.field(orc.F_X)
+    assert np.abs(X).max() > 1e-8                     # the correction is exercised
+    np.testing.assert_allclose(b["rho"], a["rho"], rtol=1e-14)
+    np.testing.assert_allclose(b["j"], a["j"] + X, rtol=0, atol=1e-14 * a["rho"].max())
+    np.testing.assert_allclose(b["rhoE"], a["rhoE"], rtol=1e-13)
+
+
+def test_collision_species_mass_and_momentum():
+    """sum_i f_ai' = rho_a + rho_dot_a (eq. sumfDotc) and, from eqs. fStar and
+    transform1, the post-collision species momentum is 2 rho_a (u + du_a) - j_a +
+    rho_dot_a u (the trapezoidal transform reflects j_a about rho_a (u + du_a))."""
+    prob, sim, pop = _noisy_config1()
+    sim.step(1)
+    post = sim.post()
+    M = prob.M
+    a, b = moments(pop, M), moments(post, M)
+    rdot = sim.field(orc.F_RDOT)
+    du = sim.field(orc.F_DU)
+    assert np.abs(rdot).max() > 0 and np.abs(du).max() > 1e-6
+    u = a["j"] / a["rho"]
+    for s in range(M - 1):
+        np.testing.assert_allclose(b["rho_a"][s], a["rho_a"][s] + rdot[s], rtol=1e-13)
+        expect = 2 * a["rho_a"][s] * (u + du[s]) - a["j_a"][s] + rdot[s] * u
+        np.testing.assert_allclose(b["j_a"][s], expect, rtol=0, atol=1e-14 * a["rho"].max())
+
+
+def test_collision_energy_second_moment_relaxes_with_omega():
+    """g* shares the 0th and 2nd moments of g^eq, so the 2nd moment of g relaxes with
+    omega alone: (R - R_post) = omega (R - R^eq); check it is independent of omega1."""
+    out = []
+    for om1 in (1.3, 0.9):
+        prob, sim, pop = _noisy_config1()
+        prob.omega1 = om1
+        sim = orc.OracleSim(prob)
+        sim.set_state(pop, sim.state()[1] * 0 + 1000.0)
+        sim.step(1)
+        post = sim.post()
+        R0 = np.einsum("in,ia,ib->abn", pop[prob.M], CI, CI)
+        R1 = np.einsum("in,ia,ib->abn", post[prob.M], CI, CI)
+        out.append((R0 - R1) / prob.omega)
+    np.testing.assert_allclose(out[0], out[1], rtol=0, atol=1e-13 * np.abs(out[0]).max())
+
+
+# --- global conservation (periodic, config 1) --------------------------------------------
+def test_global_conservation_config1():
+    """Mass, momentum (X telescopes), total energy incl. formation, element moles."""
+    prob = W.config1()
+    x = np.arange(prob.N) % prob.nx
+    prob.u[0] = 0.01 * np.sin(2 * math.pi * x / prob.nx)
+    prob.u[1] = 0.005 * np.cos(2 * math.pi * x / prob.nx)
+    sim = orc.OracleSim(prob).init()
+    mech = prob.mech
+
+    def totals():
+        pop, _ = sim.state()
+        mo = moments(pop, prob.M)
+        moles = mo["rho_a"] / mech.molar_mass[:, None]
+        elem = (mech.elements.T @ moles).sum(1)
+        return mo["rho"].sum(), mo["j"].sum(1), mo["rhoE"].sum(), elem
+
+    t0 = totals()
+    assert sim.step(200) == 0
+    t1 = totals()
+    assert t1[0] == pytest.approx(t0[0], rel=1e-13)
+    np.testing.assert_allclose(t1[1], t0[1], rtol=0, atol=1e-12 * t0[0])
+    assert t1[2] == pytest.approx(t0[2], rel=1e-12)
+    np.testing.assert_allclose(t1[3], t0[3], rtol=1e-12)
+    # the reaction did run
+    mac = sim.macros()
+    assert mac["T"].mean() > 1050.0
+
+
+# --- special cases --------------------------------------------------------------------
+def test_rest_state_is_fixed_point():
+    mech = W.abc_mechanism(R_count=0)
+    prob = lattice_problem(mech, 6, 3, 2, X=[0.3, 0.3, 0.4])
+    sim = orc.OracleSim(prob).init()
+    p0, _ = sim.state()
+    sim.step(50)
+    p1, _ = sim.state()
+    np.testing.assert_allclose(p1, p0, rtol=0, atol=1e-13 * np.abs(p0).max())
+
+
+def test_uniform_flow_through_open_faces_is_preserved():
+    """A uniform moving state with open faces everywhere stays uniform: the ghost
+    equilibria equal the interior post-collision populations."""
+    mech = W.abc_mechanism(R_count=0)
+    N = 5 * 4 * 3
+    u = np.tile(np.array([[0.03], [-0.02], [0.01]]), (1, N))
+    prob = lattice_problem(mech, 5, 4, 3, bc=(1,) * 6, X=[0.3, 0.3, 0.4], u=u)
+    sim = orc.OracleSim(prob).init()
+    p0, _ = sim.state()
+    sim.step(20)
+    p1, _ = sim.state()
+    np.testing.assert_allclose(p1, p0, rtol=0, atol=1e-13 * np.abs(p0).max())
+
+
+def test_nonreactive_reduction_bitwise():
+    """No reactions and reactions with zero rate give bit-identical states."""
+    base = W.perturb_velocity(W.config1(nx=8, ny=2, nz=2, reacting=False), 0.01, 1)
+    zero = W.perturb_velocity(W.config1(nx=8, ny=2, nz=2, reacting=True), 0.01, 1)
+    zero.mech.arrhenius[:, 0] = 0.0
+    a = orc.OracleSim(base).init()
+    b = orc.OracleSim(zero).init()
+    a.step(30)
+    b.step(30)
+    np.testing.assert_array_equal(a.state()[0], b.state()[0])
+
+
+def test_thread_count_bitwise():
+    prob = W.perturb_velocity(W.config1(), 0.002, 2)
+    a = orc.OracleSim(prob).init()
+    b = orc.OracleSim(prob).init()
+    a.step(20, threads=1)
+    b.step(20, threads=4)
+    np.testing.assert_array_equal(a.state()[0], b.state()[0])
+
+
+def test_axis_permutation_symmetry():
+    """A problem varying along x, y or z gives the same profile (indexing pin)."""
+    rng = np.random.default_rng(11)
+    L = 12
+    prof_X = 0.3 + 0.05 * np.sin(2 * math.pi * np.arange(L) / L + 0.4)
+    prof_u = 0.02 * rng.uniform(-1, 1, L)
+    res = []
+    for axis in range(3):
+        dims = [2, 2, 2]
+        dims[axis] = L
+        nx, ny, nz = dims
+        n = np.arange(nx * ny * nz)
+        coord = [n % nx, (n // nx) % ny, n // (nx * ny)][axis]
+        X = np.stack([prof_X[coord], np.full(n.size, 0.3), 0.7 - prof_X[coord]])
+        u = np.zeros((3, n.size))
+        u[axis] = prof_u[coord]
+        prob = lattice_problem(W.abc_mechanism(A=3e7), nx, ny, nz, X=X, u=u, zeta_ref=0.05)
+        sim = orc.OracleSim(prob).init()
+        sim.step(15)
+        mac = sim.macros()
+        order = np.argsort(coord, kind="stable")[::8]
+        res.append((mac["rho"][order], mac["T"][order], mac["u"][axis][order], mac["Y"][:, order]))
+    for r in res[1:]:
+        for x0, x1 in zip(res[0], r):
+            np.testing.assert_allclose(x1, x0, rtol=1e-12, atol=1e-16)
+
+
+# --- homogeneous reactor: explicit Euler of the adiabatic constant-volume ODE ----------
+def _isothermal_abc(A=2e8, Ta=6000.0):
+    # U_C = U_A + U_B per mole at every T: a1_C = a1_A + a1_B - 1, a6_C = a6_A + a6_B
+    hA, hB = 0.0, 0.0
+    hC = hA + hB - W.R_U * W.T_REF
+    return W.abc_mechanism(A=A, Ta=Ta, cp=(2.5, 2.5, 4.0), h_f=(hA, hB, hC))
+
+
+def test_homogeneous_isothermal_reactor_exact_recurrence():
+    """Uniform state at rest: F = 0, X = 0, grad Y = 0, and the step is exactly
+    rho_a <- rho_a + rho_dot_a; with no heat of reaction T stays constant and the
+    concentrations follow the explicit-Euler map of d[A]/dt = -k [A][B]."""
+    mech = _isothermal_abc()
+    prob = lattice_problem(mech, 2, 2, 1, X=[0.35, 0.25, 0.4], zeta_ref=0.05, dt_phys=0.05)
+    sim = orc.OracleSim(prob).init()
+    mac = sim.macros()
+    c = mac["Y"][:, 0] * mac["rho"][0] * prob.rho_ref / mech.molar_mass
+    T = 1000.0
+    k = 2e8 * math.exp(-6000.0 / T)
+    cA, cB, cC = c
+    for n in range(1, 41):
+        sim.step(1)
+        q = k * cA * cB * prob.dt_phys
+        cA, cB, cC = cA - q, cB - q, cC + q
+        if n % 10 == 0:
+            mac = sim.macros()
+            co = mac["Y"][:, 0] * mac["rho"][0] * prob.rho_ref / mech.molar_mass
+            np.testing.assert_allclose(co, [cA, cB, cC], rtol=1e-12)
+            assert mac["T"][0] == pytest.approx(T, rel=1e-12)
+            np.testing.assert_allclose(mac["Y"], np.broadcast_to(mac["Y"][:, :1], mac["Y"].shape), rtol=1e-14)
+    assert cA < 0.8 * c[0]   # reaction progressed
+
+
+def test_homogeneous_reactor_converges_to_ode_first_order():
+    """Against the closed-form solution [A] = [A]0 / (1 + k [A]0 t) ([A]0 = [B]0): the
+    explicit step is first order, the error halves with the step."""
+    mech = _isothermal_abc()
+    errs = []
+    t_end = 4.0
+    for dt in (0.1, 0.05):
+        prob = lattice_problem(mech, 1, 1, 1, X=[0.3, 0.3, 0.4], zeta_ref=0.05, dt_phys=dt)
+        sim = orc.OracleSim(prob).init()
+        mac = sim.macros()
+        c0 = mac["Y"][0, 0] * mac["rho"][0] * prob.rho_ref / mech.molar_mass[0]
+        k = 2e8 * math.exp(-6000.0 / 1000.0)
+        sim.step(int(round(t_end / dt)))
+        mac = sim.macros()
+        cA = mac["Y"][0, 0] * mac["rho"][0] * prob.rho_ref / mech.molar_mass[0]
+        exact = c0 / (1 + k * c0 * t_end)
+        errs.append(abs(cA - exact) / exact)
+        assert exact < 0.7 * c0
+    assert errs[0] / errs[1] == pytest.approx(2.0, rel=0.1)
+    assert errs[0] < 0.05
+
+
+def test_adiabatic_reactor_temperature_from_energy_balance():
+    """Heat of formation drives the temperature (Sec. 3): with constant c_p the
+    temperature at every step is the closed form solving sum_a Y_a U_a(T) = E0."""
+    prob = lattice_problem(W.abc_mechanism(A=2e7, Ta=6000.0), 1, 1, 1, X=[0.3, 0.3, 0.4],
+                           zeta_ref=0.05, dt_phys=0.2)
+    mech = prob.mech
+    sim = orc.OracleSim(prob).init()
+    pop, _ = sim.state()
+    E0 = pop[prob.M].sum() / pop[prob.M - 1].sum()
+    Ra = prob.kappa * W.R_U / (mech.molar_mass * 1e-3)
+    a1, a6 = mech.nasa7[:, 0], mech.nasa7[:, 5]
+    for _ in range(5):
+        sim.step(20)
+        mac = sim.macros()
+        Y = mac["Y"][:, 0]
+        T_cf = (E0 - (Y * Ra * a6).sum()) / (Y * Ra * (a1 - 1)).sum()
+        assert mac["T"][0] == pytest.approx(T_cf, rel=1e-12)
+    assert mac["T"][0] > 1100.0
+
+
+def test_adiabatic_reactor_matches_ode_integration():
+    """Independent ODE integration (scipy, tight tolerance) of the adiabatic
+    constant-volume reactor; the lattice step converges to it at first order."""
+    from scipy.integrate import solve_ivp
+    mech = W.abc_mechanism(A=2e7, Ta=6000.0)
+    t_end = 20.0
+    errs = []
+    for dt in (0.2, 0.1):
+        prob = lattice_problem(mech, 1, 1, 1, X=[0.3, 0.3, 0.4], zeta_ref=0.05, dt_phys=dt)
+        sim = orc.OracleSim(prob).init()
+        mac0 = sim.macros()
+        rho = mac0["rho"][0]
+        c0 = mac0["Y"][:, 0] * rho * prob.rho_ref / mech.molar_mass
+        # molar internal energy of species a with constant c_p: R (a1 - 1) T + R a6
+        a1, a6 = mech.nasa7[:, 0], mech.nasa7[:, 5]
+        Uc = lambda c, T: float((c * W.R_U * ((a1 - 1) * T + a6)).sum())
+        U0 = Uc(c0, 1000.0)
+
+        def T_of(c):
+            return (U0 - (c * W.R_U * a6).sum()) / (c * W.R_U * (a1 - 1)).sum()
+
+        def rhs(t, c):
+            T = T_of(c)
+            q = 2e7 * math.exp(-6000.0 / T) * c[0] * c[1]
+            return [-q, -q, q]
+
+        ode = solve_ivp(rhs, (0, t_end), c0, method="Radau", rtol=1e-11, atol=1e-20)
+        sim.step(int(round(t_end / dt)))
+        mac = sim.macros()
+        cA = mac["Y"][0, 0] * rho * prob.rho_ref / mech.molar_mass[0]
+        errs.append(abs(cA - ode.y[0, -1]) / ode.y[0, -1])
+        assert T_of(ode.y[:, -1]) == pytest.approx(mac["T"][0], rel=2e-3)
+    assert errs[0] / errs[1] == pytest.approx(2.0, rel=0.15)
+    assert errs[1] < 0.03
+
+
+# --- hydrodynamic limits (Sec. 2 eqs. dtrhoa/constit2; Sec. 3 eqs. mu, lambda) ---------
+@pytest.mark.parametrize("D", [0.03, 0.08])
+def test_fickian_decay_binary(D):
+    """Binary mixture of equal molar masses, no reaction: a small sinusoidal
+    composition perturbation decays at D k^2 (Stefan-Maxwell reduces to Fick)."""
+    L = 64
+    mech = two_species()
+    x = np.arange(L)
+    eps = 1e-3
+    X1 = 0.5 + eps * np.sin(2 * math.pi * x / L)
+    prob = lattice_problem(mech, L, X=np.stack([X1, 1 - X1]), D=D)
+    sim = orc.OracleSim(prob).init()
+    k = 2 * math.pi / L
+    amps, ts = [], []
+    for n in range(6):
+        mac = sim.macros()
+        amps.append(fourier_amp(mac["Y"][0] - mac["Y"][0].mean(), L))
+        ts.append(n * 300)
+        sim.step(300)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    assert rate == pytest.approx(D * k * k, rel=0.01)
+
+
+def test_shear_wave_decay_viscosity():
+    """u_y = eps sin(kx) decays at nu k^2 with nu = (1/omega - 1/2) R T (eq. mu)."""
+    L = 64
+    mech = two_species()
+    x = np.arange(L)
+    u = np.zeros((3, L))
+    u[1] = 1e-3 * np.sin(2 * math.pi * x / L)
+    for omega in (1.6, 1.1):
+        prob = lattice_problem(mech, L, u=u, omega=omega)
+        sim = orc.OracleSim(prob).init()
+        zeta = prob.kappa * W.R_U * 1000.0 / 28e-3
+        nu = (1 / omega - 0.5) * zeta
+        k = 2 * math.pi / L
+        amps, ts = [], []
+        for n in range(5):
+            amps.append(fourier_amp(sim.macros()["u"][1], L))
+            ts.append(n * 200)
+            sim.step(200)
+        rate = -np.polyfit(ts, np.log(amps), 1)[0]
+        assert rate == pytest.approx(nu * k * k, rel=0.01)
+
+
+def test_thermal_mode_decay_conductivity():
+    """Isobaric temperature perturbation decays at lambda/(rho C_p) k^2 =
+    (1/omega1 - 1/2) R T k^2 (eq. lambda)."""
+    L = 64
+    mech = two_species()
+    x = np.arange(L)
+    T0, eps = 1000.0, 2e-3
+    Tf = T0 * (1 + eps * np.sin(2 * math.pi * x / L))
+    prob = lattice_problem(mech, L, T_field=Tf, omega=1.3, prandtl=0.7)
+    sim = orc.OracleSim(prob).init()
+    zeta = prob.kappa * W.R_U * T0 / 28e-3
+    alpha = (1 / prob.omega1 - 0.5) * zeta
+    k = 2 * math.pi / L
+    amps, ts = [], []
+    for n in range(8):
+        amps.append(fourier_amp(sim.macros()["T"] - T0, L))
+        ts.append(n * 150)
+        sim.step(150)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    assert rate == pytest.approx(alpha * k * k, rel=0.03)
+
+
+def interdiffusion_temperature_drift(sim_factory=None, steps=600):
+    """Binary mixture, equal molar masses and heat capacities, different formation
+    enthalpies, uniform T and P with a composition wave: returns (max |T - T0|,
+    scale) where scale is the temperature change the same composition change would
+    cause if its formation energy stayed in place."""
+    L = 32
+    mech = two_species(h_f=(0.0, 60e3))
+    x = np.arange(L)
+    eps = 0.02
+    X1 = 0.5 + eps * np.sin(2 * math.pi * x / L)
+    prob = lattice_problem(mech, L, X=np.stack([X1, 1 - X1]), D=0.08, omega=1.5, prandtl=0.5)
+    sim = (sim_factory or orc.OracleSim)(prob).init()
+    T0 = 1000.0
+    sim.step(steps)
+    mac = sim.macros()
+    cv_molar = (3.5 - 1) * W.R_U
+    scale = eps * 60e3 / cv_molar
+    return np.abs(mac["T"] - T0).max(), scale
+
+
+def test_interdiffusion_carries_formation_enthalpy():
+    """q^diff and q^corr (eqs. qdiff, corrFourier) make the energy flux carry the
+    enthalpy of the diffusing species: with no reaction and uniform T the temperature
+    stays uniform while the composition relaxes."""
+    drift, scale = interdiffusion_temperature_drift()
+    assert drift < 2e-3 * scale
+
+
+def viscous_work_flux_after_collision(omega1, sim_factory=None):
+    """Uniform state moving at U with a non-equilibrium stress Pi in f and the matching
+    viscous-work flux U.Pi in g (no heat-flux part).  Returns the post-collision first
+    moment of g at one node."""
+    mech = W.abc_mechanism(R_count=0)
+    N = 2 * 2 * 2
+    U = np.array([0.04, -0.03, 0.02])
+    u = np.tile(U[:, None], (1, N))
+    prob = lattice_problem(mech, 2, 2, 2, X=[0.3, 0.3, 0.4], u=u, omega=1.5)
+    prob.omega1 = omega1
+    sim = (sim_factory or orc.OracleSim)(prob).init()
+    pop, T = sim.state()
+    w1 = np.array([1 / 6, 2 / 3, 1 / 6])
+    w = np.array([w1[int(c[0]) + 1] * w1[int(c[1]) + 1] * w1[int(c[2]) + 1] for c in CI])
+    # zero mass and momentum, second moment Pi = diag(1,-1,0)*a + offdiag b
+    a, b = 2e-4, 1e-4
+    dfa = w * (CI[:, 0] ** 2 - CI[:, 1] ** 2) * a / (2 / 9 * 2) * 2
+    dfb = w * CI[:, 0] * CI[:, 1] * b * 9
+    df = dfa + dfb
+    Pi = np.einsum("i,ia,ib->ab", df, CI, CI)
+    dg = w * (CI @ (U @ Pi)) * 3.0
+    pop[prob.M - 1] += df[:, None]
+    pop[prob.M] += dg[:, None]
+    sim.set_state(pop, T)
+    sim.step(1)
+    post = sim.post()
+    return CI.T @ post[prob.M][:, 0], Pi
+
+
+def test_viscous_work_flux_relaxes_with_viscous_rate():
+    """The term -u.(P - P^eq) of eq. gstareq1mom makes the viscous-work part of the
+    energy flux relax with omega (variable Prandtl number): with no heat-flux part the
+    post-collision flux is independent of omega1."""
+    q1, Pi = viscous_work_flux_after_collision(1.2)
+    q2, _ = viscous_work_flux_after_collision(0.8)
+    assert np.abs(Pi).max() > 1e-5
+    np.testing.assert_allclose(q1, q2, rtol=0, atol=1e-12 * np.abs(q1).max())
+
+
+def sound_damping(U, sim_factory=None):
+    """Damping rate of a standing acoustic density wave in a frame moving at U."""
+    L = 48
+    x = np.arange(L)
+    u = np.zeros((3, L))
+    u[0] = U
+    prob = lattice_problem(two_species(), L, u=u, omega=1.3, zeta_ref=0.1)
+    prob.rho = prob.rho * (1 + 1e-3 * np.sin(2 * math.pi * x / L))
+    sim = (sim_factory or orc.OracleSim)(prob).init()
+    amps, ts = [], []
+    for n in range(300):
+        m = sim.macros()
+        amps.append(fourier_amp(m["rho"] - m["rho"].mean(), L))
+        ts.append(2 * n)
+        if sim.step(2):
+            return float("nan")
+    amps, ts = np.array(amps), np.array(ts)
+    peaks = [i for i in range(1, len(amps) - 1) if amps[i] >= amps[i - 1] and amps[i] >= amps[i + 1]]
+    return -np.polyfit(ts[peaks], np.log(amps[peaks]), 1)[0]
+
+
+def test_sound_damping_galilean_invariance():
+    """Acoustic damping is frame independent up to the O(Ma^2) lattice error; the
+    isotropy correction X (eq. Xalpha) with its cubic term keeps it so at Ma ~ 0.27."""
+    g0, g1 = sound_damping(0.0), sound_damping(0.1)
+    assert g0 > 0
+    assert abs(g1 / g0 - 1) < 0.15
