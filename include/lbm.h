@@ -1,0 +1,168 @@
+/*
+ * C ABI of the reactive-mixture lattice Boltzmann step on one MI355X (gfx950).
+ *
+ * The model is the one of Sawant, Dorschner & Karlin, "Reactive mixtures with the
+ * lattice Boltzmann model": M species populations (Sec. 2, eq. finalNumerical-
+ * Equations) relaxing to a Stefan-Maxwell quasi-equilibrium with an Arrhenius
+ * source, a mixture population f for mass and momentum (Sec. 3, eq. f) and an
+ * energy population g for total energy with heat of formation (Sec. 3, eq. g),
+ * temperature recovered from energy (eq. temperature), on the D3Q27 lattice.  The
+ * last species is slaved to the mixture (eq. strongest), so M + 1 population sets
+ * are stored.
+ *
+ * Conventions
+ *   - Lattice units dx = dt = 1.  Node n = x + nx (y + ny z), x fastest.
+ *   - Velocity index i = (cx+1) + 3 (cy+1) + 9 (cz+1), c in {-1,0,1}^3.
+ *   - Population sets s = 0..M-2 species, s = M-1 mixture f, s = M energy g.
+ *   - All device pointers are caller-owned; the library never allocates or frees
+ *     device memory.  Device work is enqueued on the given stream (a hipStream_t
+ *     passed as void*, NULL = default stream) and is asynchronous; only
+ *     lbm_status_sync and lbm_step_timed wait for the device.
+ *   - Every call returns an lbm_status; nothing aborts or throws across the ABI.
+ *     On error, lbm_last_error(h) explains it (lbm_last_error(NULL) for errors of
+ *     calls that have no handle).
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef REACTLBM_LBM_H
+#define REACTLBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx *lbm_handle;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,            /* invalid argument or descriptor                 */
+  LBM_ERR_UNSUPPORTED = -2,    /* valid but not provided by this build           */
+  LBM_ERR_HIP = -3,            /* a HIP runtime call failed                      */
+  LBM_ERR_WORKSPACE = -4,      /* workspace too small or misaligned              */
+  LBM_ERR_DEVICE_ANOMALY = -5  /* lbm_status_sync found anomaly bits set         */
+} lbm_status;
+
+/* boundary types per face (Sec. 5.1: zero-gradient ends by equilibrium ghosts,
+ * zero velocity imposed at the unburnt end) */
+enum {
+  LBM_BC_PERIODIC = 0, /* both faces of an axis must be periodic together        */
+  LBM_BC_OPEN_EQ = 1,  /* ghost = equilibrium at the adjacent node's rho_a, u, T  */
+  LBM_BC_OPEN_EQ_U0 = 2 /* same with ghost velocity 0                            */
+};
+
+/* population storage; FP64 islands (temperature inversion, thermo, production
+ * rates, Stefan-Maxwell solve) are double precision in both */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1 };
+
+/* anomaly bits latched on the device, read by lbm_status_sync */
+enum {
+  LBM_ANOM_NONFINITE = 1u,    /* non-finite density, energy or temperature        */
+  LBM_ANOM_NEWTON = 2u,       /* temperature inversion did not converge in 50 its */
+  LBM_ANOM_NEG_DENSITY = 4u   /* rho <= 0 or slaved species density <= 0          */
+};
+
+#define LBM_MAX_SPECIES 10
+#define LBM_MAX_REACTIONS 64
+
+/*
+ * Statement of the problem (Sec. 2-4).  Host arrays, copied by lbm_create.
+ *   nx, ny, nz      lattice size, each >= 1
+ *   bc[6]           faces -x,+x,-y,+y,-z,+z (LBM_BC_*)
+ *   n_species       M, 2..LBM_MAX_SPECIES; species M-1 is slaved (eq. strongest)
+ *   n_reactions     R, 0..LBM_MAX_REACTIONS
+ *   molar_mass[M]   g/mol
+ *   nasa7[M][7]     single-range NASA-7 coefficients (c_p/R polynomial a1..a5,
+ *                   enthalpy constant a6 including the formation enthalpy,
+ *                   entropy constant a7); eq. specHa
+ *   diff_ab[M][M]   binary diffusivities D_ab in lattice units, symmetric, > 0
+ *                   off the diagonal (eqs. stefanMaxwell, tauab)
+ *   nu_reac[R][M], nu_prod[R][M]   stoichiometric coefficients, 0..3
+ *   arrhenius[R][3] A (CGS mol, cm^3, s), temperature exponent b, activation
+ *                   temperature Ta (K): k_f = A T^b exp(-Ta/T)
+ *   reversible[R]   nonzero: reverse rate k_f / K_c, K_c from the NASA-7 Gibbs
+ *                   function at p0
+ *   omega, omega1   relaxation of f and of the energy flux (eqs. f, g), in (0,2)
+ *   kappa           (dt/dx)^2 in s^2/m^2: lattice R_a T = kappa R_U T / m_a
+ *   dt_phys         seconds per step (chemistry)
+ *   rho_ref         g/cm^3 per lattice density unit (chemistry)
+ *   p0              standard pressure of the thermo data, Pa (Sec. 4: 1 atm)
+ *   storage         LBM_STORE_*
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t bc[6];
+  int32_t n_species;
+  int32_t n_reactions;
+  const double *molar_mass;
+  const double *nasa7;
+  const double *diff_ab;
+  const int32_t *nu_reac;
+  const int32_t *nu_prod;
+  const double *arrhenius;
+  const uint8_t *reversible;
+  double omega, omega1;
+  double kappa, dt_phys, rho_ref, p0;
+  int32_t storage;
+  int32_t reserved;
+} lbm_desc;
+
+/* Bytes of device workspace the descriptor needs (populations x2 with a ghost
+ * layer on open axes, temperature, side channel, tables, status word). */
+lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
+
+/* Validate the descriptor, copy it, and upload its tables into the caller's
+ * device workspace (256-byte aligned, >= lbm_workspace_size bytes, must outlive
+ * the handle).  The current HIP device must be the workspace's device.  The
+ * upload is synchronous. */
+lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm_handle *out);
+
+/* Release the host handle (the workspace is untouched). */
+lbm_status lbm_destroy(lbm_handle h);
+
+/* Equilibrium initial state (no non-equilibrium part) from device FP64 fields:
+ * rho[N], u[3][N], T[N] (K), Y[M][N] mass fractions.  Also sets the stored
+ * temperature (Newton start) and clears the anomaly word. */
+lbm_status lbm_init_fields(lbm_handle h, const double *d_rho, const double *d_u,
+                           const double *d_T, const double *d_Y, void *stream);
+
+/* Advance n_steps >= 0 time steps (one step: moments, temperature, chemistry,
+ * Stefan-Maxwell solve, collision of all sets, ghosts, streaming). */
+lbm_status lbm_step(lbm_handle h, int32_t n_steps, void *stream);
+
+/* Same as lbm_step, then waits and returns the summed device time of each kernel
+ * kind in ms_out[LBM_NUM_KERNELS] (HIP events around every launch). */
+#define LBM_NUM_KERNELS 4 /* 0 main step, 1 psi stencil, 2 correction stencil, 3 ghosts */
+lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms_out);
+
+/* Macroscopic fields of the current (pre-collision) state into device FP64
+ * arrays, any of which may be NULL: rho[N], u[3][N], T[N], P[N] (lattice
+ * pressure rho R T), Y[M][N].  Does not modify the state. */
+lbm_status lbm_macros(lbm_handle h, double *d_rho, double *d_u, double *d_T, double *d_P,
+                      double *d_Y, void *stream);
+
+/* Pre-collision populations of the current state at the listed nodes (device
+ * int64 node ids in [0, N)) as FP64 out[(s*27 + i)*n_nodes + k], and the stored
+ * temperature at those nodes in T_out[k] (T_out may be NULL). */
+lbm_status lbm_populations(lbm_handle h, const int64_t *d_nodes, int64_t n_nodes, double *d_out,
+                           double *d_T_out, void *stream);
+
+/* Discrete adjoint of one step.  Not provided by this build: returns
+ * LBM_ERR_UNSUPPORTED. */
+lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, double *d_grad_params,
+                            void *stream);
+
+/* Wait for the stream, return the latched anomaly bits and clear them.  Returns
+ * LBM_ERR_DEVICE_ANOMALY when any bit was set. */
+lbm_status lbm_status_sync(lbm_handle h, void *stream, uint32_t *anomaly_bits);
+
+/* Message of the last failed call on h (or of a handle-less call for NULL);
+ * valid until the next call on the same handle. */
+const char *lbm_last_error(lbm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

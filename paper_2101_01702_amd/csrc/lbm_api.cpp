@@ -1,0 +1,430 @@
+// Host side of the C ABI: descriptor validation, workspace layout, table upload and
+// the launch sequence of one step.  No device memory is allocated here: the
+// workspace belongs to the caller.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr double R_UNIV = 8.314462618;
+constexpr size_t ALIGN = 256;
+
+thread_local std::string g_last_error;
+
+size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  size_t status, tables, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, total;
+  size_t corr_bytes;
+};
+
+Geom make_geom(const lbm_desc &d) {
+  Geom g{};
+  g.M = d.n_species;
+  g.nx = d.nx; g.ny = d.ny; g.nz = d.nz;
+  const int n[3] = {d.nx, d.ny, d.nz};
+  int pad[3];
+  for (int a = 0; a < 3; ++a) {
+    g.per[a] = d.bc[2 * a] == LBM_BC_PERIODIC ? 1 : 0;
+    pad[a] = g.per[a] ? 0 : 1;
+  }
+  for (int k = 0; k < 6; ++k) g.bc[k] = d.bc[k];
+  g.px = pad[0]; g.py = pad[1]; g.pz = pad[2];
+  g.NX = n[0] + 2 * pad[0]; g.NY = n[1] + 2 * pad[1]; g.NZ = n[2] + 2 * pad[2];
+  g.N = (int64_t)d.nx * d.ny * d.nz;
+  g.NPAD = (int64_t)g.NX * g.NY * g.NZ;
+  return g;
+}
+
+Layout make_layout(const lbm_desc &d, const Geom &g) {
+  const size_t st = d.storage == LBM_STORE_F64 ? 8 : 4;   // population storage word size
+  const size_t ct = 8;                                      // compute word size (side channel)
+  const size_t S = (size_t)d.n_species + 1;
+  const size_t N = (size_t)g.N, M = (size_t)d.n_species;
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes);
+    return at;
+  };
+  L.status = take(64);
+  L.tables = take(sizeof(Tables));
+  L.pop0 = take(S * Q * (size_t)g.NPAD * st);
+  L.pop1 = take(S * Q * (size_t)g.NPAD * st);
+  L.T = take(N * 8);
+  L.side_Y = take(M * N * ct);
+  L.side_w = take(M * N * ct);
+  L.side_phi = take(3 * N * ct);
+  L.side_rho = take(N * ct);
+  L.side_u = take(3 * N * ct);
+  L.psi = take(3 * N * ct);
+  L.corr_bytes = 6 * N * ct;
+  L.corr = take(L.corr_bytes);
+  L.total = off;
+  return L;
+}
+
+bool fail(std::string *where, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  *where = buf;
+  return false;
+}
+
+bool validate(const lbm_desc *d, std::string *err) {
+  if (!d) return fail(err, "descriptor is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(err, "lattice sizes must be >= 1 (got %d x %d x %d)", d->nx, d->ny, d->nz);
+  const double nodes = (double)d->nx * d->ny * d->nz;
+  if (nodes > 1073741824.0) return fail(err, "lattice has %.0f nodes; at most 2^30 are supported", nodes);
+  for (int a = 0; a < 3; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      const int b = d->bc[2 * a + s];
+      if (b != LBM_BC_PERIODIC && b != LBM_BC_OPEN_EQ && b != LBM_BC_OPEN_EQ_U0)
+        return fail(err, "bc[%d] = %d is not a boundary type", 2 * a + s, b);
+    }
+    if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))
+      return fail(err, "axis %d: periodic faces must come in pairs", a);
+  }
+  const int M = d->n_species, R = d->n_reactions;
+  if (M < 2 || M > LBM_MAX_SPECIES) return fail(err, "n_species = %d outside [2, %d]", M, LBM_MAX_SPECIES);
+  if (R < 0 || R > LBM_MAX_REACTIONS) return fail(err, "n_reactions = %d outside [0, %d]", R, LBM_MAX_REACTIONS);
+  if (!d->molar_mass || !d->nasa7 || !d->diff_ab) return fail(err, "species arrays must not be NULL");
+  if (R > 0 && (!d->nu_reac || !d->nu_prod || !d->arrhenius || !d->reversible))
+    return fail(err, "reaction arrays must not be NULL when n_reactions > 0");
+  for (int a = 0; a < M; ++a) {
+    if (!(d->molar_mass[a] > 0.0) || !std::isfinite(d->molar_mass[a])) return fail(err, "molar_mass[%d] must be > 0", a);
+    for (int k = 0; k < 7; ++k)
+      if (!std::isfinite(d->nasa7[a * 7 + k])) return fail(err, "nasa7[%d][%d] is not finite", a, k);
+    for (int b = 0; b < M; ++b) {
+      if (a == b) continue;
+      const double D = d->diff_ab[a * M + b], Dt = d->diff_ab[b * M + a];
+      if (!(D > 0.0) || !std::isfinite(D)) return fail(err, "diff_ab[%d][%d] must be > 0", a, b);
+      if (std::fabs(D - Dt) > 1e-12 * std::fabs(D)) return fail(err, "diff_ab is not symmetric at (%d, %d)", a, b);
+    }
+  }
+  for (int k = 0; k < R; ++k) {
+    double mass_in = 0.0, mass_out = 0.0;
+    for (int a = 0; a < M; ++a) {
+      const int nr = d->nu_reac[k * M + a], np = d->nu_prod[k * M + a];
+      if (nr < 0 || nr > 3 || np < 0 || np > 3) return fail(err, "reaction %d: stoichiometric coefficients must be in 0..3", k);
+      mass_in += nr * d->molar_mass[a];
+      mass_out += np * d->molar_mass[a];
+    }
+    if (std::fabs(mass_in - mass_out) > 1e-9 * (mass_in + mass_out))
+      return fail(err, "reaction %d does not conserve mass", k);
+    const double A = d->arrhenius[k * 3], b = d->arrhenius[k * 3 + 1], Ta = d->arrhenius[k * 3 + 2];
+    if (!(A >= 0.0) || !std::isfinite(A) || !std::isfinite(b) || !std::isfinite(Ta))
+      return fail(err, "reaction %d: Arrhenius parameters must be finite with A >= 0", k);
+  }
+  if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(err, "omega = %g outside (0, 2)", d->omega);
+  if (!(d->omega1 > 0.0 && d->omega1 < 2.0)) return fail(err, "omega1 = %g outside (0, 2)", d->omega1);
+  if (!(d->kappa > 0.0) || !std::isfinite(d->kappa)) return fail(err, "kappa must be > 0");
+  if (!(d->dt_phys >= 0.0) || !std::isfinite(d->dt_phys)) return fail(err, "dt_phys must be >= 0");
+  if (!(d->rho_ref > 0.0) || !std::isfinite(d->rho_ref)) return fail(err, "rho_ref must be > 0");
+  if (!(d->p0 > 0.0) || !std::isfinite(d->p0)) return fail(err, "p0 must be > 0");
+  if (d->storage != LBM_STORE_F64 && d->storage != LBM_STORE_F32)
+    return fail(err, "storage = %d is not supported", d->storage);
+  return true;
+}
+
+void build_tables(const lbm_desc &d, Tables &t) {
+  std::memset(&t, 0, sizeof(t));
+  const int M = d.n_species, R = d.n_reactions;
+  t.M = M;
+  t.R = R;
+  t.S = M + 1;
+  t.open_any = (d.bc[0] != LBM_BC_PERIODIC) || (d.bc[2] != LBM_BC_PERIODIC) || (d.bc[4] != LBM_BC_PERIODIC);
+  for (int a = 0; a < M; ++a) {
+    const double *n = d.nasa7 + a * 7;
+    const double Ra = d.kappa * R_UNIV / (d.molar_mass[a] * 1e-3);
+    t.Ra[a] = Ra;
+    for (int k = 0; k < 7; ++k) t.nasa[a][k] = n[k];
+    // U_a = Ra (T h - T) with T h = a1 T + a2 T^2/2 + ... + a5 T^5/5 + a6
+    t.ucoef[a][0] = Ra * n[5];
+    t.ucoef[a][1] = Ra * (n[0] - 1.0);
+    t.ucoef[a][2] = Ra * n[1] / 2.0;
+    t.ucoef[a][3] = Ra * n[2] / 3.0;
+    t.ucoef[a][4] = Ra * n[3] / 4.0;
+    t.ucoef[a][5] = Ra * n[4] / 5.0;
+    t.cvcoef[a][0] = Ra * (n[0] - 1.0);
+    for (int k = 1; k < 5; ++k) t.cvcoef[a][k] = Ra * n[k];
+    for (int b = 0; b < M; ++b) {
+      t.invD[a][b] = (a == b) ? 0.0 : 1.0 / d.diff_ab[a * M + b];
+      t.invDf[a][b] = (float)t.invD[a][b];
+    }
+    t.conc_scale[a] = d.rho_ref / d.molar_mass[a];
+    t.rdot_scale[a] = d.molar_mass[a] * d.dt_phys / d.rho_ref;
+  }
+  for (int k = 0; k < R; ++k) {
+    const double A = d.arrhenius[k * 3];
+    t.lnA[k] = A > 0.0 ? std::log(A) : -HUGE_VAL;
+    t.bexp[k] = d.arrhenius[k * 3 + 1];
+    t.Ta[k] = d.arrhenius[k * 3 + 2];
+    t.rev[k] = d.reversible[k] ? 1 : 0;
+    int dn = 0;
+    for (int a = 0; a < M; ++a) {
+      t.nu_r[k][a] = d.nu_reac[k * M + a];
+      t.nu_p[k][a] = d.nu_prod[k * M + a];
+      dn += t.nu_p[k][a] - t.nu_r[k][a];
+    }
+    t.dnu[k] = dn;
+  }
+  t.ln_c0_const = std::log(d.p0 * 1e-6 / R_UNIV);
+  t.omega = d.omega;
+  t.omega1 = d.omega1;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_desc d{};
+  std::vector<double> molar_mass, nasa7, diff;
+  std::vector<int32_t> nu_r, nu_p;
+  std::vector<double> arrh;
+  std::vector<uint8_t> rev;
+  Geom g{};
+  Layout L{};
+  Buffers b{};
+  int cur = 0;
+  int device = 0;
+  std::string err;
+};
+
+namespace {
+
+lbm_status hip_fail(lbm_ctx *h, hipError_t e, const char *what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  if (h) h->err = msg; else g_last_error = msg;
+  return LBM_ERR_HIP;
+}
+
+lbm_status arg_fail(lbm_ctx *h, const char *msg) {
+  if (h) h->err = msg; else g_last_error = msg;
+  return LBM_ERR_ARG;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes) {
+  std::string err;
+  if (!bytes) return arg_fail(nullptr, "bytes is NULL");
+  if (!validate(desc, &err)) {
+    g_last_error = err;
+    return LBM_ERR_ARG;
+  }
+  const Geom g = make_geom(*desc);
+  *bytes = make_layout(*desc, g).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm_handle *out) {
+  std::string err;
+  if (!out) return arg_fail(nullptr, "out is NULL");
+  *out = nullptr;
+  if (!validate(desc, &err)) {
+    g_last_error = err;
+    return LBM_ERR_ARG;
+  }
+  if (!d_workspace) return arg_fail(nullptr, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % ALIGN != 0) {
+    g_last_error = "workspace must be 256-byte aligned";
+    return LBM_ERR_WORKSPACE;
+  }
+  lbm_ctx *h = new lbm_ctx();
+  const int M = desc->n_species, R = desc->n_reactions;
+  h->d = *desc;
+  h->molar_mass.assign(desc->molar_mass, desc->molar_mass + M);
+  h->nasa7.assign(desc->nasa7, desc->nasa7 + 7 * M);
+  h->diff.assign(desc->diff_ab, desc->diff_ab + M * M);
+  if (R > 0) {
+    h->nu_r.assign(desc->nu_reac, desc->nu_reac + R * M);
+    h->nu_p.assign(desc->nu_prod, desc->nu_prod + R * M);
+    h->arrh.assign(desc->arrhenius, desc->arrhenius + 3 * R);
+    h->rev.assign(desc->reversible, desc->reversible + R);
+  }
+  h->d.molar_mass = h->molar_mass.data();
+  h->d.nasa7 = h->nasa7.data();
+  h->d.diff_ab = h->diff.data();
+  h->d.nu_reac = R ? h->nu_r.data() : nullptr;
+  h->d.nu_prod = R ? h->nu_p.data() : nullptr;
+  h->d.arrhenius = R ? h->arrh.data() : nullptr;
+  h->d.reversible = R ? h->rev.data() : nullptr;
+  h->g = make_geom(h->d);
+  h->L = make_layout(h->d, h->g);
+  if (bytes < h->L.total) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "workspace has %zu bytes, %zu needed", bytes, h->L.total);
+    g_last_error = buf;
+    delete h;
+    return LBM_ERR_WORKSPACE;
+  }
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    lbm_status s = hip_fail(nullptr, e, "hipGetDevice");
+    delete h;
+    return s;
+  }
+  char *ws = static_cast<char *>(d_workspace);
+  const Layout &L = h->L;
+  Buffers &b = h->b;
+  b.status = reinterpret_cast<uint32_t *>(ws + L.status);
+  b.tab = reinterpret_cast<const Tables *>(ws + L.tables);
+  b.pop[0] = ws + L.pop0;
+  b.pop[1] = ws + L.pop1;
+  b.T = reinterpret_cast<double *>(ws + L.T);
+  b.side_Y = ws + L.side_Y;
+  b.side_w = ws + L.side_w;
+  b.side_phi = ws + L.side_phi;
+  b.side_rho = ws + L.side_rho;
+  b.side_u = ws + L.side_u;
+  b.psi = ws + L.psi;
+  b.corr = ws + L.corr;
+  Tables t;
+  build_tables(h->d, t);
+  e = hipMemcpy(ws + L.tables, &t, sizeof(Tables), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    uint32_t zero[16] = {0};
+    e = hipMemcpy(ws + L.status, zero, sizeof(zero), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    lbm_status s = hip_fail(nullptr, e, "uploading tables");
+    delete h;
+    return s;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_handle h) {
+  delete h;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_handle h, const double *d_rho, const double *d_u, const double *d_T,
+                           const double *d_Y, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!d_rho || !d_u || !d_T || !d_Y) return arg_fail(h, "init fields must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  h->cur = 0;
+  hipError_t e = launch_zero(h->b.corr, (int64_t)(h->L.corr_bytes / 4), st);
+  if (e == hipSuccess) e = launch_zero(h->b.status, 16, st);
+  if (e == hipSuccess) e = launch_init(h->g, h->b, h->d.storage, d_rho, d_u, d_T, d_Y, h->cur, st);
+  if (e != hipSuccess) return hip_fail(h, e, "init");
+  return LBM_OK;
+}
+
+static lbm_status run_steps(lbm_handle h, int32_t n_steps, hipStream_t st, float *ms) {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (ms) {
+    for (int k = 0; k < LBM_NUM_KERNELS; ++k) ms[k] = 0.f;
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+      return hip_fail(h, hipErrorOutOfMemory, "hipEventCreate");
+  }
+  auto timed = [&](int which, auto &&launch) -> hipError_t {
+    if (!ms) return launch();
+    hipError_t e = hipEventRecord(ev[0], st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev[1], st);
+    if (e != hipSuccess) return e;
+    e = hipEventSynchronize(ev[1]);
+    if (e != hipSuccess) return e;
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, ev[0], ev[1]);
+    ms[which] += t;
+    return e;
+  };
+  const int store = h->d.storage;
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+    const int cur = h->cur;
+    e = timed(0, [&] { return launch_main(h->g, h->b, store, cur, st); });
+    if (e == hipSuccess) e = timed(3, [&] { return launch_ghost(h->g, h->b, store, cur, st); });
+    if (e == hipSuccess) e = timed(1, [&] { return launch_psi(h->g, h->b, store, st); });
+    if (e == hipSuccess) e = timed(2, [&] { return launch_corr(h->g, h->b, store, st); });
+    if (e == hipSuccess) h->cur ^= 1;
+  }
+  if (ms) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "step");
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle h, int32_t n_steps, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (n_steps < 0) return arg_fail(h, "n_steps must be >= 0");
+  return run_steps(h, n_steps, static_cast<hipStream_t>(stream), nullptr);
+}
+
+lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms_out) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (n_steps < 0) return arg_fail(h, "n_steps must be >= 0");
+  if (!ms_out) return arg_fail(h, "ms_out is NULL");
+  return run_steps(h, n_steps, static_cast<hipStream_t>(stream), ms_out);
+}
+
+lbm_status lbm_macros(lbm_handle h, double *d_rho, double *d_u, double *d_T, double *d_P, double *d_Y,
+                      void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  hipError_t e = launch_macros(h->g, h->b, h->d.storage, h->cur, d_rho, d_u, d_T, d_P, d_Y,
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "macros");
+  return LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_handle h, const int64_t *d_nodes, int64_t n_nodes, double *d_out,
+                           double *d_T_out, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (n_nodes < 0) return arg_fail(h, "n_nodes must be >= 0");
+  if (n_nodes > 0 && (!d_nodes || !d_out)) return arg_fail(h, "node list and output must not be NULL");
+  hipError_t e = launch_export(h->g, h->b, h->d.storage, h->cur, d_nodes, n_nodes, d_out, d_T_out,
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "populations");
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_handle h, const void *, void *, double *, void *) {
+  if (h) h->err = "the discrete adjoint step is not provided by this build";
+  else g_last_error = "the discrete adjoint step is not provided by this build";
+  return LBM_ERR_UNSUPPORTED;
+}
+
+lbm_status lbm_status_sync(lbm_handle h, void *stream, uint32_t *anomaly_bits) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t bits = 0;
+  hipError_t e = hipMemcpyAsync(&bits, h->b.status, sizeof(bits), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = launch_zero(h->b.status, 1, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(h, e, "status");
+  if (anomaly_bits) *anomaly_bits = bits;
+  if (bits) {
+    h->err = "device anomaly bits set";
+    return LBM_ERR_DEVICE_ANOMALY;
+  }
+  return LBM_OK;
+}
+
+const char *lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

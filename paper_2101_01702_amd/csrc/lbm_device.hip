@@ -1,0 +1,931 @@
+// HIP kernels (gfx950) of the reactive-mixture lattice Boltzmann step.
+//
+// Model: Sawant, Dorschner & Karlin, "Reactive mixtures with the lattice Boltzmann
+// model" -- species LBE (Sec. 2, eqs. finalNumericalEquations, fStar, tauab,
+// transform1, feq, fstar, fsource), mixture f and energy g (Sec. 3, eqs. f, g, Xalpha,
+// Ai, gieq, giqeq, geq1mom, geq2mom, gstareq1mom, qdiff, corrFourier, temperature,
+// strongest), coupling loop (Sec. 4), equilibrium ghosts at open ends (Sec. 5.1).
+//
+// Data layout: populations SoA [set][i][z][y][x] with a one-cell ghost layer on open
+// axes, two ping-pong buffers, pull streaming.  One thread per node.
+//
+// The non-local terms of the collision (isotropy correction A_i.X of eq. f and the
+// Fourier correction flux q^corr of eq. corrFourier) depend on neighbour macros of
+// the same time level.  They enter the post-collision populations additively, so the
+// main kernel stores the post-collision populations without them, the stencil
+// kernels compute them from a small side channel, and the next pull adds them back
+// to each population as it is read (deferred correction).  One step therefore moves
+// each population through HBM once in and once out.
+#include <utility>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+__host__ __device__ constexpr int cx_of(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy_of(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz_of(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double wgt(int i) { return w1(cx_of(i)) * w1(cy_of(i)) * w1(cz_of(i)); }
+__host__ __device__ constexpr int c2_of(int i) {
+  return cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_of(i) * cz_of(i);
+}
+
+// product-form factor Psi_c(xi, zeta) (eq. phis), with s = xi^2 + zeta precomputed
+template <typename R>
+__device__ __forceinline__ R psi_c(int c, R xi, R s) {
+  return c == 0 ? R(1) - s : (c > 0 ? R(0.5) * (xi + s) : R(0.5) * (s - xi));
+}
+
+// Source coordinates of the pull along c for one axis: periodic wrap or ghost.
+struct Src {
+  int64_t ps;   // padded storage index of the source
+  int64_t ns;   // interior node index of the source, -1 when it is a ghost cell
+};
+
+struct AxisSrc {
+  int s[3];     // source coordinate for c = -1, 0, +1 (x - c)
+  bool out[3];
+};
+
+__device__ __forceinline__ AxisSrc axis_src(int x, int n, bool periodic) {
+  AxisSrc a;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int c = k - 1;
+    int s = x - c;
+    if (periodic) s = s < 0 ? s + n : (s >= n ? s - n : s);
+    a.s[k] = s;
+    a.out[k] = (s < 0) || (s >= n);
+  }
+  return a;
+}
+
+__device__ __forceinline__ Src make_src(const Geom &g, const AxisSrc &ax, const AxisSrc &ay,
+                                        const AxisSrc &az, int kx, int ky, int kz) {
+  Src r;
+  const int64_t sx = ax.s[kx], sy = ay.s[ky], sz = az.s[kz];
+  r.ps = ((sz + g.pz) * g.NY + (sy + g.py)) * g.NX + (sx + g.px);
+  const bool out = ax.out[kx] || ay.out[ky] || az.out[kz];
+  r.ns = out ? -1 : (sz * g.ny + sy) * g.nx + sx;
+  return r;
+}
+
+// neighbour for the isotropic gradient: periodic wrap or clamp at open faces
+__device__ __forceinline__ int nb_coord(int x, int c, int n, bool periodic) {
+  int s = x + c;
+  if (periodic) return s < 0 ? s + n : (s >= n ? s - n : s);
+  return s < 0 ? 0 : (s >= n ? n - 1 : s);
+}
+
+template <typename RT>
+struct Corr {
+  const RT *X;    // [3][N]
+  const RT *Cg;   // [3][N]
+  int64_t N;
+};
+
+// pulled value of the mixture f along c = (CX, cy, cz) with the deferred A_i.X term
+template <int CX, typename ST, typename RT>
+__device__ __forceinline__ RT pull_f(const ST *__restrict__ base, const Src &r, const Corr<RT> &cr, int cy,
+                                     int cz) {
+  RT v = RT(base[r.ps]);
+  if (r.ns >= 0) {
+    if constexpr (CX != 0) {
+      if (cy == 0 && cz == 0) v += RT(0.5 * CX) * cr.X[r.ns];
+    } else {
+      if (cy != 0 && cz == 0) v += RT(0.5) * RT(cy) * cr.X[cr.N + r.ns];
+      if (cy == 0 && cz != 0) v += RT(0.5) * RT(cz) * cr.X[2 * cr.N + r.ns];
+    }
+  }
+  return v;
+}
+
+// pulled value of g with the deferred Fourier-correction flux 3 w_i c_i . Cg
+template <int CX, typename ST, typename RT>
+__device__ __forceinline__ RT pull_g(const ST *__restrict__ base, const Src &r, const Corr<RT> &cr, int cy,
+                                     int cz, RT w3) {
+  RT v = RT(base[r.ps]);
+  if (r.ns >= 0) {
+    RT d = RT(0);
+    if constexpr (CX != 0) d += RT(CX) * cr.Cg[r.ns];
+    if (cy != 0) d += RT(cy) * cr.Cg[cr.N + r.ns];
+    if (cz != 0) d += RT(cz) * cr.Cg[2 * cr.N + r.ns];
+    v += w3 * d;
+  }
+  return v;
+}
+
+template <int... Is, typename F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, Is...>, F &&f) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// ---- thermodynamics (eqs. specHa, Umix; NASA-7) -------------------------------------
+__device__ __forceinline__ double h_RT(const double *a, double T, double invT) {
+  return a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * (a[4] * 0.2)))) +
+         a[5] * invT;
+}
+__device__ __forceinline__ double s_R(const double *a, double T, double lnT) {
+  return a[0] * lnT + T * (a[1] + T * (a[2] * 0.5 + T * (a[3] * (1.0 / 3.0) + T * (a[4] * 0.25)))) +
+         a[6];
+}
+
+// ---- moments of the pulled state (shared by step and macros) -----------------------
+template <int M>
+struct Macro {
+  double rho, u[3], rhoE;
+  double P6[6], q[3];            // pressure tensor (xx yy zz xy xz yz), energy flux
+  double rs[M];                  // species densities, last one slaved (eq. strongest)
+  double du0[M][3];              // u_a - u (right-hand side of eq. transform1)
+};
+
+template <int M, typename ST, typename RT>
+__device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict__ pop, const Corr<RT> &cr,
+                                             const AxisSrc &ax, const AxisSrc &ay, const AxisSrc &az,
+                                             Macro<M> &m) {
+  const int64_t NPAD = g.NPAD;
+  double rho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+  double rE = 0, qx = 0, qy = 0, qz = 0;
+  double ra[M - 1], jax[M - 1], jay[M - 1], jaz[M - 1];
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) ra[a] = jax[a] = jay[a] = jaz[a] = 0.0;
+#pragma unroll 1
+  for (int kyz = 0; kyz < 9; ++kyz) {
+    const int ky = kyz % 3, kz = kyz / 3;
+    const int cy = ky - 1, cz = kz - 1;
+    const RT wyz3 = RT(3.0 * w1(cy) * w1(cz));
+    static_for<3>([&](auto Kx) {
+      constexpr int kx = decltype(Kx)::value;
+      constexpr int cx = kx - 1;
+      const int i = kx + 3 * kyz;
+      const Src r = make_src(g, ax, ay, az, kx, ky, kz);
+      const double f = (double)pull_f<cx, ST, RT>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
+      const double gg =
+          (double)pull_g<cx, ST, RT>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, RT(w1(cx)) * wyz3);
+      rho += f;
+      rE += gg;
+      if constexpr (cx != 0) {
+        jx += cx * f; qx += cx * gg; pxx += f;
+        pxy += (cx * cy) * f; pxz += (cx * cz) * f;
+      }
+      jy += cy * f; qy += cy * gg; pyy += (cy * cy) * f;
+      jz += cz * f; qz += cz * gg; pzz += (cz * cz) * f;
+      pyz += (cy * cz) * f;
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) {
+        const double fa = (double)pop[((int64_t)a * Q + i) * NPAD + r.ps];
+        ra[a] += fa;
+        if constexpr (cx != 0) jax[a] += cx * fa;
+        jay[a] += cy * fa;
+        jaz[a] += cz * fa;
+      }
+    });
+  }
+  m.rho = rho;
+  m.rhoE = rE;
+  m.P6[0] = pxx; m.P6[1] = pyy; m.P6[2] = pzz; m.P6[3] = pxy; m.P6[4] = pxz; m.P6[5] = pyz;
+  m.q[0] = qx; m.q[1] = qy; m.q[2] = qz;
+  const double inv_rho = 1.0 / rho;
+  m.u[0] = jx * inv_rho; m.u[1] = jy * inv_rho; m.u[2] = jz * inv_rho;
+  double rsum = 0, jsx = 0, jsy = 0, jsz = 0;
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    m.rs[a] = ra[a];
+    rsum += ra[a]; jsx += jax[a]; jsy += jay[a]; jsz += jaz[a];
+    const bool tiny = fabs(ra[a]) < 1e-300;
+    const double inv = tiny ? 0.0 : 1.0 / ra[a];
+    m.du0[a][0] = tiny ? 0.0 : jax[a] * inv - m.u[0];
+    m.du0[a][1] = tiny ? 0.0 : jay[a] * inv - m.u[1];
+    m.du0[a][2] = tiny ? 0.0 : jaz[a] * inv - m.u[2];
+  }
+  {
+    const double rM = rho - rsum;
+    const double jM[3] = {jx - jsx, jy - jsy, jz - jsz};
+    m.rs[M - 1] = rM;
+    const bool tiny = fabs(rM) < 1e-300;
+    const double inv = tiny ? 0.0 : 1.0 / rM;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) m.du0[M - 1][d] = tiny ? 0.0 : jM[d] * inv - m.u[d];
+  }
+}
+
+// temperature from E - u^2/2 (eq. temperature) by Newton from T0; returns 1 when converged
+template <int M>
+__device__ __forceinline__ int node_temperature(const Tables &tb, const Macro<M> &m, double T0, double &T_out) {
+  double ec[6], dc[5];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ec[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) dc[k] = 0.0;
+  const double inv_rho = 1.0 / m.rho;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double Y = m.rs[a] * inv_rho;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ec[k] += Y * tb.ucoef[a][k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) dc[k] += Y * tb.cvcoef[a][k];
+  }
+  const double usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  const double target = m.rhoE * inv_rho - 0.5 * usq;
+  double T = T0;
+  int ok = 0;
+  for (int it = 0; it < 50; ++it) {
+    const double e = ec[0] + T * (ec[1] + T * (ec[2] + T * (ec[3] + T * (ec[4] + T * ec[5])))) - target;
+    const double de = dc[0] + T * (dc[1] + T * (dc[2] + T * (dc[3] + T * dc[4])));
+    const double dT = -e / de;
+    T += dT;
+    if (fabs(dT) <= 1e-12 * fabs(T)) {
+      ok = 1;
+      break;
+    }
+  }
+  T_out = T;
+  return ok;
+}
+
+template <typename RT>
+__device__ __forceinline__ void store_rt(void *base, int64_t idx, RT v) {
+  static_cast<RT *>(base)[idx] = v;
+}
+
+// ---- the step --------------------------------------------------------------------
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(256) void k_main(Geom g, Buffers b, int cur) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const Tables &tb = *b.tab;
+  const int x = (int)(n % g.nx);
+  const int y = (int)((n / g.nx) % g.ny);
+  const int z = (int)(n / ((int64_t)g.nx * g.ny));
+  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
+  ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
+  const int64_t N = g.N, NPAD = g.NPAD;
+  const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
+  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
+  const AxisSrc az = axis_src(z, g.nz, g.per[2]);
+
+  // O1: moments of the pulled state
+  Macro<M> m;
+  node_moments<M, ST, RT>(g, src, cr, ax, ay, az, m);
+  uint32_t anom = 0;
+  if (!(m.rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
+  const double inv_rho = 1.0 / m.rho;
+
+  // O2: temperature and mixture gas constant
+  double T;
+  if (!node_temperature<M>(tb, m, b.T[n], T)) anom |= LBM_ANOM_NEWTON;
+  const double invT = 1.0 / T, lnT = log(T);
+  double zeta = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) zeta += m.rs[a] * inv_rho * tb.Ra[a];
+  zeta *= T;
+  const double P = m.rho * zeta;
+
+  // O3: production rates (mass action, K_c from the NASA-7 Gibbs function)
+  RT rdot[M - 1];
+  {
+    double c[M], wd[M], gib[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      c[a] = m.rs[a] * tb.conc_scale[a];
+      wd[a] = 0.0;
+      gib[a] = h_RT(tb.nasa[a], T, invT) - s_R(tb.nasa[a], T, lnT);
+    }
+    const double ln_c0 = tb.ln_c0_const - lnT;
+    for (int k = 0; k < tb.R; ++k) {
+      const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
+      double fwd = exp(lnkf);
+#pragma unroll
+      for (int a = 0; a < M; ++a)
+        for (int r = 0; r < tb.nu_r[k][a]; ++r) fwd *= c[a];
+      double rev = 0.0;
+      if (tb.rev[k]) {
+        double dG = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) dG += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * gib[a];
+        const double lnKc = -dG + tb.dnu[k] * ln_c0;
+        rev = exp(lnkf - lnKc);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+          for (int r = 0; r < tb.nu_p[k][a]; ++r) rev *= c[a];
+      }
+      const double qk = fwd - rev;
+#pragma unroll
+      for (int a = 0; a < M; ++a) wd[a] += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * qk;
+    }
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) rdot[a] = RT(tb.rdot_scale[a] * wd[a]);
+  }
+
+  // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1);
+  // m.du0 is overwritten with the solution du_a
+  const double inv_zeta = 1.0 / zeta;
+  RT beta[M - 1];
+  {
+    double A[M][M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const double za = tb.Ra[a] * T;
+      double it = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < M; ++bb) {
+        const double Yb = m.rs[bb] * inv_rho;
+        const double K = za * (tb.Ra[bb] * T) * tb.invD[a][bb] * inv_zeta;
+        it += Yb * K;
+        A[a][bb] = -0.5 * K * Yb;
+      }
+      A[a][a] = 1.0 + 0.5 * it;
+      if (a < M - 1) beta[a] = RT(it / (it + 2.0));
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const double piv = 1.0 / A[k][k];
+#pragma unroll
+      for (int r = k + 1; r < M; ++r) {
+        const double l = A[r][k] * piv;
+#pragma unroll
+        for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) m.du0[r][d] -= l * m.du0[k][d];
+      }
+    }
+#pragma unroll
+    for (int r = M - 1; r >= 0; --r) {
+      const double inv = 1.0 / A[r][r];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double v = m.du0[r][d];
+#pragma unroll
+        for (int c = r + 1; c < M; ++c) v -= A[r][c] * m.du0[c][d];
+        m.du0[r][d] = v * inv;
+      }
+    }
+  }
+
+  // O5: side channel for the non-local terms and the ghosts, stored temperature;
+  // energy-flux vector V of the g collision
+  double Hmix = 0.0, hyd[3] = {0.0, 0.0, 0.0};
+  {
+    const double wc = 0.5 * (2.0 - tb.omega1) * P;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const double Ya = m.rs[a] * inv_rho;
+      const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
+      Hmix += Ya * Ha;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) hyd[d] += Ha * Ya * m.du0[a][d];
+      store_rt<RT>(b.side_Y, a * N + n, RT(Ya));
+      store_rt<RT>(b.side_w, a * N + n, RT(wc * Ha));
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = m.u[d];
+      store_rt<RT>(b.side_phi, d * N + n, RT(m.rho * u * (1.0 - 3.0 * zeta) - m.rho * u * u * u));
+    }
+    if (tb.open_any) {
+      store_rt<RT>(b.side_rho, n, RT(m.rho));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) store_rt<RT>(b.side_u, d * N + n, RT(m.u[d]));
+    }
+    b.T[n] = T;
+    if (!isfinite(T) || !isfinite(m.rho) || !isfinite(m.rhoE)) anom |= LBM_ANOM_NONFINITE;
+    if (anom) atomicOr(b.status, anom);
+  }
+
+  // O7: collision coefficients in the compute precision
+  const RT om = RT(tb.omega);
+  const RT u0 = RT(m.u[0]), u1 = RT(m.u[1]), u2 = RT(m.u[2]);
+  const RT zr = RT(zeta), rr = RT(m.rho);
+  // energy g (eq. g, folded): g' = (1-omega) g + w_i [A0 + A1.c + A2 : c c] where the
+  // Grad equilibrium (eqs. gieq, geq1mom, geq2mom) and the quasi-equilibrium flux
+  // (eqs. gstareq1mom, qdiff) enter through
+  // V = (omega-omega1)(q - u.(P - P^eq) - q^eq) + omega1 rho sum_a H_a Y_a du_a
+  RT gA0, gA1[3], gA2[6];
+  {
+    const double usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+    const double h2 = Hmix + 0.5 * usq;
+    const double *u = m.u;
+    double qeq[3], Peq[6], Req[6];
+    for (int d = 0; d < 3; ++d) qeq[d] = h2 * m.rho * u[d];
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      Peq[k] = (k < 3 ? m.rho * zeta : 0.0) + m.rho * u[ia[k]] * u[ib[k]];
+      Req[k] = h2 * Peq[k] + P * u[ia[k]] * u[ib[k]];
+    }
+    const double om_d = tb.omega, om1 = tb.omega1;
+    const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    double V[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double uP = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uP += u[c] * (m.P6[sym[c][d]] - Peq[sym[c][d]]);
+      V[d] = (om_d - om1) * (m.q[d] - uP - qeq[d]) + om1 * m.rho * hyd[d];
+    }
+    const double trR = Req[0] + Req[1] + Req[2];
+    gA0 = RT(om_d * (2.5 * m.rhoE - 1.5 * trR));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gA1[d] = RT(om_d * 3.0 * qeq[d] + 3.0 * V[d]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      gA2[k] = RT(om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal counted twice
+  }
+  // species a < M-1 (eq. finalNumericalEquations with F_ai of eq. fStar):
+  // f_ai' = (1 - 2 beta_a) f_ai + (2 beta_a rho_a + rho_dot_a) Phi_a(u)
+  //         + (beta_a - 1) (Y_a zeta_a / zeta) sum_b invD_ab rho_b zeta_b (Phi_b(u) - Phi_b(u + du_b))
+  // with Phi_b(v) the unit-density product form at zeta_b (eqs. feq, fstar, fsource)
+  RT zb[M], xs[M][3], tbw[M];
+  RT omb[M - 1], ca[M - 1], rcoef[M - 1];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double za = tb.Ra[a] * T;
+    zb[a] = RT(za);
+    tbw[a] = RT(m.rs[a] * za);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xs[a][d] = RT(m.u[d] + m.du0[a][d]);
+  }
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    const RT bt = beta[a];
+    omb[a] = RT(1) - RT(2) * bt;
+    ca[a] = RT(2) * bt * RT(m.rs[a]) + rdot[a];
+    rcoef[a] = (bt - RT(1)) * RT(m.rs[a] * inv_rho * tb.Ra[a] * T * inv_zeta);
+  }
+
+  // O7 + store: second pass over the pulled populations
+  const int64_t pself = ((int64_t)(z + g.pz) * g.NY + (y + g.py)) * g.NX + (x + g.px);
+  const RT s0 = u0 * u0 + zr;
+#pragma unroll 1
+  for (int kyz = 0; kyz < 9; ++kyz) {
+    const int ky = kyz % 3, kz = kyz / 3;
+    const int cy = ky - 1, cz = kz - 1;
+    const RT wyz = RT(w1(cy) * w1(cz));
+    const RT fcy = RT(cy), fcz = RT(cz);
+    // y and z factors of the product forms for this (cy, cz)
+    const RT fyz = rr * psi_c<RT>(cy, u1, u1 * u1 + zr) * psi_c<RT>(cz, u2, u2 * u2 + zr);
+    RT pe_yz[M], ps_yz[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      pe_yz[a] = psi_c<RT>(cy, u1, u1 * u1 + zb[a]) * psi_c<RT>(cz, u2, u2 * u2 + zb[a]);
+      ps_yz[a] = psi_c<RT>(cy, xs[a][1], xs[a][1] * xs[a][1] + zb[a]) *
+                 psi_c<RT>(cz, xs[a][2], xs[a][2] * xs[a][2] + zb[a]);
+    }
+    const RT gyz = gA0 + fcy * gA1[1] + fcz * gA1[2] + fcy * fcy * gA2[1] + fcz * fcz * gA2[2] +
+                   fcy * fcz * gA2[5];
+    static_for<3>([&](auto Kx) {
+      constexpr int kx = decltype(Kx)::value;
+      constexpr int cx = kx - 1;
+      const int i = kx + 3 * kyz;
+      const Src r = make_src(g, ax, ay, az, kx, ky, kz);
+      const RT wi = RT(w1(cx)) * wyz;
+      // mixture f (eq. f); A_i.X is added by the next pull
+      {
+        const RT f = pull_f<cx, ST, RT>(src + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
+        const RT feq = fyz * psi_c<RT>(cx, u0, s0);
+        dst[((int64_t)(M - 1) * Q + i) * NPAD + pself] = ST((RT(1) - om) * f + om * feq);
+      }
+      // energy g; the q^corr part is added by the next pull
+      {
+        const RT gv = pull_g<cx, ST, RT>(src + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, RT(3) * wi);
+        RT acc = gyz;
+        if constexpr (cx != 0) acc += RT(cx) * gA1[0] + gA2[0] + RT(cx) * (fcy * gA2[3] + fcz * gA2[4]);
+        dst[((int64_t)M * Q + i) * NPAD + pself] = ST((RT(1) - om) * gv + wi * acc);
+      }
+      // species
+      RT phe[M], dd[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const RT pe = pe_yz[a] * psi_c<RT>(cx, u0, u0 * u0 + zb[a]);
+        const RT ps = ps_yz[a] * psi_c<RT>(cx, xs[a][0], xs[a][0] * xs[a][0] + zb[a]);
+        phe[a] = pe;
+        dd[a] = tbw[a] * (pe - ps);
+      }
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) {
+        RT F = RT(0);
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) {
+          if (bb == a) continue;
+          if constexpr (sizeof(RT) == 4)
+            F += tb.invDf[a][bb] * dd[bb];
+          else
+            F += RT(tb.invD[a][bb]) * dd[bb];
+        }
+        const RT fa = RT(src[((int64_t)a * Q + i) * NPAD + r.ps]);
+        dst[((int64_t)a * Q + i) * NPAD + pself] = ST(omb[a] * fa + ca[a] * phe[a] + rcoef[a] * F);
+      }
+    });
+  }
+}
+
+// ---- psi_alpha = (1/omega - 1/2) d_alpha phi_alpha (isotropic gradient) ------------
+template <typename RT>
+__global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  const RT *phi = static_cast<const RT *>(b.side_phi);
+  const int64_t N = g.N;
+  const RT coef = RT(1.0 / b.tab->omega - 0.5);
+  int xs[3], ys[3], zs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xs[k] = nb_coord(x, k - 1, g.nx, g.per[0]);
+    ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
+    zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
+  }
+  RT acc[3] = {0, 0, 0};
+  static_for<27>([&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+    const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
+    constexpr RT w = RT(3.0 * wgt(I));
+    if constexpr (cx != 0) acc[0] += (cx * w) * phi[0 * N + nn];
+    if constexpr (cy != 0) acc[1] += (cy * w) * phi[1 * N + nn];
+    if constexpr (cz != 0) acc[2] += (cz * w) * phi[2 * N + nn];
+  });
+  RT *psi = static_cast<RT *>(b.psi);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) psi[d * N + n] = coef * acc[d];
+}
+
+// ---- X_alpha = -d_alpha psi_alpha; Cg = sum_a w_a grad Y_a ---------------------------
+template <int M, typename RT>
+__global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  const RT *psi = static_cast<const RT *>(b.psi);
+  const RT *Yf = static_cast<const RT *>(b.side_Y);
+  const RT *wf = static_cast<const RT *>(b.side_w);
+  const int64_t N = g.N;
+  int xs[3], ys[3], zs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    xs[k] = nb_coord(x, k - 1, g.nx, g.per[0]);
+    ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
+    zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
+  }
+  RT wa[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) wa[a] = wf[a * N + n];
+  RT X[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+  static_for<27>([&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+    if constexpr (I != 13) {
+      const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
+      constexpr RT w = RT(3.0 * wgt(I));
+      if constexpr (cx != 0) X[0] -= (cx * w) * psi[0 * N + nn];
+      if constexpr (cy != 0) X[1] -= (cy * w) * psi[1 * N + nn];
+      if constexpr (cz != 0) X[2] -= (cz * w) * psi[2 * N + nn];
+      RT hy = RT(0);
+#pragma unroll
+      for (int a = 0; a < M; ++a) hy += wa[a] * Yf[a * N + nn];
+      if constexpr (cx != 0) C[0] += (cx * w) * hy;
+      if constexpr (cy != 0) C[1] += (cy * w) * hy;
+      if constexpr (cz != 0) C[2] += (cz * w) * hy;
+    }
+  });
+  RT *corr = static_cast<RT *>(b.corr);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    corr[d * N + n] = X[d];
+    corr[(3 + d) * N + n] = C[d];
+  }
+}
+
+// ---- equilibria of one state (init and ghosts) --------------------------------------
+template <int M, typename ST>
+__device__ __forceinline__ void write_equilibria(const Tables &tb, ST *__restrict__ dst, int64_t NPAD,
+                                                 const int64_t (&pidx)[27], double rho, const double *u,
+                                                 double T, const double *Y) {
+  double zeta_a[M], zeta = 0.0, H = 0.0, U = 0.0;
+  const double invT = 1.0 / T;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    zeta_a[a] = tb.Ra[a] * T;
+    zeta += Y[a] * zeta_a[a];
+    const double h = h_RT(tb.nasa[a], T, invT);
+    H += Y[a] * zeta_a[a] * h;
+    U += Y[a] * zeta_a[a] * (h - 1.0);
+  }
+  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double rhoE = rho * (U + 0.5 * usq);
+  const double h2 = H + 0.5 * usq, P = rho * zeta;
+  double qeq[3], Req[6];
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  for (int d = 0; d < 3; ++d) qeq[d] = h2 * rho * u[d];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double Peq = (k < 3 ? rho * zeta : 0.0) + rho * u[ia[k]] * u[ib[k]];
+    Req[k] = h2 * Peq + P * u[ia[k]] * u[ib[k]];
+  }
+  const double trR = Req[0] + Req[1] + Req[2];
+  const double A0 = 2.5 * rhoE - 1.5 * trR;
+  double su[3];
+  for (int d = 0; d < 3; ++d) su[d] = u[d] * u[d];
+  static_for<27>([&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+    const int64_t p = pidx[I];
+    if (p < 0) return;
+    const double fe = rho * psi_c<double>(cx, u[0], su[0] + zeta) * psi_c<double>(cy, u[1], su[1] + zeta) *
+                      psi_c<double>(cz, u[2], su[2] + zeta);
+    dst[(int64_t)((M - 1) * Q + I) * NPAD + p] = ST(fe);
+    double acc = A0 + 3.0 * (cx * qeq[0] + cy * qeq[1] + cz * qeq[2]);
+    acc += cx * cx * (4.5 * Req[0] - 1.5 * rhoE) + cy * cy * (4.5 * Req[1] - 1.5 * rhoE) +
+           cz * cz * (4.5 * Req[2] - 1.5 * rhoE);
+    acc += 9.0 * (cx * cy * Req[3] + cx * cz * Req[4] + cy * cz * Req[5]);
+    dst[(int64_t)(M * Q + I) * NPAD + p] = ST(wgt(I) * acc);
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) {
+      const double z = zeta_a[a];
+      const double fa = rho * Y[a] * psi_c<double>(cx, u[0], su[0] + z) * psi_c<double>(cy, u[1], su[1] + z) *
+                        psi_c<double>(cz, u[2], su[2] + z);
+      dst[(int64_t)(a * Q + I) * NPAD + p] = ST(fa);
+    }
+  });
+}
+
+// initial state: equilibria pushed to where the first pull reads them
+template <int M, typename ST>
+__global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, const double *rho, const double *u,
+                                              const double *T, const double *Y, int cur) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
+  const AxisSrc az = axis_src(z, g.nz, g.per[2]);
+  int64_t pidx[27];
+  static_for<27>([&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    pidx[I] = make_src(g, ax, ay, az, cx_of(I) + 1, cy_of(I) + 1, cz_of(I) + 1).ps;
+  });
+  const int64_t N = g.N;
+  double uu[3] = {u[n], u[N + n], u[2 * N + n]};
+  double Yl[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) Yl[a] = Y[a * N + n];
+  write_equilibria<M, ST>(*b.tab, static_cast<ST *>(b.pop[cur]), g.NPAD, pidx, rho[n], uu, T[n], Yl);
+  b.T[n] = T[n];
+}
+
+// ghost layer of open faces: equilibria at the adjacent boundary node (Sec. 5.1)
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, int cur, int64_t nx_slab, int64_t ny_slab,
+                                               int64_t nz_slab) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int gx, gy, gz;
+  if (t < nx_slab) {          // x = -1 or nx, all padded y, z
+    const int64_t per = (int64_t)g.NY * g.NZ;
+    gx = (t < per) ? -1 : g.nx;
+    const int64_t r = t % per;
+    gy = (int)(r % g.NY) - g.py;
+    gz = (int)(r / g.NY) - g.pz;
+  } else if ((t -= nx_slab) < ny_slab) {   // y = -1 or ny, interior x, padded z
+    const int64_t per = (int64_t)g.nx * g.NZ;
+    gy = (t < per) ? -1 : g.ny;
+    const int64_t r = t % per;
+    gx = (int)(r % g.nx);
+    gz = (int)(r / g.nx) - g.pz;
+  } else if ((t -= ny_slab) < nz_slab) {   // z = -1 or nz, interior x, y
+    const int64_t per = (int64_t)g.nx * g.ny;
+    gz = (t < per) ? -1 : g.nz;
+    const int64_t r = t % per;
+    gx = (int)(r % g.nx);
+    gy = (int)(r / g.nx);
+  } else {
+    return;
+  }
+  bool zero_u = false;
+  const int gc[3] = {gx, gy, gz};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  int a3[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int v = gc[d];
+    if (v < 0) {
+      zero_u |= (g.bc[2 * d] == LBM_BC_OPEN_EQ_U0);
+      v = 0;
+    } else if (v >= nn[d]) {
+      zero_u |= (g.bc[2 * d + 1] == LBM_BC_OPEN_EQ_U0);
+      v = nn[d] - 1;
+    }
+    a3[d] = v;
+  }
+  const int64_t N = g.N;
+  const int64_t na = ((int64_t)a3[2] * g.ny + a3[1]) * g.nx + a3[0];
+  const RT *srho = static_cast<const RT *>(b.side_rho);
+  const RT *su = static_cast<const RT *>(b.side_u);
+  const RT *sY = static_cast<const RT *>(b.side_Y);
+  double u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) u[d] = zero_u ? 0.0 : double(su[d * N + na]);
+  double Y[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
+  const int64_t p = ((int64_t)(gz + g.pz) * g.NY + (gy + g.py)) * g.NX + (gx + g.px);
+  int64_t pidx[27];
+#pragma unroll
+  for (int i = 0; i < 27; ++i) pidx[i] = p;
+  write_equilibria<M, ST>(*b.tab, static_cast<ST *>(b.pop[cur ^ 1]), g.NPAD, pidx, double(srho[na]), u,
+                          b.T[na], Y);
+}
+
+// macroscopic fields of the current state (no state change)
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, int cur, double *rho, double *u, double *T,
+                                                double *P, double *Y) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  const int64_t N = g.N;
+  const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
+  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
+  const AxisSrc az = axis_src(z, g.nz, g.per[2]);
+  Macro<M> m;
+  node_moments<M, ST, RT>(g, static_cast<const ST *>(b.pop[cur]), cr, ax, ay, az, m);
+  const Tables &tb = *b.tab;
+  double Tn;
+  node_temperature<M>(tb, m, b.T[n], Tn);
+  const double inv_rho = 1.0 / m.rho;
+  if (rho) rho[n] = m.rho;
+  if (u)
+    for (int d = 0; d < 3; ++d) u[d * N + n] = m.u[d];
+  if (T) T[n] = Tn;
+  if (P) {
+    double zeta = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) zeta += m.rs[a] * inv_rho * tb.Ra[a];
+    P[n] = m.rho * zeta * Tn;
+  }
+  if (Y)
+#pragma unroll
+    for (int a = 0; a < M; ++a) Y[a * N + n] = m.rs[a] * inv_rho;
+}
+
+// pre-collision populations at listed nodes
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, const int64_t *nodes, int64_t nn,
+                                                double *out, double *T_out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nn) return;
+  const int64_t n = nodes[k];
+  if (n < 0 || n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  const int64_t N = g.N, NPAD = g.NPAD;
+  const ST *pop = static_cast<const ST *>(b.pop[cur]);
+  const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
+  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
+  const AxisSrc az = axis_src(z, g.nz, g.per[2]);
+  for (int kyz = 0; kyz < 9; ++kyz) {
+    const int ky = kyz % 3, kz = kyz / 3;
+    const int cy = ky - 1, cz = kz - 1;
+    static_for<3>([&](auto Kx) {
+      constexpr int kx = decltype(Kx)::value;
+      constexpr int cx = kx - 1;
+      const int i = kx + 3 * kyz;
+      const Src r = make_src(g, ax, ay, az, kx, ky, kz);
+      const RT w3 = RT(3.0 * w1(cx) * w1(cy) * w1(cz));
+      out[((int64_t)(M - 1) * Q + i) * nn + k] =
+          (double)pull_f<cx, ST, RT>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
+      out[((int64_t)M * Q + i) * nn + k] =
+          (double)pull_g<cx, ST, RT>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w3);
+      for (int a = 0; a < M - 1; ++a)
+        out[((int64_t)a * Q + i) * nn + k] = (double)pop[((int64_t)a * Q + i) * NPAD + r.ps];
+    });
+  }
+  if (T_out) T_out[k] = b.T[n];
+}
+
+__global__ void k_zero(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// dispatch on (species count, storage)
+template <template <int, typename, typename> class K, typename... Args>
+hipError_t dispatch(int M, int store, Args &&...args) {
+#define LBM_CASE(MM)                                                              \
+  case MM:                                                                        \
+    return store == LBM_STORE_F64 ? K<MM, double, double>::run(args...)           \
+                                  : K<MM, float, double>::run(args...);
+  switch (M) {
+    LBM_CASE(2) LBM_CASE(3) LBM_CASE(4) LBM_CASE(5) LBM_CASE(6) LBM_CASE(7) LBM_CASE(8) LBM_CASE(9)
+    LBM_CASE(10)
+    default: return hipErrorInvalidValue;
+  }
+#undef LBM_CASE
+}
+
+template <int M, typename ST, typename RT>
+struct RunMain {
+  static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
+    hipLaunchKernelGGL((k_main<M, ST, RT>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b, cur);
+    return hipGetLastError();
+  }
+};
+template <int M, typename ST, typename RT>
+struct RunCorr {
+  static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
+    hipLaunchKernelGGL((k_corr<M, RT>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    return hipGetLastError();
+  }
+};
+template <int M, typename ST, typename RT>
+struct RunInit {
+  static hipError_t run(const Geom &g, const Buffers &b, const double *rho, const double *u, const double *T,
+                        const double *Y, int cur, hipStream_t st) {
+    hipLaunchKernelGGL((k_init<M, ST>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, rho, u, T, Y, cur);
+    return hipGetLastError();
+  }
+};
+template <int M, typename ST, typename RT>
+struct RunGhost {
+  static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
+    const int64_t sx = g.px ? 2LL * g.NY * g.NZ : 0;
+    const int64_t sy = g.py ? 2LL * g.nx * g.NZ : 0;
+    const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
+    const int64_t tot = sx + sy + sz;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ghost<M, ST, RT>), dim3(blocks_for(tot, 128)), dim3(128), 0, st, g, b, cur, sx, sy, sz);
+    return hipGetLastError();
+  }
+};
+template <int M, typename ST, typename RT>
+struct RunMacros {
+  static hipError_t run(const Geom &g, const Buffers &b, int cur, double *rho, double *u, double *T, double *P,
+                        double *Y, hipStream_t st) {
+    hipLaunchKernelGGL((k_macros<M, ST, RT>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, cur, rho, u, T, P, Y);
+    return hipGetLastError();
+  }
+};
+template <int M, typename ST, typename RT>
+struct RunExport {
+  static hipError_t run(const Geom &g, const Buffers &b, int cur, const int64_t *nodes, int64_t nn, double *out,
+                        double *T_out, hipStream_t st) {
+    if (nn == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_export<M, ST, RT>), dim3(blocks_for(nn, 128)), dim3(128), 0, st, g, b, cur, nodes, nn, out, T_out);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t launch_main(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
+  return dispatch<RunMain>(g.M, store, g, b, cur, st);
+}
+
+hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {
+  (void)store;
+  hipLaunchKernelGGL((k_psi<double>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st) {
+  return dispatch<RunCorr>(g.M, store, g, b, st);
+}
+
+hipError_t launch_init(const Geom &g, const Buffers &b, int store, const double *rho, const double *u,
+                       const double *T, const double *Y, int cur, hipStream_t st) {
+  return dispatch<RunInit>(g.M, store, g, b, rho, u, T, Y, cur, st);
+}
+
+hipError_t launch_ghost(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
+  return dispatch<RunGhost>(g.M, store, g, b, cur, st);
+}
+
+hipError_t launch_macros(const Geom &g, const Buffers &b, int store, int cur, double *rho, double *u,
+                         double *T, double *P, double *Y, hipStream_t st) {
+  return dispatch<RunMacros>(g.M, store, g, b, cur, rho, u, T, P, Y, st);
+}
+
+hipError_t launch_export(const Geom &g, const Buffers &b, int store, int cur, const int64_t *nodes,
+                         int64_t n_nodes, double *out, double *T_out, hipStream_t st) {
+  return dispatch<RunExport>(g.M, store, g, b, cur, nodes, n_nodes, out, T_out, st);
+}
+
+hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st) {
+  if (n_words32 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(blocks_for(n_words32, 256)), dim3(256), 0, st, static_cast<uint32_t *>(p),
+                     n_words32);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,74 @@
+// Internal layout shared by the kernels and the host side of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm.h"
+
+namespace lbm {
+
+constexpr int Q = 27;
+constexpr int MAXM = LBM_MAX_SPECIES;
+constexpr int MAXR = LBM_MAX_REACTIONS;
+
+// Read-only constant tables, uploaded into the workspace at create time and read
+// with uniform loads by every kernel.
+struct Tables {
+  int32_t M, R, S, open_any;
+  double Ra[MAXM];            // lattice gas constant kappa R_U / m_a  (per K)
+  double nasa[MAXM][7];       // NASA-7 rows
+  double ucoef[MAXM][6];      // U_a(T) = sum_k ucoef[k] T^k (k=0: Ra a6; 1: Ra (a1-1); k>=2: Ra a_k/k)
+  double cvcoef[MAXM][5];     // C_v,a(T) = sum_k cvcoef[k] T^k
+  double invD[MAXM][MAXM];    // 1 / D_ab, zero on the diagonal
+  float invDf[MAXM][MAXM];
+  double conc_scale[MAXM];    // rho_ref / m_a: lattice density -> mol/cm^3
+  double rdot_scale[MAXM];    // m_a dt_phys / rho_ref: mol/(cm^3 s) -> lattice density/step
+  double lnA[MAXR], bexp[MAXR], Ta[MAXR], dnu[MAXR];
+  int32_t rev[MAXR];
+  int32_t nu_r[MAXR][MAXM];
+  int32_t nu_p[MAXR][MAXM];
+  double ln_c0_const;         // ln(p0 * 1e-6 / R_U): ln c0(T) = ln_c0_const - ln T (mol/cm^3)
+  double omega, omega1;
+};
+
+struct Geom {
+  int32_t M;                  // species
+  int32_t nx, ny, nz;
+  int32_t px, py, pz;         // ghost padding per axis (1 on open axes)
+  int32_t NX, NY, NZ;         // padded sizes
+  int32_t per[3];             // periodic axis flags
+  int32_t bc[6];
+  int64_t N, NPAD;
+};
+
+// Device pointers into the workspace.
+struct Buffers {
+  uint32_t *status;           // anomaly word
+  const Tables *tab;
+  void *pop[2];               // [S][27][NPAD] storage type
+  double *T;                  // [N] stored temperature
+  void *side_Y;               // [M][N] compute type: mass fractions
+  void *side_w;               // [M][N]: (2 - omega1)/2 * P * H_a
+  void *side_phi;             // [3][N]: argument of the isotropy correction
+  void *side_rho;             // [N]   density (ghost equilibria)
+  void *side_u;               // [3][N] velocity (ghost equilibria)
+  void *psi;                  // [3][N]
+  void *corr;                 // [6][N]: X (3), then the energy-flux correction (3)
+};
+
+// launchers (lbm_device.hip)
+hipError_t launch_init(const Geom &g, const Buffers &b, int store, const double *rho, const double *u,
+                       const double *T, const double *Y, int cur, hipStream_t st);
+hipError_t launch_main(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
+hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st);
+hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st);
+hipError_t launch_ghost(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
+hipError_t launch_macros(const Geom &g, const Buffers &b, int store, int cur, double *rho, double *u,
+                         double *T, double *P, double *Y, hipStream_t st);
+hipError_t launch_export(const Geom &g, const Buffers &b, int store, int cur, const int64_t *nodes,
+                         int64_t n_nodes, double *out, double *T_out, hipStream_t st);
+hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,243 @@
+"""Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Device memory (the workspace and the field buffers) and the stream come from
+PyTorch; every step of the method runs in the HIP library liblbm.so.  There is no
+fallback: if the library is missing or no HIP device is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK = 0
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP",
+                -4: "LBM_ERR_WORKSPACE", -5: "LBM_ERR_DEVICE_ANOMALY"}
+STORE_F64, STORE_F32 = 0, 1
+NUM_KERNELS = 4
+KERNEL_NAMES = ("main", "psi", "corr", "ghost")
+ANOM_NONFINITE, ANOM_NEWTON, ANOM_NEG_DENSITY = 1, 2, 4
+MAX_SPECIES = 10
+MAX_REACTIONS = 64
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_up = C.POINTER(C.c_uint8)
+
+
+class LbmDesc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("bc", C.c_int32 * 6),
+        ("n_species", C.c_int32), ("n_reactions", C.c_int32),
+        ("molar_mass", _dp), ("nasa7", _dp), ("diff_ab", _dp),
+        ("nu_reac", _ip), ("nu_prod", _ip), ("arrhenius", _dp), ("reversible", _up),
+        ("omega", C.c_double), ("omega1", C.c_double),
+        ("kappa", C.c_double), ("dt_phys", C.c_double), ("rho_ref", C.c_double), ("p0", C.c_double),
+        ("storage", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ("lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_step",
+           "lbm_step_timed", "lbm_macros", "lbm_populations", "lbm_adjoint_step", "lbm_status_sync",
+           "lbm_last_error")
+
+
+def load(path: Optional[str] = None):
+    """Load liblbm.so (built by ``python -m paper_2101_01702_amd.build``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -m paper_2101_01702_amd.build`")
+    lib = C.CDLL(p)
+    vp = C.c_void_p
+    lib.lbm_workspace_size.argtypes = [C.POINTER(LbmDesc), C.POINTER(C.c_size_t)]
+    lib.lbm_create.argtypes = [C.POINTER(LbmDesc), vp, C.c_size_t, C.POINTER(vp)]
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_init_fields.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.lbm_step.argtypes = [vp, C.c_int32, vp]
+    lib.lbm_step_timed.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_float)]
+    lib.lbm_macros.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.lbm_populations.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+    lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_status_sync.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
+    lib.lbm_last_error.argtypes = [vp]
+    lib.lbm_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name != "lbm_last_error":
+            getattr(lib, name).restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_desc(prob, storage: Optional[int] = None):
+    """lbm_desc of a workloads.Problem; returns (desc, arrays kept alive)."""
+    mech = prob.mech
+    keep = dict(molar_mass=_c64(mech.molar_mass), nasa7=_c64(mech.nasa7), diff=_c64(prob.diff),
+                nu_reac=np.ascontiguousarray(mech.nu_reac, np.int32).reshape(-1),
+                nu_prod=np.ascontiguousarray(mech.nu_prod, np.int32).reshape(-1),
+                arrhenius=_c64(mech.arrhenius).reshape(-1),
+                reversible=np.ascontiguousarray(mech.reversible, np.uint8))
+    d = LbmDesc()
+    d.nx, d.ny, d.nz = prob.nx, prob.ny, prob.nz
+    d.bc = (C.c_int32 * 6)(*prob.bc)
+    d.n_species, d.n_reactions = mech.M, mech.R
+    d.molar_mass = keep["molar_mass"].ctypes.data_as(_dp)
+    d.nasa7 = keep["nasa7"].ctypes.data_as(_dp)
+    d.diff_ab = keep["diff"].ctypes.data_as(_dp)
+    if mech.R:
+        d.nu_reac = keep["nu_reac"].ctypes.data_as(_ip)
+        d.nu_prod = keep["nu_prod"].ctypes.data_as(_ip)
+        d.arrhenius = keep["arrhenius"].ctypes.data_as(_dp)
+        d.reversible = keep["reversible"].ctypes.data_as(_up)
+    d.omega, d.omega1 = prob.omega, prob.omega1
+    d.kappa, d.dt_phys, d.rho_ref, d.p0 = prob.kappa, prob.dt_phys, prob.rho_ref, prob.p0
+    d.storage = prob.storage if storage is None else storage
+    return d, keep
+
+
+def workspace_size(prob, storage: Optional[int] = None) -> int:
+    lib = load()
+    d, _keep = make_desc(prob, storage)
+    n = C.c_size_t(0)
+    st = lib.lbm_workspace_size(C.byref(d), C.byref(n))
+    if st != LBM_OK:
+        raise LbmError(st, lib.lbm_last_error(None).decode())
+    return int(n.value)
+
+
+class Solver:
+    """One lattice on one HIP device, advanced by the HIP library."""
+
+    def __init__(self, prob, storage: Optional[int] = None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the reactive LBM step runs only on the GPU")
+        self.torch = torch
+        self.lib = load()
+        self.prob = prob
+        self.M = prob.mech.M
+        self.S = self.M + 1
+        self.N = prob.N
+        self.device = (torch.device(device) if device is not None
+                       else torch.device("cuda", torch.cuda.current_device()))
+        self.desc, self._keep = make_desc(prob, storage)
+        self.storage = self.desc.storage
+        n = C.c_size_t(0)
+        self._check(self.lib.lbm_workspace_size(C.byref(self.desc), C.byref(n)), None)
+        self.ws_bytes = int(n.value)
+        with torch.cuda.device(self.device):
+            self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws_raw.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            h = C.c_void_p()
+            self._check(self.lib.lbm_create(C.byref(self.desc), C.c_void_p(self._ws_ptr), C.c_size_t(self.ws_bytes),
+                                            C.byref(h)), None)
+        self.h = h
+
+    # ------------------------------------------------------------------------------
+    def _check(self, st, h):
+        if st != LBM_OK:
+            msg = self.lib.lbm_last_error(h)
+            raise LbmError(st, msg.decode() if msg else "")
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _dev(self, a, dtype=None):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=dtype or t.float64).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype or t.float64, device=self.device).contiguous()
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.lbm_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------------------
+    def init(self, rho=None, u=None, T=None, Y=None):
+        p = self.prob
+        N, M = self.N, self.M
+        r = self._dev(p.rho if rho is None else rho).reshape(N)
+        uu = self._dev(p.u if u is None else u).reshape(3, N)
+        TT = self._dev(p.T if T is None else T).reshape(N)
+        YY = self._dev(p.Y if Y is None else Y).reshape(M, N)
+        self._init_keep = (r, uu, TT, YY)
+        self._check(self.lib.lbm_init_fields(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(uu.data_ptr()),
+                                             C.c_void_p(TT.data_ptr()), C.c_void_p(YY.data_ptr()),
+                                             self._stream()), self.h)
+        return self
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_step(self.h, int(n), self._stream()), self.h)
+
+    def step_timed(self, n: int = 1) -> Dict[str, float]:
+        ms = (C.c_float * NUM_KERNELS)()
+        self._check(self.lib.lbm_step_timed(self.h, int(n), self._stream(), ms), self.h)
+        return {KERNEL_NAMES[k]: float(ms[k]) for k in range(NUM_KERNELS)}
+
+    def macros(self, to_numpy: bool = True):
+        t = self.torch
+        N, M = self.N, self.M
+        rho = t.empty(N, dtype=t.float64, device=self.device)
+        u = t.empty(3, N, dtype=t.float64, device=self.device)
+        T = t.empty(N, dtype=t.float64, device=self.device)
+        P = t.empty(N, dtype=t.float64, device=self.device)
+        Y = t.empty(M, N, dtype=t.float64, device=self.device)
+        self._check(self.lib.lbm_macros(self.h, *(C.c_void_p(a.data_ptr()) for a in (rho, u, T, P, Y)),
+                                        self._stream()), self.h)
+        out = dict(rho=rho, u=u, T=T, P=P, Y=Y)
+        if to_numpy:
+            t.cuda.synchronize(self.device)
+            out = {k: v.cpu().numpy() for k, v in out.items()}
+        return out
+
+    def populations(self, nodes: Sequence[int], to_numpy: bool = True):
+        """Pre-collision populations [S, 27, k] and stored temperatures at node ids."""
+        t = self.torch
+        idx = self._dev(np.asarray(nodes, dtype=np.int64), dtype=t.int64).reshape(-1)
+        k = idx.numel()
+        out = t.empty(self.S, 27, max(k, 1), dtype=t.float64, device=self.device)
+        Tn = t.empty(max(k, 1), dtype=t.float64, device=self.device)
+        self._check(self.lib.lbm_populations(self.h, C.c_void_p(idx.data_ptr()), C.c_int64(k),
+                                             C.c_void_p(out.data_ptr()), C.c_void_p(Tn.data_ptr()),
+                                             self._stream()), self.h)
+        out, Tn = out[:, :, :k], Tn[:k]
+        if to_numpy:
+            t.cuda.synchronize(self.device)
+            return out.cpu().numpy(), Tn.cpu().numpy()
+        return out, Tn
+
+    def status(self) -> int:
+        bits = C.c_uint32(0)
+        st = self.lib.lbm_status_sync(self.h, self._stream(), C.byref(bits))
+        if st not in (LBM_OK, -5):
+            self._check(st, self.h)
+        return int(bits.value)

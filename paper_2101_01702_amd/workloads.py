@@ -269,8 +269,9 @@ def h2air_mechanism(seed: int = 7, n_reactions: int = 19) -> Mechanism:
     element-balanced A+B<=>C+D and A+B<=>C templates over the 8 reactive species,
     with every species present and fuel connected to product; log10 A ~ U[8,14],
     b ~ U[-1,1], Ta ~ U[0,2e4] K.  NASA-7 rows are seeded: cp/R in [2.5, 8] on
-    [250, 3500] K, h_f = 0 for H2/O2/N2, U[30,260] kJ/mol for radicals and
-    U[-250,-100] kJ/mol for the two stable products, s0 ~ U[100,240] J/(mol K)."""
+    [250, 3500] K, h_f = 0 for H2/O2/N2, U[200,260] kJ/mol for the radical atoms,
+    U[30,60] kJ/mol for the polyatomic radicals and U[-250,-100] kJ/mol for the two
+    stable products, s0 in [100,240] J/(mol K) growing with the atom count."""
     rng = np.random.default_rng(seed)
     names = [s[0] for s in H2AIR_SPECIES]
     comp = np.array([s[1:] for s in H2AIR_SPECIES], np.int32)
@@ -295,10 +296,12 @@ def h2air_mechanism(seed: int = 7, n_reactions: int = 19) -> Mechanism:
         if nm in ("H2", "O2", "N2"):
             h_f = 0.0
         elif nm in _RADICALS:
-            h_f = rng.uniform(30e3, 260e3)
+            # atoms are the most endothermic radicals
+            h_f = rng.uniform(200e3, 260e3) if atoms == 1 else rng.uniform(30e3, 60e3)
         else:
             h_f = rng.uniform(-250e3, -100e3)
-        s0 = rng.uniform(100.0, 240.0)
+        # standard entropy grows with the number of atoms (bounded to [100, 240])
+        s0 = {1: rng.uniform(110.0, 165.0), 2: rng.uniform(130.0, 210.0)}.get(atoms, rng.uniform(185.0, 235.0))
         nasa[a] = nasa7_coeffs(cp, h_f, s0)
     n_reactive = M - 1
     cands = _candidate_reactions(comp, n_reactive)
@@ -309,8 +312,13 @@ def h2air_mechanism(seed: int = 7, n_reactions: int = 19) -> Mechanism:
         present = set(a for lhs, rhs in reacs for a in lhs + rhs)
         if len(present) == n_reactive and _connected(reacs, n_reactive, fuel, prod):
             break
+    h_form = np.array([nasa[a, 5] + nasa[a, 0] * T_REF for a in range(M)])  # h_f / R_U at T_REF
     reactions = []
     for lhs, rhs in reacs:
+        # each reaction is written in its exothermic direction, so that the sampled
+        # Arrhenius law is the fast direction and the reverse rate k_f/K_c stays bounded
+        if sum(h_form[a] for a in rhs) > sum(h_form[a] for a in lhs):
+            lhs, rhs = rhs, lhs
         A = 10.0 ** rng.uniform(8, 14)
         b = rng.uniform(-1, 1)
         Ta = rng.uniform(0, 2e4)
@@ -341,8 +349,8 @@ def _default_transport(M: int, rng: np.random.Generator, lo: float, hi: float) -
 
 
 def flame1d(nx: int = 4096, seed: int = 7, phi: float = 1.0, T_u: float = 300.0,
-            T_hot: float = 2000.0, hot_cells: int = 64, zeta_ref: float = 0.05,
-            omega: float = 1.6, prandtl: float = 0.7, dt_phys: float = 2e-7,
+            T_hot: float = 2000.0, hot_cells: int = 64, zeta_ref: float = 0.003,
+            omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 1e-12,
             diff_range=(0.02, 0.08), steps: int = 20000, edge: float = 2.0,
             storage: int = STORE_F64, mech: Optional[Mechanism] = None) -> Problem:
     """Quasi-1D premixed flame: nx x 1 x 1, periodic y/z, zero-velocity open end at
@@ -369,8 +377,8 @@ def flame1d(nx: int = 4096, seed: int = 7, phi: float = 1.0, T_u: float = 300.0,
 
 
 def sphere3d(n: int = 256, seed: int = 7, phi: float = 0.8, T_u: float = 300.0,
-             T_ig: float = 1500.0, radius: float = 12.0, zeta_ref: float = 0.05,
-             omega: float = 1.6, prandtl: float = 0.7, dt_phys: float = 2e-7,
+             T_ig: float = 1500.0, radius: float = 12.0, zeta_ref: float = 0.003,
+             omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 1e-12,
              diff_range=(0.02, 0.08), edge: float = 2.0, storage: int = STORE_F32,
              shape: Optional[Tuple[int, int, int]] = None,
              mech: Optional[Mechanism] = None) -> Problem:

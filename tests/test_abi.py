@@ -1,0 +1,132 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every entry
+point the header declares, and rejects invalid descriptors with explicit errors."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2101_01702_amd import lbm
+from paper_2101_01702_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_2101_01702_amd import build
+        build.build()
+    return lbm.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:lbm_status|const char \*)\s*(lbm_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_macros", "lbm_adjoint_step"):
+        assert n in names
+    assert set(names) == set(lbm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _desc(prob, **kw):
+    d, keep = lbm.make_desc(prob)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d, keep
+
+
+def _ws(lib, d):
+    n = C.c_size_t(0)
+    st = lib.lbm_workspace_size(C.byref(d), C.byref(n))
+    return st, n.value, lib.lbm_last_error(None).decode()
+
+
+def test_workspace_size_config1(lib):
+    prob = W.config1()
+    d, keep = _desc(prob)
+    st, n, _ = _ws(lib, d)
+    assert st == 0
+    S, N = 4, 512
+    pops = 2 * S * 27 * N * 8
+    assert pops < n < pops + 200_000
+
+
+def test_workspace_grows_with_ghost_layer(lib):
+    per = W.config1(nx=16, ny=4, nz=4)
+    opn = W.config1(nx=16, ny=4, nz=4)
+    opn.bc = (1, 1, 0, 0, 0, 0)
+    d1, k1 = _desc(per)
+    d2, k2 = _desc(opn)
+    assert _ws(lib, d2)[1] - _ws(lib, d1)[1] >= 2 * 4 * 27 * (2 * 4 * 4) * 8
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("nx", 0, "lattice sizes"),
+    ("n_species", 1, "n_species"),
+    ("n_species", 11, "n_species"),
+    ("n_reactions", -1, "n_reactions"),
+    ("omega", 2.0, "omega"),
+    ("omega1", 0.0, "omega1"),
+    ("kappa", 0.0, "kappa"),
+    ("rho_ref", -1.0, "rho_ref"),
+    ("storage", 7, "storage"),
+])
+def test_invalid_descriptor_rejected(lib, field, value, needle):
+    d, keep = _desc(W.config1(), **{field: value})
+    st, _, msg = _ws(lib, d)
+    assert st == -1
+    assert needle in msg
+
+
+def test_unpaired_periodic_face_rejected(lib):
+    d, keep = _desc(W.config1())
+    d.bc = (C.c_int32 * 6)(0, 1, 0, 0, 0, 0)
+    st, _, msg = _ws(lib, d)
+    assert st == -1 and "pairs" in msg
+
+
+def test_asymmetric_diffusivity_rejected(lib):
+    prob = W.config1()
+    prob.diff = prob.diff.copy()
+    prob.diff[0, 1] *= 1.5
+    d, keep = _desc(prob)
+    st, _, msg = _ws(lib, d)
+    assert st == -1 and "symmetric" in msg
+
+
+def test_mass_unbalanced_reaction_rejected(lib):
+    prob = W.config1()
+    prob.mech.nu_prod = prob.mech.nu_prod * 2
+    d, keep = _desc(prob)
+    st, _, msg = _ws(lib, d)
+    assert st == -1 and "mass" in msg
+
+
+def test_create_rejects_bad_workspace_without_device(lib):
+    d, keep = _desc(W.config1())
+    h = C.c_void_p()
+    assert lib.lbm_create(C.byref(d), None, 0, C.byref(h)) == -1
+    assert lib.lbm_create(C.byref(d), C.c_void_p(0x1001), 1 << 30, C.byref(h)) == -4
+    assert "aligned" in lib.lbm_last_error(None).decode()
+    assert lib.lbm_create(C.byref(d), C.c_void_p(0x100000), 1024, C.byref(h)) == -4
+    assert "needed" in lib.lbm_last_error(None).decode()
+    assert not h.value
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.lbm_step(None, 1, None) == -1
+    assert lib.lbm_macros(None, None, None, None, None, None, None) == -1
+    assert lib.lbm_init_fields(None, None, None, None, None, None) == -1
+    assert lib.lbm_status_sync(None, None, None) == -1
+    assert lib.lbm_adjoint_step(None, None, None, None, None) == -2
