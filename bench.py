@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the reactive-mixture LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: 3D expanding spherical flame, 256^3 D3Q27 lattice, all faces open, 9
+species / 19 reversible reactions (seeded synthetic mechanism), FP32 population
+storage with FP64 arithmetic.  One step = the whole hot path (moments, temperature,
+production rates, Stefan-Maxwell solve, collision of all M+1 sets, non-local
+correction stencils, equilibrium ghosts, streaming).  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "reactive MLUPS & % of HBM peak at stated error vs FP64; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_main_sphere3d_256.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01702_amd", "csrc", "lbm_device.hip")
+
+
+def kernel_source_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the main kernel from committed rocprofv3 counters, or
+    None when the kernel source changed since they were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec
+
+
+def copy_ceiling_gbs(torch, dev, nbytes=4 << 30, reps=5):
+    """Read+write bandwidth of a plain device copy (measured ceiling)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize(dev)
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / dt / 1e9
+
+
+def cpu_baseline(seconds=12.0):
+    """FP64 CPU oracle on a 32^3 crop of the same workload, time-boxed."""
+    from oracle import oracle as orc
+    from paper_2101_01702_amd import workloads as W
+    cores = max(1, min(16, os.cpu_count() or 1))
+    prob = W.sphere3d(shape=(32, 32, 32))
+    sim = orc.OracleSim(prob).init()
+    sim.step(1, cores)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds or steps < 2:
+        sim.step(1, cores)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(prob.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"32^3 crop of the same spherical flame (M=9, R=19, FP64), {steps} steps, {dt:.1f} s"}
+
+
+def error_vs_f64(lbm, W, steps=100):
+    """Normwise field error of FP32 storage against FP64 storage on a 32^3 crop."""
+    import numpy as np
+    prob = W.sphere3d(shape=(32, 32, 32))
+    out = {}
+    for st in (W.STORE_F64, W.STORE_F32):
+        s = lbm.Solver(prob, storage=st).init()
+        s.step(steps)
+        out[st] = s.macros()
+        s.close()
+    a, b = out[W.STORE_F32], out[W.STORE_F64]
+    zeta = prob.kappa * W.R_U * prob.T.min() / (1e-3 / (prob.Y[:, 0] / prob.mech.molar_mass).sum())
+    errs = {}
+    for k in ("rho", "T", "P"):
+        errs[k] = float(np.abs(a[k] - b[k]).max() / np.abs(b[k]).max())
+    errs["u"] = float(max(np.abs(a["u"][d] - b["u"][d]).max() / max(np.abs(b["u"][d]).max(), math.sqrt(zeta))
+                          for d in range(3)))
+    errs["Y"] = float(max(np.abs(a["Y"][k] - b["Y"][k]).max() / max(np.abs(b["Y"][k]).max(), 1e-12)
+                          for k in range(prob.M)))
+    return {"max_rel": max(errs.values()), "fields": errs, "steps": steps, "lattice": "32^3 crop"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="lattice edge (256 = the benchmarked workload)")
+    ap.add_argument("--storage", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--copy-only", action="store_true", help="run only the copy kernel (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the step has no multi-GPU path in this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2101_01702_amd import lbm
+    from paper_2101_01702_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.copy_only:
+        print(json.dumps({"copy_ceiling_GBps": round(copy_ceiling_gbs(torch, dev), 1), "bytes": 2 * (4 << 30)}))
+        return
+
+    storage = W.STORE_F32 if args.storage == "f32" else W.STORE_F64
+    word = 4 if storage == W.STORE_F32 else 8
+    prob = W.sphere3d(n=args.n, storage=storage)
+    M = prob.M
+    N = prob.N
+    solver = lbm.Solver(prob, storage=storage, device=dev).init()
+    del prob.rho, prob.u, prob.T, prob.Y
+    torch.cuda.synchronize(dev)
+    solver.step(args.warmup)
+    if solver.status():
+        raise RuntimeError("device anomaly during warm-up")
+    torch.cuda.synchronize(dev)
+
+    t0 = time.perf_counter()
+    kernel_ms = solver.step_timed(args.steps)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    anomaly = solver.status()
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+
+    mlups = N * args.steps / wall / 1e6
+    ms_per_step = wall * 1e3 / args.steps
+    # algorithmic bytes of the main kernel per node: every population of the M+1 sets
+    # read once and written once
+    alg_bytes_node = 2 * 27 * (M + 1) * word
+    main_ms = kernel_ms["main"] / args.steps
+    achieved = alg_bytes_node * N / (main_ms * 1e-3) / 1e9
+    rec = recorded_traffic()
+    traffic = rec["traffic_bytes_per_launch"] if (rec and args.n == 256 and storage == W.STORE_F32) else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"spherical flame {args.n}^3 D3Q27, 9 species, 19 reversible reactions, "
+                               f"{args.storage} population storage, FP64 arithmetic",
+                   "lattice": [args.n] * 3, "species": M, "reactions": 19, "storage": args.storage,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in kernel_ms.items()},
+        "whole_step_hbm_frac": round(alg_bytes_node * N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "anomaly_bits": anomaly,
+    }
+    if not args.no_error_check:
+        out["error_vs_f64"] = error_vs_f64(lbm, W)
+    out["copy_ceiling_GBps"] = round(copy_ceiling_gbs(torch, dev), 1)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,11 @@ void build_tables(const lbm_desc &d, Tables &t) {
       t.invD[a][b] = (a == b) ? 0.0 : 1.0 / d.diff_ab[a * M + b];
       t.invDf[a][b] = (float)t.invD[a][b];
     }
+    for (int b = a + 1; b < M; ++b) {
+      const int k = a * M - a * (a + 1) / 2 + (b - a - 1);
+      t.invDp[k] = 1.0 / d.diff_ab[a * M + b];
+      t.invDpf[k] = (float)t.invDp[k];
+    }
     t.conc_scale[a] = d.rho_ref / d.molar_mass[a];
     t.rdot_scale[a] = d.molar_mass[a] * d.dt_phys / d.rho_ref;
   }

@@ -39,10 +39,20 @@ __device__ __forceinline__ R psi_c(int c, R xi, R s) {
   return c == 0 ? R(1) - s : (c > 0 ? R(0.5) * (xi + s) : R(0.5) * (s - xi));
 }
 
-// Source coordinates of the pull along c for one axis: periodic wrap or ghost.
+// Psi_c(xi, zeta) - Psi_c(xi + d, zeta) in closed form (eq. phis): for c = 0 it is
+// d (2 xi + d), for c = +-1 it is -d (c + 2 xi + d) / 2
+template <typename R>
+__device__ __forceinline__ R psi_diff(int c, R xi, R d) {
+  return c == 0 ? d * (R(2) * xi + d) : R(-0.5) * d * (R(c) + R(2) * xi + d);
+}
+
+// Source of the pull along c: byte offset of the source in one (set, direction)
+// plane of the padded lattice, and its interior node index (-1 for a ghost cell).
+// Plane bases are wave-uniform, so loads use a scalar base and a 32-bit offset (a
+// plane of the largest lattice is far below 4 GiB).
 struct Src {
-  int64_t ps;   // padded storage index of the source
-  int64_t ns;   // interior node index of the source, -1 when it is a ghost cell
+  uint32_t ps;  // padded node index of the source
+  int32_t ns;   // interior node index of the source, -1 when it is a ghost cell
 };
 
 struct AxisSrc {
@@ -66,11 +76,47 @@ __device__ __forceinline__ AxisSrc axis_src(int x, int n, bool periodic) {
 __device__ __forceinline__ Src make_src(const Geom &g, const AxisSrc &ax, const AxisSrc &ay,
                                         const AxisSrc &az, int kx, int ky, int kz) {
   Src r;
-  const int64_t sx = ax.s[kx], sy = ay.s[ky], sz = az.s[kz];
-  r.ps = ((sz + g.pz) * g.NY + (sy + g.py)) * g.NX + (sx + g.px);
+  const uint32_t sx = (uint32_t)(ax.s[kx] + g.px), sy = (uint32_t)(ay.s[ky] + g.py),
+                 sz = (uint32_t)(az.s[kz] + g.pz);
+  r.ps = (sz * (uint32_t)g.NY + sy) * (uint32_t)g.NX + sx;
   const bool out = ax.out[kx] || ay.out[ky] || az.out[kz];
-  r.ns = out ? -1 : (sz * g.ny + sy) * g.nx + sx;
+  r.ns = out ? -1 : (az.s[kz] * g.ny + ay.s[ky]) * g.nx + ax.s[kx];
   return r;
+}
+
+// source of the pull for a uniform (cy, cz) and a compile-time x index: the y and z
+// coordinates are wrapped or left in the ghost layer without table lookups
+struct RowSrc {
+  uint32_t prow;   // padded row index (z, y) times NX
+  int32_t nrow;    // interior row index times nx, or -1 when (y, z) is in the ghost layer
+};
+
+__device__ __forceinline__ RowSrc row_src(const Geom &g, int y, int z, int cy, int cz) {
+  int sy = y - cy, sz = z - cz;
+  if (g.per[1]) sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+  if (g.per[2]) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
+  const bool out = sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz;
+  RowSrc r;
+  r.prow = ((uint32_t)(sz + g.pz) * (uint32_t)g.NY + (uint32_t)(sy + g.py)) * (uint32_t)g.NX;
+  r.nrow = out ? -1 : (sz * g.ny + sy) * g.nx;
+  return r;
+}
+
+__device__ __forceinline__ Src src_from_row(const Geom &g, const RowSrc &row, const AxisSrc &ax, int kx) {
+  Src r;
+  r.ps = row.prow + (uint32_t)(ax.s[kx] + g.px);
+  r.ns = (row.nrow < 0 || ax.out[kx]) ? -1 : row.nrow + ax.s[kx];
+  return r;
+}
+
+// element `idx` of a plane with a uniform base, addressed by a 32-bit byte offset
+template <typename T>
+__device__ __forceinline__ T ld(const T *__restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T *__restrict__ base, uint32_t idx, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (uint32_t)sizeof(T)) = v;
 }
 
 // neighbour for the isotropic gradient: periodic wrap or clamp at open faces
@@ -91,13 +137,14 @@ struct Corr {
 template <int CX, typename ST, typename RT>
 __device__ __forceinline__ RT pull_f(const ST *__restrict__ base, const Src &r, const Corr<RT> &cr, int cy,
                                      int cz) {
-  RT v = RT(base[r.ps]);
+  RT v = RT(ld(base, r.ps));
   if (r.ns >= 0) {
+    const uint32_t ns = (uint32_t)r.ns;
     if constexpr (CX != 0) {
-      if (cy == 0 && cz == 0) v += RT(0.5 * CX) * cr.X[r.ns];
+      if (cy == 0 && cz == 0) v += RT(0.5 * CX) * ld(cr.X, ns);
     } else {
-      if (cy != 0 && cz == 0) v += RT(0.5) * RT(cy) * cr.X[cr.N + r.ns];
-      if (cy == 0 && cz != 0) v += RT(0.5) * RT(cz) * cr.X[2 * cr.N + r.ns];
+      if (cy != 0 && cz == 0) v += RT(0.5) * RT(cy) * ld(cr.X + cr.N, ns);
+      if (cy == 0 && cz != 0) v += RT(0.5) * RT(cz) * ld(cr.X + 2 * cr.N, ns);
     }
   }
   return v;
@@ -107,12 +154,13 @@ __device__ __forceinline__ RT pull_f(const ST *__restrict__ base, const Src &r, 
 template <int CX, typename ST, typename RT>
 __device__ __forceinline__ RT pull_g(const ST *__restrict__ base, const Src &r, const Corr<RT> &cr, int cy,
                                      int cz, RT w3) {
-  RT v = RT(base[r.ps]);
+  RT v = RT(ld(base, r.ps));
   if (r.ns >= 0) {
+    const uint32_t ns = (uint32_t)r.ns;
     RT d = RT(0);
-    if constexpr (CX != 0) d += RT(CX) * cr.Cg[r.ns];
-    if (cy != 0) d += RT(cy) * cr.Cg[cr.N + r.ns];
-    if (cz != 0) d += RT(cz) * cr.Cg[2 * cr.N + r.ns];
+    if constexpr (CX != 0) d += RT(CX) * ld(cr.Cg, ns);
+    if (cy != 0) d += RT(cy) * ld(cr.Cg + cr.N, ns);
+    if (cz != 0) d += RT(cz) * ld(cr.Cg + 2 * cr.N, ns);
     v += w3 * d;
   }
   return v;
@@ -148,8 +196,8 @@ struct Macro {
 
 template <int M, typename ST, typename RT>
 __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict__ pop, const Corr<RT> &cr,
-                                             const AxisSrc &ax, const AxisSrc &ay, const AxisSrc &az,
-                                             Macro<M> &m) {
+                                             int x, int y, int z, Macro<M> &m) {
+  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
   const int64_t NPAD = g.NPAD;
   double rho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
   double rE = 0, qx = 0, qy = 0, qz = 0;
@@ -161,11 +209,12 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
     const int ky = kyz % 3, kz = kyz / 3;
     const int cy = ky - 1, cz = kz - 1;
     const RT wyz3 = RT(3.0 * w1(cy) * w1(cz));
+    const RowSrc row = row_src(g, y, z, cy, cz);
     static_for<3>([&](auto Kx) {
       constexpr int kx = decltype(Kx)::value;
       constexpr int cx = kx - 1;
       const int i = kx + 3 * kyz;
-      const Src r = make_src(g, ax, ay, az, kx, ky, kz);
+      const Src r = src_from_row(g, row, ax, kx);
       const double f = (double)pull_f<cx, ST, RT>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
       const double gg =
           (double)pull_g<cx, ST, RT>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, RT(w1(cx)) * wyz3);
@@ -180,7 +229,7 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
       pyz += (cy * cz) * f;
 #pragma unroll
       for (int a = 0; a < M - 1; ++a) {
-        const double fa = (double)pop[((int64_t)a * Q + i) * NPAD + r.ps];
+        const double fa = (double)ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
         ra[a] += fa;
         if constexpr (cx != 0) jax[a] += cx * fa;
         jay[a] += cy * fa;
@@ -257,8 +306,32 @@ __device__ __forceinline__ void store_rt(void *base, int64_t idx, RT v) {
 }
 
 // ---- the step --------------------------------------------------------------------
+// Per-thread LDS stash of the values that live across the Stefan-Maxwell solve, so
+// that the solve holds only its matrix in registers.  Word-major layout (word w of
+// thread t at w * blockDim + t): conflict-free.
+template <int M>
+struct StashLayout {
+  static constexpr int RS = 0;            // species densities [M]
+  static constexpr int U = RS + M;        // velocity [3]
+  static constexpr int G = U + 3;         // g coefficients [10]: A0, A1[3], A2[6]
+  static constexpr int RD = G + 10;       // production rates [M-1]
+  static constexpr int WORDS = RD + M - 1;
+};
+constexpr int MAIN_BLOCK = 256;
+
+// Precision of the inter-species term F of eq. fStar (a correction whose sum over
+// directions vanishes): FP64 for FP64 storage, FP32 for FP32 storage.
+template <typename ST>
+using FT = ST;
+
 template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(256) void k_main(Geom g, Buffers b, int cur) {
+__global__ __launch_bounds__(MAIN_BLOCK) void k_main(Geom g, Buffers b, int cur) {
+  using SL = StashLayout<M>;
+  __shared__ double stash[SL::WORDS * MAIN_BLOCK];
+  const int tid = threadIdx.x;
+  auto st_w = [&](int w, double v) { stash[w * MAIN_BLOCK + tid] = v; };
+  auto st_r = [&](int w) { return stash[w * MAIN_BLOCK + tid]; };
+
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const Tables &tb = *b.tab;
@@ -269,67 +342,132 @@ __global__ __launch_bounds__(256) void k_main(Geom g, Buffers b, int cur) {
   ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
   const int64_t N = g.N, NPAD = g.NPAD;
   const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
-  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
-  const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
-  const AxisSrc az = axis_src(z, g.nz, g.per[2]);
 
-  // O1: moments of the pulled state
-  Macro<M> m;
-  node_moments<M, ST, RT>(g, src, cr, ax, ay, az, m);
   uint32_t anom = 0;
-  if (!(m.rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
-  const double inv_rho = 1.0 / m.rho;
-
-  // O2: temperature and mixture gas constant
-  double T;
-  if (!node_temperature<M>(tb, m, b.T[n], T)) anom |= LBM_ANOM_NEWTON;
-  const double invT = 1.0 / T, lnT = log(T);
-  double zeta = 0.0;
-#pragma unroll
-  for (int a = 0; a < M; ++a) zeta += m.rs[a] * inv_rho * tb.Ra[a];
-  zeta *= T;
-  const double P = m.rho * zeta;
-
-  // O3: production rates (mass action, K_c from the NASA-7 Gibbs function)
-  RT rdot[M - 1];
+  double rho, T, zeta;
+  double du[M][3];   // right-hand side u_a - u of eq. transform1, then its solution
   {
-    double c[M], wd[M], gib[M];
+    // O1: moments of the pulled state
+    Macro<M> m;
+    node_moments<M, ST, RT>(g, src, cr, x, y, z, m);
+    if (!(m.rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
+    rho = m.rho;
+    const double inv_rho = 1.0 / rho;
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-      c[a] = m.rs[a] * tb.conc_scale[a];
-      wd[a] = 0.0;
-      gib[a] = h_RT(tb.nasa[a], T, invT) - s_R(tb.nasa[a], T, lnT);
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) du[a][d] = m.du0[a][d];
+
+    // O2: temperature, mixture gas constant, enthalpies
+    if (!node_temperature<M>(tb, m, b.T[n], T)) anom |= LBM_ANOM_NEWTON;
+    const double invT = 1.0 / T;
+    zeta = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) zeta += m.rs[a] * inv_rho * tb.Ra[a];
+    zeta *= T;
+    const double P = rho * zeta;
+    double Hmix = 0.0;
+    {
+      const double wc = 0.5 * (2.0 - tb.omega1) * P;
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const double Ya = m.rs[a] * inv_rho;
+        const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
+        Hmix += Ya * Ha;
+        store_rt<RT>(b.side_Y, a * N + n, RT(Ya));
+        store_rt<RT>(b.side_w, a * N + n, RT(wc * Ha));
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double u = m.u[d];
+        store_rt<RT>(b.side_phi, d * N + n, RT(rho * u * (1.0 - 3.0 * zeta) - rho * u * u * u));
+      }
+      if (tb.open_any) {
+        store_rt<RT>(b.side_rho, n, RT(rho));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) store_rt<RT>(b.side_u, d * N + n, RT(m.u[d]));
+      }
+      b.T[n] = T;
+      if (!isfinite(T) || !isfinite(rho) || !isfinite(m.rhoE)) anom |= LBM_ANOM_NONFINITE;
+      if (anom) atomicOr(b.status, anom);
     }
-    const double ln_c0 = tb.ln_c0_const - lnT;
-    for (int k = 0; k < tb.R; ++k) {
-      const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
-      double fwd = exp(lnkf);
+
+    // g collision coefficients (eq. g folded with eqs. gieq, geq1mom, geq2mom,
+    // gstareq1mom): g' = (1-omega) g + w_i [A0 + A1.c + A2 : c c] with
+    // A1 = 3 omega q^eq + 3 V, V = (omega-omega1)(q - u.(P - P^eq) - q^eq)
+    //      + omega1 rho sum_a H_a Y_a du_a (the last term is added after the solve)
+    {
+      const double usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+      const double h2 = Hmix + 0.5 * usq;
+      const double *u = m.u;
+      double qeq[3], Peq[6], Req[6];
+      for (int d = 0; d < 3; ++d) qeq[d] = h2 * rho * u[d];
+      const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
-      for (int a = 0; a < M; ++a)
-        for (int r = 0; r < tb.nu_r[k][a]; ++r) fwd *= c[a];
-      double rev = 0.0;
-      if (tb.rev[k]) {
-        double dG = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        Peq[k] = (k < 3 ? rho * zeta : 0.0) + rho * u[ia[k]] * u[ib[k]];
+        Req[k] = h2 * Peq[k] + P * u[ia[k]] * u[ib[k]];
+      }
+      const double om_d = tb.omega, om1 = tb.omega1;
+      const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+      const double trR = Req[0] + Req[1] + Req[2];
+      st_w(SL::G + 0, om_d * (2.5 * m.rhoE - 1.5 * trR));
 #pragma unroll
-        for (int a = 0; a < M; ++a) dG += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * gib[a];
-        const double lnKc = -dG + tb.dnu[k] * ln_c0;
-        rev = exp(lnkf - lnKc);
+      for (int d = 0; d < 3; ++d) {
+        double uP = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uP += u[c] * (m.P6[sym[c][d]] - Peq[sym[c][d]]);
+        st_w(SL::G + 1 + d, om_d * 3.0 * qeq[d] + 3.0 * (om_d - om1) * (m.q[d] - uP - qeq[d]));
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        st_w(SL::G + 4 + k, om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal twice
+    }
+
+    // O3: production rates (mass action, K_c from the NASA-7 Gibbs function)
+    {
+      const double lnT = log(T);
+      double c[M], wd[M], gib[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        c[a] = m.rs[a] * tb.conc_scale[a];
+        wd[a] = 0.0;
+        gib[a] = h_RT(tb.nasa[a], T, invT) - s_R(tb.nasa[a], T, lnT);
+      }
+      const double ln_c0 = tb.ln_c0_const - lnT;
+      for (int k = 0; k < tb.R; ++k) {
+        const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
+        double fwd = exp(lnkf);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-          for (int r = 0; r < tb.nu_p[k][a]; ++r) rev *= c[a];
-      }
-      const double qk = fwd - rev;
+          for (int r = 0; r < tb.nu_r[k][a]; ++r) fwd *= c[a];
+        double rev = 0.0;
+        if (tb.rev[k]) {
+          double dG = 0.0;
 #pragma unroll
-      for (int a = 0; a < M; ++a) wd[a] += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * qk;
+          for (int a = 0; a < M; ++a) dG += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * gib[a];
+          const double lnKc = -dG + tb.dnu[k] * ln_c0;
+          rev = exp(lnkf - lnKc);
+#pragma unroll
+          for (int a = 0; a < M; ++a)
+            for (int r = 0; r < tb.nu_p[k][a]; ++r) rev *= c[a];
+        }
+        const double qk = fwd - rev;
+#pragma unroll
+        for (int a = 0; a < M; ++a) wd[a] += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * qk;
+      }
+#pragma unroll
+      for (int a = 0; a < M - 1; ++a) st_w(SL::RD + a, tb.rdot_scale[a] * wd[a]);
     }
 #pragma unroll
-    for (int a = 0; a < M - 1; ++a) rdot[a] = RT(tb.rdot_scale[a] * wd[a]);
+    for (int a = 0; a < M; ++a) st_w(SL::RS + a, m.rs[a]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) st_w(SL::U + d, m.u[d]);
   }
 
-  // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1);
-  // m.du0 is overwritten with the solution du_a
-  const double inv_zeta = 1.0 / zeta;
-  RT beta[M - 1];
+  // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1),
+  // Gaussian elimination on the row-diagonally dominant matrix
+  const double inv_rho = 1.0 / rho, inv_zeta = 1.0 / zeta;
   {
     double A[M][M];
 #pragma unroll
@@ -338,13 +476,12 @@ __global__ __launch_bounds__(256) void k_main(Geom g, Buffers b, int cur) {
       double it = 0.0;
 #pragma unroll
       for (int bb = 0; bb < M; ++bb) {
-        const double Yb = m.rs[bb] * inv_rho;
+        const double Yb = st_r(SL::RS + bb) * inv_rho;
         const double K = za * (tb.Ra[bb] * T) * tb.invD[a][bb] * inv_zeta;
         it += Yb * K;
         A[a][bb] = -0.5 * K * Yb;
       }
       A[a][a] = 1.0 + 0.5 * it;
-      if (a < M - 1) beta[a] = RT(it / (it + 2.0));
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -355,7 +492,7 @@ __global__ __launch_bounds__(256) void k_main(Geom g, Buffers b, int cur) {
 #pragma unroll
         for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) m.du0[r][d] -= l * m.du0[k][d];
+        for (int d = 0; d < 3; ++d) du[r][d] -= l * du[k][d];
       }
     }
 #pragma unroll
@@ -363,168 +500,144 @@ __global__ __launch_bounds__(256) void k_main(Geom g, Buffers b, int cur) {
       const double inv = 1.0 / A[r][r];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        double v = m.du0[r][d];
+        double v = du[r][d];
 #pragma unroll
-        for (int c = r + 1; c < M; ++c) v -= A[r][c] * m.du0[c][d];
-        m.du0[r][d] = v * inv;
+        for (int c = r + 1; c < M; ++c) v -= A[r][c] * du[c][d];
+        du[r][d] = v * inv;
       }
     }
   }
 
-  // O5: side channel for the non-local terms and the ghosts, stored temperature;
-  // energy-flux vector V of the g collision
-  double Hmix = 0.0, hyd[3] = {0.0, 0.0, 0.0};
+  // O7: collision coefficients
+  using F = FT<ST>;
+  const double u0 = st_r(SL::U + 0), u1 = st_r(SL::U + 1), u2 = st_r(SL::U + 2);
+  const double om = tb.omega;
+  double gA0, gA1[3], gA2[6];
   {
-    const double wc = 0.5 * (2.0 - tb.omega1) * P;
+    const double invT = 1.0 / T;
+    double hyd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      const double Ya = m.rs[a] * inv_rho;
       const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
-      Hmix += Ya * Ha;
+      const double HY = Ha * st_r(SL::RS + a) * inv_rho;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) hyd[d] += Ha * Ya * m.du0[a][d];
-      store_rt<RT>(b.side_Y, a * N + n, RT(Ya));
-      store_rt<RT>(b.side_w, a * N + n, RT(wc * Ha));
+      for (int d = 0; d < 3; ++d) hyd[d] += HY * du[a][d];
     }
+    gA0 = st_r(SL::G + 0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double u = m.u[d];
-      store_rt<RT>(b.side_phi, d * N + n, RT(m.rho * u * (1.0 - 3.0 * zeta) - m.rho * u * u * u));
-    }
-    if (tb.open_any) {
-      store_rt<RT>(b.side_rho, n, RT(m.rho));
+    for (int d = 0; d < 3; ++d) gA1[d] = st_r(SL::G + 1 + d) + 3.0 * tb.omega1 * rho * hyd[d];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) store_rt<RT>(b.side_u, d * N + n, RT(m.u[d]));
-    }
-    b.T[n] = T;
-    if (!isfinite(T) || !isfinite(m.rho) || !isfinite(m.rhoE)) anom |= LBM_ANOM_NONFINITE;
-    if (anom) atomicOr(b.status, anom);
-  }
-
-  // O7: collision coefficients in the compute precision
-  const RT om = RT(tb.omega);
-  const RT u0 = RT(m.u[0]), u1 = RT(m.u[1]), u2 = RT(m.u[2]);
-  const RT zr = RT(zeta), rr = RT(m.rho);
-  // energy g (eq. g, folded): g' = (1-omega) g + w_i [A0 + A1.c + A2 : c c] where the
-  // Grad equilibrium (eqs. gieq, geq1mom, geq2mom) and the quasi-equilibrium flux
-  // (eqs. gstareq1mom, qdiff) enter through
-  // V = (omega-omega1)(q - u.(P - P^eq) - q^eq) + omega1 rho sum_a H_a Y_a du_a
-  RT gA0, gA1[3], gA2[6];
-  {
-    const double usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-    const double h2 = Hmix + 0.5 * usq;
-    const double *u = m.u;
-    double qeq[3], Peq[6], Req[6];
-    for (int d = 0; d < 3; ++d) qeq[d] = h2 * m.rho * u[d];
-    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      Peq[k] = (k < 3 ? m.rho * zeta : 0.0) + m.rho * u[ia[k]] * u[ib[k]];
-      Req[k] = h2 * Peq[k] + P * u[ia[k]] * u[ib[k]];
-    }
-    const double om_d = tb.omega, om1 = tb.omega1;
-    const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    double V[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double uP = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) uP += u[c] * (m.P6[sym[c][d]] - Peq[sym[c][d]]);
-      V[d] = (om_d - om1) * (m.q[d] - uP - qeq[d]) + om1 * m.rho * hyd[d];
-    }
-    const double trR = Req[0] + Req[1] + Req[2];
-    gA0 = RT(om_d * (2.5 * m.rhoE - 1.5 * trR));
-#pragma unroll
-    for (int d = 0; d < 3; ++d) gA1[d] = RT(om_d * 3.0 * qeq[d] + 3.0 * V[d]);
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-      gA2[k] = RT(om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal counted twice
+    for (int k = 0; k < 6; ++k) gA2[k] = st_r(SL::G + 4 + k);
   }
   // species a < M-1 (eq. finalNumericalEquations with F_ai of eq. fStar):
   // f_ai' = (1 - 2 beta_a) f_ai + (2 beta_a rho_a + rho_dot_a) Phi_a(u)
   //         + (beta_a - 1) (Y_a zeta_a / zeta) sum_b invD_ab rho_b zeta_b (Phi_b(u) - Phi_b(u + du_b))
   // with Phi_b(v) the unit-density product form at zeta_b (eqs. feq, fstar, fsource)
-  RT zb[M], xs[M][3], tbw[M];
-  RT omb[M - 1], ca[M - 1], rcoef[M - 1];
+  double zb[M];
+  F dv[M][3], tbw[M];
+  double omb[M - 1], ca[M - 1];
+  F rcoef[M - 1];
 #pragma unroll
   for (int a = 0; a < M; ++a) {
     const double za = tb.Ra[a] * T;
-    zb[a] = RT(za);
-    tbw[a] = RT(m.rs[a] * za);
+    const double ra = st_r(SL::RS + a);
+    zb[a] = za;
+    tbw[a] = F(ra * za);
+    dv[a][0] = F(du[a][0]);
+    dv[a][1] = F(du[a][1]);
+    dv[a][2] = F(du[a][2]);
+    if (a < M - 1) {
+      // beta_a = dt / (2 tau_a + dt) with 1/tau_a = sum_b Y_b / tau_ab (eq. fStar, tauab)
+      double it = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xs[a][d] = RT(m.u[d] + m.du0[a][d]);
-  }
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    const RT bt = beta[a];
-    omb[a] = RT(1) - RT(2) * bt;
-    ca[a] = RT(2) * bt * RT(m.rs[a]) + rdot[a];
-    rcoef[a] = (bt - RT(1)) * RT(m.rs[a] * inv_rho * tb.Ra[a] * T * inv_zeta);
+      for (int bb = 0; bb < M; ++bb) it += st_r(SL::RS + bb) * inv_rho * (tb.Ra[bb] * T) * tb.invD[a][bb];
+      it *= za * inv_zeta;
+      const double bt = it / (it + 2.0);
+      omb[a] = 1.0 - 2.0 * bt;
+      ca[a] = 2.0 * bt * ra + st_r(SL::RD + a);
+      rcoef[a] = F((bt - 1.0) * ra * inv_rho * za * inv_zeta);
+    }
   }
 
   // O7 + store: second pass over the pulled populations
-  const int64_t pself = ((int64_t)(z + g.pz) * g.NY + (y + g.py)) * g.NX + (x + g.px);
-  const RT s0 = u0 * u0 + zr;
+  const uint32_t pself = ((uint32_t)(z + g.pz) * (uint32_t)g.NY + (uint32_t)(y + g.py)) * (uint32_t)g.NX +
+                         (uint32_t)(x + g.px);
+  const double s0 = u0 * u0 + zeta;
 #pragma unroll 1
-  for (int kyz = 0; kyz < 9; ++kyz) {
-    const int ky = kyz % 3, kz = kyz / 3;
-    const int cy = ky - 1, cz = kz - 1;
-    const RT wyz = RT(w1(cy) * w1(cz));
-    const RT fcy = RT(cy), fcz = RT(cz);
-    // y and z factors of the product forms for this (cy, cz)
-    const RT fyz = rr * psi_c<RT>(cy, u1, u1 * u1 + zr) * psi_c<RT>(cz, u2, u2 * u2 + zr);
-    RT pe_yz[M], ps_yz[M];
+  for (int i = 0; i < 27; ++i) {
+    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    const double fcx = cx, fcy = cy, fcz = cz;
+    const double wi = w1(cx) * w1(cy) * w1(cz);
+    Src r;
+    {
+      int sx = x - cx, sy = y - cy, sz = z - cz;
+      if (g.per[0]) sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+      if (g.per[1]) sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+      if (g.per[2]) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
+      const bool out = sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz;
+      r.ps = ((uint32_t)(sz + g.pz) * (uint32_t)g.NY + (uint32_t)(sy + g.py)) * (uint32_t)g.NX + (uint32_t)(sx + g.px);
+      r.ns = out ? -1 : (sz * g.ny + sy) * g.nx + sx;
+    }
+    // mixture f (eq. f); A_i.X is added by the next pull
+    {
+      double f = (double)ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, r.ps);
+      if (r.ns >= 0 && (cx * cx + cy * cy + cz * cz) == 1) {
+        const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
+        f += 0.5 * double(cx + cy + cz) * (double)ld(cr.X + axis * N, (uint32_t)r.ns);
+      }
+      const double feq = rho * psi_c<double>(cx, u0, s0) * psi_c<double>(cy, u1, u1 * u1 + zeta) *
+                         psi_c<double>(cz, u2, u2 * u2 + zeta);
+      st(dst + ((int64_t)(M - 1) * Q + i) * NPAD, pself, ST((1.0 - om) * f + om * feq));
+    }
+    // energy g; the q^corr part is added by the next pull
+    {
+      double gv = (double)ld(src + ((int64_t)M * Q + i) * NPAD, r.ps);
+      if (r.ns >= 0) {
+        const uint32_t ns = (uint32_t)r.ns;
+        gv += 3.0 * wi * (fcx * (double)ld(cr.Cg, ns) + fcy * (double)ld(cr.Cg + N, ns) + fcz * (double)ld(cr.Cg + 2 * N, ns));
+      }
+      const double acc = gA0 + fcx * gA1[0] + fcy * gA1[1] + fcz * gA1[2] + fcx * fcx * gA2[0] + fcy * fcy * gA2[1] +
+                         fcz * fcz * gA2[2] + fcx * fcy * gA2[3] + fcx * fcz * gA2[4] + fcy * fcz * gA2[5];
+      st(dst + ((int64_t)M * Q + i) * NPAD, pself, ST((1.0 - om) * gv + wi * acc));
+    }
+    // species: Phi_b(u) - Phi_b(u + du_b) by telescoping the three axis factors, each
+    // factor difference in closed form, so the difference keeps relative precision.
+    // Axis factor of species b: Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.
+    double phe[M];
+    F dd[M];
+    const double Bx = cx == 0 ? -1.0 : 0.5, By = cy == 0 ? -1.0 : 0.5, Bz = cz == 0 ? -1.0 : 0.5;
+    const double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
+                 Az = psi_c<double>(cz, u2, u2 * u2);
+    const F u0f = F(u0), u1f = F(u1), u2f = F(u2);
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      pe_yz[a] = psi_c<RT>(cy, u1, u1 * u1 + zb[a]) * psi_c<RT>(cz, u2, u2 * u2 + zb[a]);
-      ps_yz[a] = psi_c<RT>(cy, xs[a][1], xs[a][1] * xs[a][1] + zb[a]) *
-                 psi_c<RT>(cz, xs[a][2], xs[a][2] * xs[a][2] + zb[a]);
+      const double z = zb[a];
+      const double ex = Ax + Bx * z, ey = Ay + By * z, ez = Az + Bz * z;
+      phe[a] = ex * ey * ez;
+      const F dx = psi_diff<F>(cx, u0f, dv[a][0]), dy = psi_diff<F>(cy, u1f, dv[a][1]),
+              dz = psi_diff<F>(cz, u2f, dv[a][2]);
+      const F exf = F(ex), eyf = F(ey), ezf = F(ez);
+      const F sx = exf - dx, sy = eyf - dy;
+      dd[a] = tbw[a] * (dx * eyf * ezf + sx * dy * ezf + sx * sy * dz);
     }
-    const RT gyz = gA0 + fcy * gA1[1] + fcz * gA1[2] + fcy * fcy * gA2[1] + fcz * fcz * gA2[2] +
-                   fcy * fcz * gA2[5];
-    static_for<3>([&](auto Kx) {
-      constexpr int kx = decltype(Kx)::value;
-      constexpr int cx = kx - 1;
-      const int i = kx + 3 * kyz;
-      const Src r = make_src(g, ax, ay, az, kx, ky, kz);
-      const RT wi = RT(w1(cx)) * wyz;
-      // mixture f (eq. f); A_i.X is added by the next pull
-      {
-        const RT f = pull_f<cx, ST, RT>(src + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-        const RT feq = fyz * psi_c<RT>(cx, u0, s0);
-        dst[((int64_t)(M - 1) * Q + i) * NPAD + pself] = ST((RT(1) - om) * f + om * feq);
-      }
-      // energy g; the q^corr part is added by the next pull
-      {
-        const RT gv = pull_g<cx, ST, RT>(src + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, RT(3) * wi);
-        RT acc = gyz;
-        if constexpr (cx != 0) acc += RT(cx) * gA1[0] + gA2[0] + RT(cx) * (fcy * gA2[3] + fcz * gA2[4]);
-        dst[((int64_t)M * Q + i) * NPAD + pself] = ST((RT(1) - om) * gv + wi * acc);
-      }
-      // species
-      RT phe[M], dd[M];
+    F Fa[M - 1];
 #pragma unroll
-      for (int a = 0; a < M; ++a) {
-        const RT pe = pe_yz[a] * psi_c<RT>(cx, u0, u0 * u0 + zb[a]);
-        const RT ps = ps_yz[a] * psi_c<RT>(cx, xs[a][0], xs[a][0] * xs[a][0] + zb[a]);
-        phe[a] = pe;
-        dd[a] = tbw[a] * (pe - ps);
+    for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a)
+#pragma unroll
+      for (int bb = a + 1; bb < M; ++bb) {
+        const int k = a * M - a * (a + 1) / 2 + (bb - a - 1);
+        F c;
+        if constexpr (sizeof(F) == 4) c = tb.invDpf[k]; else c = F(tb.invDp[k]);
+        Fa[a] += c * dd[bb];
+        if (bb < M - 1) Fa[bb] += c * dd[a];
       }
 #pragma unroll
-      for (int a = 0; a < M - 1; ++a) {
-        RT F = RT(0);
-#pragma unroll
-        for (int bb = 0; bb < M; ++bb) {
-          if (bb == a) continue;
-          if constexpr (sizeof(RT) == 4)
-            F += tb.invDf[a][bb] * dd[bb];
-          else
-            F += RT(tb.invD[a][bb]) * dd[bb];
-        }
-        const RT fa = RT(src[((int64_t)a * Q + i) * NPAD + r.ps]);
-        dst[((int64_t)a * Q + i) * NPAD + pself] = ST(omb[a] * fa + ca[a] * phe[a] + rcoef[a] * F);
-      }
-    });
+    for (int a = 0; a < M - 1; ++a) {
+      const double fa = (double)ld(src + ((int64_t)a * Q + i) * NPAD, r.ps);
+      st(dst + ((int64_t)a * Q + i) * NPAD, pself, ST(omb[a] * fa + ca[a] * phe[a] + double(rcoef[a] * Fa[a])));
+    }
   }
 }
 
@@ -753,11 +866,8 @@ __global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, int cur, doub
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const int64_t N = g.N;
   const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
-  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
-  const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
-  const AxisSrc az = axis_src(z, g.nz, g.per[2]);
   Macro<M> m;
-  node_moments<M, ST, RT>(g, static_cast<const ST *>(b.pop[cur]), cr, ax, ay, az, m);
+  node_moments<M, ST, RT>(g, static_cast<const ST *>(b.pop[cur]), cr, x, y, z, m);
   const Tables &tb = *b.tab;
   double Tn;
   node_temperature<M>(tb, m, b.T[n], Tn);
@@ -806,7 +916,7 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, cons
       out[((int64_t)M * Q + i) * nn + k] =
           (double)pull_g<cx, ST, RT>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w3);
       for (int a = 0; a < M - 1; ++a)
-        out[((int64_t)a * Q + i) * nn + k] = (double)pop[((int64_t)a * Q + i) * NPAD + r.ps];
+        out[((int64_t)a * Q + i) * nn + k] = (double)ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
     });
   }
   if (T_out) T_out[k] = b.T[n];

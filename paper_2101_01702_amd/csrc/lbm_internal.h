@@ -23,6 +23,8 @@ struct Tables {
   double cvcoef[MAXM][5];     // C_v,a(T) = sum_k cvcoef[k] T^k
   double invD[MAXM][MAXM];    // 1 / D_ab, zero on the diagonal
   float invDf[MAXM][MAXM];
+  double invDp[MAXM * (MAXM - 1) / 2];   // 1 / D_ab for a < b, row-major pairs
+  float invDpf[MAXM * (MAXM - 1) / 2];
   double conc_scale[MAXM];    // rho_ref / m_a: lattice density -> mol/cm^3
   double rdot_scale[MAXM];    // m_a dt_phys / rho_ref: mol/(cm^3 s) -> lattice density/step
   double lnA[MAXR], bexp[MAXR], Ta[MAXR], dnu[MAXR];
