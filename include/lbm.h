@@ -108,8 +108,11 @@ typedef struct {
   int32_t reserved;
 } lbm_desc;
 
-/* Bytes of device workspace the descriptor needs (populations x2 with a ghost
- * layer on open axes, temperature, side channel, tables, status word). */
+/* Bytes of device workspace the descriptor needs: populations x2 with a ghost
+ * layer on open axes, temperature, a side channel of node fields for the
+ * gradient stencils, the deferred corrections, a per-node collision record
+ * (15 + 2(M-1) FP64 words and 5M-1 storage words) written by the node-local
+ * kernel and read by the collide kernel, the constant tables and a status word. */
 lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 
 /* Validate the descriptor, copy it, and upload its tables into the caller's
@@ -133,7 +136,8 @@ lbm_status lbm_step(lbm_handle h, int32_t n_steps, void *stream);
 
 /* Same as lbm_step, then waits and returns the summed device time of each kernel
  * kind in ms_out[LBM_NUM_KERNELS] (HIP events around every launch). */
-#define LBM_NUM_KERNELS 4 /* 0 main step, 1 psi stencil, 2 correction stencil, 3 ghosts */
+#define LBM_NUM_KERNELS 5 /* 0 node-local part (moments, temperature, chemistry, Stefan-Maxwell),
+                             1 psi stencil, 2 correction stencil, 3 ghosts, 4 collide and stream */
 lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms_out);
 
 /* Macroscopic fields of the current (pre-collision) state into device FP64

@@ -126,42 +126,44 @@ __device__ __forceinline__ int nb_coord(int x, int c, int n, bool periodic) {
   return s < 0 ? 0 : (s >= n ? n - 1 : s);
 }
 
-template <typename RT>
+template <typename CT>
 struct Corr {
-  const RT *X;    // [3][N]
-  const RT *Cg;   // [3][N]
+  const CT *X;    // [3][N]
+  const CT *Cg;   // [3][N]
   int64_t N;
 };
 
-// pulled value of the mixture f along c = (CX, cy, cz) with the deferred A_i.X term
-template <int CX, typename ST, typename RT>
-__device__ __forceinline__ RT pull_f(const ST *__restrict__ base, const Src &r, const Corr<RT> &cr, int cy,
-                                     int cz) {
-  RT v = RT(ld(base, r.ps));
+// pulled value of the mixture f along c = (CX, cy, cz) with the deferred A_i.X term;
+// the corrections are held in the storage precision ST and added in FP64, the same
+// way in every kernel that pulls
+template <int CX, typename ST, typename CT>
+__device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src &r, const Corr<CT> &cr, int cy,
+                                         int cz) {
+  double v = double(ld(base, r.ps));
   if (r.ns >= 0) {
     const uint32_t ns = (uint32_t)r.ns;
     if constexpr (CX != 0) {
-      if (cy == 0 && cz == 0) v += RT(0.5 * CX) * ld(cr.X, ns);
+      if (cy == 0 && cz == 0) v += double(ST(0.5 * CX * double(ld(cr.X, ns))));
     } else {
-      if (cy != 0 && cz == 0) v += RT(0.5) * RT(cy) * ld(cr.X + cr.N, ns);
-      if (cy == 0 && cz != 0) v += RT(0.5) * RT(cz) * ld(cr.X + 2 * cr.N, ns);
+      if (cy != 0 && cz == 0) v += double(ST(0.5 * cy * double(ld(cr.X + cr.N, ns))));
+      if (cy == 0 && cz != 0) v += double(ST(0.5 * cz * double(ld(cr.X + 2 * cr.N, ns))));
     }
   }
   return v;
 }
 
 // pulled value of g with the deferred Fourier-correction flux 3 w_i c_i . Cg
-template <int CX, typename ST, typename RT>
-__device__ __forceinline__ RT pull_g(const ST *__restrict__ base, const Src &r, const Corr<RT> &cr, int cy,
-                                     int cz, RT w3) {
-  RT v = RT(ld(base, r.ps));
+template <int CX, typename ST, typename CT>
+__device__ __forceinline__ double pull_g(const ST *__restrict__ base, const Src &r, const Corr<CT> &cr, int cy,
+                                         int cz, double w3) {
+  double v = double(ld(base, r.ps));
   if (r.ns >= 0) {
     const uint32_t ns = (uint32_t)r.ns;
-    RT d = RT(0);
-    if constexpr (CX != 0) d += RT(CX) * ld(cr.Cg, ns);
-    if (cy != 0) d += RT(cy) * ld(cr.Cg + cr.N, ns);
-    if (cz != 0) d += RT(cz) * ld(cr.Cg + 2 * cr.N, ns);
-    v += w3 * d;
+    double d = 0.0;
+    if constexpr (CX != 0) d += CX * double(ld(cr.Cg, ns));
+    if (cy != 0) d += cy * double(ld(cr.Cg + cr.N, ns));
+    if (cz != 0) d += cz * double(ld(cr.Cg + 2 * cr.N, ns));
+    v += double(ST(w3 * d));
   }
   return v;
 }
@@ -194,8 +196,8 @@ struct Macro {
   double du0[M][3];              // u_a - u (right-hand side of eq. transform1)
 };
 
-template <int M, typename ST, typename RT>
-__device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict__ pop, const Corr<RT> &cr,
+template <int M, typename ST>
+__device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict__ pop, const Corr<ST> &cr,
                                              int x, int y, int z, Macro<M> &m) {
   const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
   const int64_t NPAD = g.NPAD;
@@ -208,16 +210,15 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
   for (int kyz = 0; kyz < 9; ++kyz) {
     const int ky = kyz % 3, kz = kyz / 3;
     const int cy = ky - 1, cz = kz - 1;
-    const RT wyz3 = RT(3.0 * w1(cy) * w1(cz));
+    const double wyz3 = 3.0 * w1(cy) * w1(cz);
     const RowSrc row = row_src(g, y, z, cy, cz);
     static_for<3>([&](auto Kx) {
       constexpr int kx = decltype(Kx)::value;
       constexpr int cx = kx - 1;
       const int i = kx + 3 * kyz;
       const Src r = src_from_row(g, row, ax, kx);
-      const double f = (double)pull_f<cx, ST, RT>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-      const double gg =
-          (double)pull_g<cx, ST, RT>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, RT(w1(cx)) * wyz3);
+      const double f = pull_f<cx, ST, ST>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
+      const double gg = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w1(cx) * wyz3);
       rho += f;
       rE += gg;
       if constexpr (cx != 0) {
@@ -315,43 +316,47 @@ struct StashLayout {
   static constexpr int U = RS + M;        // velocity [3]
   static constexpr int G = U + 3;         // g coefficients [10]: A0, A1[3], A2[6]
   static constexpr int RD = G + 10;       // production rates [M-1]
-  static constexpr int WORDS = RD + M - 1;
+  static constexpr int BETA = RD + M - 1; // relaxation parameters beta_a [M-1]
+  static constexpr int WORDS = BETA + M - 1;
 };
 constexpr int MAIN_BLOCK = 256;
+
+// The accesses are volatile: a thread reads back only its own words, and without it
+// the compiler forwards the stored values and keeps them in registers.
+struct Stash {
+  volatile double *p;   // &stash[tid]
+  __device__ __forceinline__ void w(int k, double v) const { p[k * MAIN_BLOCK] = v; }
+  __device__ __forceinline__ double r(int k) const { return p[k * MAIN_BLOCK]; }
+};
 
 // Precision of the inter-species term F of eq. fStar (a correction whose sum over
 // directions vanishes): FP64 for FP64 storage, FP32 for FP32 storage.
 template <typename ST>
 using FT = ST;
 
-template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(MAIN_BLOCK) void k_main(Geom g, Buffers b, int cur) {
+// coefficients of the collision of one node
+template <int M, typename F>
+struct CollCoef {
+  double u0, u1, u2, rho, zeta;
+  double gA0, gA1[3], gA2[6];
+  double zb[M];
+  F dv[M][3], tbw[M];
+  double omb[M - 1], ca[M - 1];
+  F rcoef[M - 1];
+};
+
+// O2-O5 and the collision coefficients of one node from its moments: temperature,
+// side channel, g coefficients, production rates, Stefan-Maxwell solve.
+template <int M, typename RT, typename F>
+__device__ __forceinline__ void node_islands(const Tables &tb, const Buffers &b, int64_t n, int64_t N,
+                                             const Macro<M> &m, const Stash &sh, CollCoef<M, F> &cc) {
   using SL = StashLayout<M>;
-  __shared__ double stash[SL::WORDS * MAIN_BLOCK];
-  const int tid = threadIdx.x;
-  auto st_w = [&](int w, double v) { stash[w * MAIN_BLOCK + tid] = v; };
-  auto st_r = [&](int w) { return stash[w * MAIN_BLOCK + tid]; };
-
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.N) return;
-  const Tables &tb = *b.tab;
-  const int x = (int)(n % g.nx);
-  const int y = (int)((n / g.nx) % g.ny);
-  const int z = (int)(n / ((int64_t)g.nx * g.ny));
-  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
-  ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
-  const int64_t N = g.N, NPAD = g.NPAD;
-  const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
-
   uint32_t anom = 0;
-  double rho, T, zeta;
+  const double rho = m.rho;
+  double T, zeta;
   double du[M][3];   // right-hand side u_a - u of eq. transform1, then its solution
   {
-    // O1: moments of the pulled state
-    Macro<M> m;
-    node_moments<M, ST, RT>(g, src, cr, x, y, z, m);
-    if (!(m.rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
-    rho = m.rho;
+    if (!(rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
     const double inv_rho = 1.0 / rho;
 #pragma unroll
     for (int a = 0; a < M; ++a)
@@ -411,17 +416,17 @@ __global__ __launch_bounds__(MAIN_BLOCK) void k_main(Geom g, Buffers b, int cur)
       const double om_d = tb.omega, om1 = tb.omega1;
       const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
       const double trR = Req[0] + Req[1] + Req[2];
-      st_w(SL::G + 0, om_d * (2.5 * m.rhoE - 1.5 * trR));
+      sh.w(SL::G + 0, om_d * (2.5 * m.rhoE - 1.5 * trR));
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double uP = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) uP += u[c] * (m.P6[sym[c][d]] - Peq[sym[c][d]]);
-        st_w(SL::G + 1 + d, om_d * 3.0 * qeq[d] + 3.0 * (om_d - om1) * (m.q[d] - uP - qeq[d]));
+        sh.w(SL::G + 1 + d, om_d * 3.0 * qeq[d] + 3.0 * (om_d - om1) * (m.q[d] - uP - qeq[d]));
       }
 #pragma unroll
       for (int k = 0; k < 6; ++k)
-        st_w(SL::G + 4 + k, om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal twice
+        sh.w(SL::G + 4 + k, om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal twice
     }
 
     // O3: production rates (mass action, K_c from the NASA-7 Gibbs function)
@@ -457,31 +462,42 @@ __global__ __launch_bounds__(MAIN_BLOCK) void k_main(Geom g, Buffers b, int cur)
         for (int a = 0; a < M; ++a) wd[a] += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * qk;
       }
 #pragma unroll
-      for (int a = 0; a < M - 1; ++a) st_w(SL::RD + a, tb.rdot_scale[a] * wd[a]);
+      for (int a = 0; a < M - 1; ++a) sh.w(SL::RD + a, tb.rdot_scale[a] * wd[a]);
     }
 #pragma unroll
-    for (int a = 0; a < M; ++a) st_w(SL::RS + a, m.rs[a]);
+    for (int a = 0; a < M; ++a) sh.w(SL::RS + a, m.rs[a]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) st_w(SL::U + d, m.u[d]);
+    for (int d = 0; d < 3; ++d) sh.w(SL::U + d, m.u[d]);
   }
 
   // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1),
-  // Gaussian elimination on the row-diagonally dominant matrix
+  // Gaussian elimination on the row-diagonally dominant matrix.  1/tau_ab =
+  // (R_a T)(R_b T) / ((R T) D_ab) is symmetric: built from the pair table.
   const double inv_rho = 1.0 / rho, inv_zeta = 1.0 / zeta;
   {
-    double A[M][M];
+    double A[M][M], Yb[M], zl[M], it[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      const double za = tb.Ra[a] * T;
-      double it = 0.0;
+      Yb[a] = sh.r(SL::RS + a) * inv_rho;
+      zl[a] = tb.Ra[a] * T;
+      it[a] = 0.0;
+    }
 #pragma unroll
-      for (int bb = 0; bb < M; ++bb) {
-        const double Yb = st_r(SL::RS + bb) * inv_rho;
-        const double K = za * (tb.Ra[bb] * T) * tb.invD[a][bb] * inv_zeta;
-        it += Yb * K;
-        A[a][bb] = -0.5 * K * Yb;
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int bb = a + 1; bb < M; ++bb) {
+        const int k = a * M - a * (a + 1) / 2 + (bb - a - 1);
+        const double K = zl[a] * zl[bb] * tb.invDp[k] * inv_zeta;
+        A[a][bb] = -0.5 * K * Yb[bb];
+        A[bb][a] = -0.5 * K * Yb[a];
+        it[a] += Yb[bb] * K;
+        it[bb] += Yb[a] * K;
       }
-      A[a][a] = 1.0 + 0.5 * it;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      A[a][a] = 1.0 + 0.5 * it[a];
+      // beta_a = dt / (2 tau_a + dt) with 1/tau_a = sum_b Y_b / tau_ab (eq. fStar, tauab)
+      if (a < M - 1) sh.w(SL::BETA + a, it[a] / (it[a] + 2.0));
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -509,135 +525,255 @@ __global__ __launch_bounds__(MAIN_BLOCK) void k_main(Geom g, Buffers b, int cur)
   }
 
   // O7: collision coefficients
-  using F = FT<ST>;
-  const double u0 = st_r(SL::U + 0), u1 = st_r(SL::U + 1), u2 = st_r(SL::U + 2);
-  const double om = tb.omega;
-  double gA0, gA1[3], gA2[6];
+  cc.u0 = sh.r(SL::U + 0);
+  cc.u1 = sh.r(SL::U + 1);
+  cc.u2 = sh.r(SL::U + 2);
+  cc.rho = rho;
+  cc.zeta = zeta;
   {
     const double invT = 1.0 / T;
     double hyd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
       const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
-      const double HY = Ha * st_r(SL::RS + a) * inv_rho;
+      const double HY = Ha * sh.r(SL::RS + a) * inv_rho;
 #pragma unroll
       for (int d = 0; d < 3; ++d) hyd[d] += HY * du[a][d];
     }
-    gA0 = st_r(SL::G + 0);
+    cc.gA0 = sh.r(SL::G + 0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) gA1[d] = st_r(SL::G + 1 + d) + 3.0 * tb.omega1 * rho * hyd[d];
+    for (int d = 0; d < 3; ++d) cc.gA1[d] = sh.r(SL::G + 1 + d) + 3.0 * tb.omega1 * rho * hyd[d];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gA2[k] = st_r(SL::G + 4 + k);
+    for (int k = 0; k < 6; ++k) cc.gA2[k] = sh.r(SL::G + 4 + k);
   }
   // species a < M-1 (eq. finalNumericalEquations with F_ai of eq. fStar):
   // f_ai' = (1 - 2 beta_a) f_ai + (2 beta_a rho_a + rho_dot_a) Phi_a(u)
   //         + (beta_a - 1) (Y_a zeta_a / zeta) sum_b invD_ab rho_b zeta_b (Phi_b(u) - Phi_b(u + du_b))
   // with Phi_b(v) the unit-density product form at zeta_b (eqs. feq, fstar, fsource)
-  double zb[M];
-  F dv[M][3], tbw[M];
-  double omb[M - 1], ca[M - 1];
-  F rcoef[M - 1];
 #pragma unroll
   for (int a = 0; a < M; ++a) {
     const double za = tb.Ra[a] * T;
-    const double ra = st_r(SL::RS + a);
-    zb[a] = za;
-    tbw[a] = F(ra * za);
-    dv[a][0] = F(du[a][0]);
-    dv[a][1] = F(du[a][1]);
-    dv[a][2] = F(du[a][2]);
+    const double ra = sh.r(SL::RS + a);
+    cc.zb[a] = za;
+    cc.tbw[a] = F(ra * za);
+    cc.dv[a][0] = F(du[a][0]);
+    cc.dv[a][1] = F(du[a][1]);
+    cc.dv[a][2] = F(du[a][2]);
     if (a < M - 1) {
-      // beta_a = dt / (2 tau_a + dt) with 1/tau_a = sum_b Y_b / tau_ab (eq. fStar, tauab)
-      double it = 0.0;
-#pragma unroll
-      for (int bb = 0; bb < M; ++bb) it += st_r(SL::RS + bb) * inv_rho * (tb.Ra[bb] * T) * tb.invD[a][bb];
-      it *= za * inv_zeta;
-      const double bt = it / (it + 2.0);
-      omb[a] = 1.0 - 2.0 * bt;
-      ca[a] = 2.0 * bt * ra + st_r(SL::RD + a);
-      rcoef[a] = F((bt - 1.0) * ra * inv_rho * za * inv_zeta);
+      const double bt = sh.r(SL::BETA + a);
+      cc.omb[a] = 1.0 - 2.0 * bt;
+      cc.ca[a] = 2.0 * bt * ra + sh.r(SL::RD + a);
+      cc.rcoef[a] = F((bt - 1.0) * ra * inv_rho * za * inv_zeta);
     }
   }
+}
 
-  // O7 + store: second pass over the pulled populations
+// O7 for one direction: f, g and the species a < M-1; fa(a) returns the pulled
+// species population, store(set, value) writes the post-collision population
+template <int M, typename F, typename FaFn, typename StFn>
+__device__ __forceinline__ void collide_dir(const Tables &tb, const CollCoef<M, F> &cc, int cx, int cy, int cz,
+                                            double f, double gv, FaFn &&fa, StFn &&store) {
+  const double om = tb.omega;
+  const double fcx = cx, fcy = cy, fcz = cz;
+  const double wi = w1(cx) * w1(cy) * w1(cz);
+  const double u0 = cc.u0, u1 = cc.u1, u2 = cc.u2;
+  // mixture f (eq. f); A_i.X is added by the next pull
+  {
+    const double feq = cc.rho * psi_c<double>(cx, u0, u0 * u0 + cc.zeta) * psi_c<double>(cy, u1, u1 * u1 + cc.zeta) *
+                       psi_c<double>(cz, u2, u2 * u2 + cc.zeta);
+    store(M - 1, (1.0 - om) * f + om * feq);
+  }
+  // energy g; the q^corr part is added by the next pull
+  {
+    const double acc = cc.gA0 + fcx * cc.gA1[0] + fcy * cc.gA1[1] + fcz * cc.gA1[2] + fcx * fcx * cc.gA2[0] +
+                       fcy * fcy * cc.gA2[1] + fcz * fcz * cc.gA2[2] + fcx * fcy * cc.gA2[3] + fcx * fcz * cc.gA2[4] +
+                       fcy * fcz * cc.gA2[5];
+    store(M, (1.0 - om) * gv + wi * acc);
+  }
+  // species: Phi_b(u) - Phi_b(u + du_b) by telescoping the three axis factors, each
+  // factor difference in closed form, so the difference keeps relative precision.
+  // Axis factor of species b: Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.
+  double phe[M];
+  F dd[M];
+  const double Bx = cx == 0 ? -1.0 : 0.5, By = cy == 0 ? -1.0 : 0.5, Bz = cz == 0 ? -1.0 : 0.5;
+  const double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
+               Az = psi_c<double>(cz, u2, u2 * u2);
+  const F u0f = F(u0), u1f = F(u1), u2f = F(u2);
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double z = cc.zb[a];
+    const double ex = Ax + Bx * z, ey = Ay + By * z, ez = Az + Bz * z;
+    phe[a] = ex * ey * ez;
+    const F dx = psi_diff<F>(cx, u0f, cc.dv[a][0]), dy = psi_diff<F>(cy, u1f, cc.dv[a][1]),
+            dz = psi_diff<F>(cz, u2f, cc.dv[a][2]);
+    const F exf = F(ex), eyf = F(ey), ezf = F(ez);
+    const F sx = exf - dx, sy = eyf - dy;
+    dd[a] = cc.tbw[a] * (dx * eyf * ezf + sx * dy * ezf + sx * sy * dz);
+  }
+  F Fa[M - 1];
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a)
+#pragma unroll
+    for (int bb = a + 1; bb < M; ++bb) {
+      const int k = a * M - a * (a + 1) / 2 + (bb - a - 1);
+      F c;
+      if constexpr (sizeof(F) == 4) c = tb.invDpf[k]; else c = F(tb.invDp[k]);
+      Fa[a] += c * dd[bb];
+      if (bb < M - 1) Fa[bb] += c * dd[a];
+    }
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) store(a, cc.omb[a] * fa(a) + cc.ca[a] * phe[a] + double(cc.rcoef[a] * Fa[a]));
+}
+
+// ---- per-node collision record (written by k_islands, read by k_collide) ---------
+// SoA, N entries per word.  FP64 words keep the zeroth moments exact: rho, u, R T and
+// the g coefficients that enter sum_i g_i', and (1 - 2 beta_a), (2 beta_a rho_a +
+// rho_dot_a); the remaining words are in the precision F of the inter-species term.
+template <int M>
+struct RecLayout {
+  static constexpr int RHO = 0, U = 1, ZETA = 4, GA0 = 5, GA1 = 6, GA2 = 9, OMB = 15, CA = OMB + M - 1;
+  static constexpr int DWORDS = CA + M - 1;
+  static constexpr int DV = 0, TBW = 3 * M, RC = 4 * M;
+  static constexpr int FWORDS = RC + M - 1;
+};
+
+template <int M, typename F>
+__device__ __forceinline__ void store_record(const Buffers &b, int64_t n, int64_t N, const CollCoef<M, F> &cc) {
+  using RL = RecLayout<M>;
+  double *rd = static_cast<double *>(b.rec_d);
+  F *rf = static_cast<F *>(b.rec_f);
+  rd[RL::RHO * N + n] = cc.rho;
+  rd[(RL::U + 0) * N + n] = cc.u0;
+  rd[(RL::U + 1) * N + n] = cc.u1;
+  rd[(RL::U + 2) * N + n] = cc.u2;
+  rd[RL::ZETA * N + n] = cc.zeta;
+  rd[RL::GA0 * N + n] = cc.gA0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) rd[(RL::GA1 + d) * N + n] = cc.gA1[d];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) rd[(RL::GA2 + k) * N + n] = cc.gA2[k];
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    rd[(RL::OMB + a) * N + n] = cc.omb[a];
+    rd[(RL::CA + a) * N + n] = cc.ca[a];
+    rf[(RL::RC + a) * N + n] = cc.rcoef[a];
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rf[(RL::DV + 3 * a + d) * N + n] = cc.dv[a][d];
+    rf[(RL::TBW + a) * N + n] = cc.tbw[a];
+  }
+}
+
+template <int M, typename F>
+__device__ __forceinline__ void load_record(const Tables &tb, const Buffers &b, int64_t n, int64_t N,
+                                            CollCoef<M, F> &cc) {
+  using RL = RecLayout<M>;
+  const double *rd = static_cast<const double *>(b.rec_d);
+  const F *rf = static_cast<const F *>(b.rec_f);
+  const uint32_t i = (uint32_t)n;
+  cc.rho = ld(rd + RL::RHO * N, i);
+  cc.u0 = ld(rd + (RL::U + 0) * N, i);
+  cc.u1 = ld(rd + (RL::U + 1) * N, i);
+  cc.u2 = ld(rd + (RL::U + 2) * N, i);
+  cc.zeta = ld(rd + RL::ZETA * N, i);
+  cc.gA0 = ld(rd + RL::GA0 * N, i);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cc.gA1[d] = ld(rd + (RL::GA1 + d) * N, i);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) cc.gA2[k] = ld(rd + (RL::GA2 + k) * N, i);
+  const double T = ld(b.T, i);
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    cc.omb[a] = ld(rd + (RL::OMB + a) * N, i);
+    cc.ca[a] = ld(rd + (RL::CA + a) * N, i);
+    cc.rcoef[a] = ld(rf + (RL::RC + a) * N, i);
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    cc.zb[a] = tb.Ra[a] * T;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cc.dv[a][d] = ld(rf + (RL::DV + 3 * a + d) * N, i);
+    cc.tbw[a] = ld(rf + (RL::TBW + a) * N, i);
+  }
+}
+
+// Step, part 1: moments of the pulled state and everything of the collision that is
+// local to the node (temperature, production rates, Stefan-Maxwell solve).
+template <int M, typename ST>
+__global__ __launch_bounds__(MAIN_BLOCK) void k_islands(Geom g, Buffers b, int cur) {
+  using SL = StashLayout<M>;
+  using F = FT<ST>;
+  __shared__ double stash[SL::WORDS * MAIN_BLOCK];
+  const Stash sh{&stash[threadIdx.x]};
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const Tables &tb = *b.tab;
+  const int x = (int)(n % g.nx);
+  const int y = (int)((n / g.nx) % g.ny);
+  const int z = (int)(n / ((int64_t)g.nx * g.ny));
+  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
+  const int64_t N = g.N;
+  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
+  CollCoef<M, F> cc;
+  {
+    Macro<M> m;
+    node_moments<M, ST>(g, src, cr, x, y, z, m);
+    node_islands<M, double, F>(tb, b, n, N, m, sh, cc);
+  }
+  store_record<M, F>(b, n, N, cc);
+}
+
+// Step, part 2: one streaming pass, each population pulled, collided and stored.
+template <int M, typename ST>
+__global__ __launch_bounds__(MAIN_BLOCK) void k_collide(Geom g, Buffers b, int cur) {
+  using F = FT<ST>;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const Tables &tb = *b.tab;
+  const int x = (int)(n % g.nx);
+  const int y = (int)((n / g.nx) % g.ny);
+  const int z = (int)(n / ((int64_t)g.nx * g.ny));
+  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
+  ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
+  const int64_t N = g.N, NPAD = g.NPAD;
+  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
+  CollCoef<M, F> cc;
+  load_record<M, F>(tb, b, n, N, cc);
   const uint32_t pself = ((uint32_t)(z + g.pz) * (uint32_t)g.NY + (uint32_t)(y + g.py)) * (uint32_t)g.NX +
                          (uint32_t)(x + g.px);
-  const double s0 = u0 * u0 + zeta;
 #pragma unroll 1
   for (int i = 0; i < 27; ++i) {
     const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-    const double fcx = cx, fcy = cy, fcz = cz;
-    const double wi = w1(cx) * w1(cy) * w1(cz);
+    const RowSrc row = row_src(g, y, z, cy, cz);
     Src r;
     {
-      int sx = x - cx, sy = y - cy, sz = z - cz;
+      int sx = x - cx;
       if (g.per[0]) sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
-      if (g.per[1]) sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
-      if (g.per[2]) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
-      const bool out = sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz;
-      r.ps = ((uint32_t)(sz + g.pz) * (uint32_t)g.NY + (uint32_t)(sy + g.py)) * (uint32_t)g.NX + (uint32_t)(sx + g.px);
-      r.ns = out ? -1 : (sz * g.ny + sy) * g.nx + sx;
+      const bool outx = sx < 0 || sx >= g.nx;
+      r.ps = row.prow + (uint32_t)(sx + g.px);
+      r.ns = (row.nrow < 0 || outx) ? -1 : row.nrow + sx;
     }
-    // mixture f (eq. f); A_i.X is added by the next pull
-    {
-      double f = (double)ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, r.ps);
-      if (r.ns >= 0 && (cx * cx + cy * cy + cz * cz) == 1) {
-        const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
-        f += 0.5 * double(cx + cy + cz) * (double)ld(cr.X + axis * N, (uint32_t)r.ns);
-      }
-      const double feq = rho * psi_c<double>(cx, u0, s0) * psi_c<double>(cy, u1, u1 * u1 + zeta) *
-                         psi_c<double>(cz, u2, u2 * u2 + zeta);
-      st(dst + ((int64_t)(M - 1) * Q + i) * NPAD, pself, ST((1.0 - om) * f + om * feq));
+    double f = (double)ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, r.ps);
+    if (r.ns >= 0 && (cx * cx + cy * cy + cz * cz) == 1) {
+      const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
+      f += double(ST(0.5 * double(cx + cy + cz) * double(ld(cr.X + axis * N, (uint32_t)r.ns))));
     }
-    // energy g; the q^corr part is added by the next pull
-    {
-      double gv = (double)ld(src + ((int64_t)M * Q + i) * NPAD, r.ps);
-      if (r.ns >= 0) {
-        const uint32_t ns = (uint32_t)r.ns;
-        gv += 3.0 * wi * (fcx * (double)ld(cr.Cg, ns) + fcy * (double)ld(cr.Cg + N, ns) + fcz * (double)ld(cr.Cg + 2 * N, ns));
-      }
-      const double acc = gA0 + fcx * gA1[0] + fcy * gA1[1] + fcz * gA1[2] + fcx * fcx * gA2[0] + fcy * fcy * gA2[1] +
-                         fcz * fcz * gA2[2] + fcx * fcy * gA2[3] + fcx * fcz * gA2[4] + fcy * fcz * gA2[5];
-      st(dst + ((int64_t)M * Q + i) * NPAD, pself, ST((1.0 - om) * gv + wi * acc));
+    double gv = (double)ld(src + ((int64_t)M * Q + i) * NPAD, r.ps);
+    if (r.ns >= 0) {
+      const uint32_t ns = (uint32_t)r.ns;
+      double d = 0.0;
+      if (cx != 0) d += cx * double(ld(cr.Cg, ns));
+      if (cy != 0) d += cy * double(ld(cr.Cg + N, ns));
+      if (cz != 0) d += cz * double(ld(cr.Cg + 2 * N, ns));
+      gv += double(ST(3.0 * (w1(cx) * w1(cy) * w1(cz)) * d));
     }
-    // species: Phi_b(u) - Phi_b(u + du_b) by telescoping the three axis factors, each
-    // factor difference in closed form, so the difference keeps relative precision.
-    // Axis factor of species b: Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.
-    double phe[M];
-    F dd[M];
-    const double Bx = cx == 0 ? -1.0 : 0.5, By = cy == 0 ? -1.0 : 0.5, Bz = cz == 0 ? -1.0 : 0.5;
-    const double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
-                 Az = psi_c<double>(cz, u2, u2 * u2);
-    const F u0f = F(u0), u1f = F(u1), u2f = F(u2);
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-      const double z = zb[a];
-      const double ex = Ax + Bx * z, ey = Ay + By * z, ez = Az + Bz * z;
-      phe[a] = ex * ey * ez;
-      const F dx = psi_diff<F>(cx, u0f, dv[a][0]), dy = psi_diff<F>(cy, u1f, dv[a][1]),
-              dz = psi_diff<F>(cz, u2f, dv[a][2]);
-      const F exf = F(ex), eyf = F(ey), ezf = F(ez);
-      const F sx = exf - dx, sy = eyf - dy;
-      dd[a] = tbw[a] * (dx * eyf * ezf + sx * dy * ezf + sx * sy * dz);
-    }
-    F Fa[M - 1];
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a)
-#pragma unroll
-      for (int bb = a + 1; bb < M; ++bb) {
-        const int k = a * M - a * (a + 1) / 2 + (bb - a - 1);
-        F c;
-        if constexpr (sizeof(F) == 4) c = tb.invDpf[k]; else c = F(tb.invDp[k]);
-        Fa[a] += c * dd[bb];
-        if (bb < M - 1) Fa[bb] += c * dd[a];
-      }
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a) {
-      const double fa = (double)ld(src + ((int64_t)a * Q + i) * NPAD, r.ps);
-      st(dst + ((int64_t)a * Q + i) * NPAD, pself, ST(omb[a] * fa + ca[a] * phe[a] + double(rcoef[a] * Fa[a])));
-    }
+    collide_dir<M, F>(
+        tb, cc, cx, cy, cz, f, gv, [&](int a) { return (double)ld(src + ((int64_t)a * Q + i) * NPAD, r.ps); },
+        [&](int set, double v) { st(dst + ((int64_t)set * Q + i) * NPAD, pself, ST(v)); });
   }
 }
 
@@ -673,7 +809,7 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
 }
 
 // ---- X_alpha = -d_alpha psi_alpha; Cg = sum_a w_a grad Y_a ---------------------------
-template <int M, typename RT>
+template <int M, typename RT, typename CT>
 __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
@@ -710,11 +846,11 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
       if constexpr (cz != 0) C[2] += (cz * w) * hy;
     }
   });
-  RT *corr = static_cast<RT *>(b.corr);
+  CT *corr = static_cast<CT *>(b.corr);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    corr[d * N + n] = X[d];
-    corr[(3 + d) * N + n] = C[d];
+    corr[d * N + n] = CT(X[d]);
+    corr[(3 + d) * N + n] = CT(C[d]);
   }
 }
 
@@ -865,9 +1001,9 @@ __global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, int cur, doub
   if (n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const int64_t N = g.N;
-  const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
+  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
   Macro<M> m;
-  node_moments<M, ST, RT>(g, static_cast<const ST *>(b.pop[cur]), cr, x, y, z, m);
+  node_moments<M, ST>(g, static_cast<const ST *>(b.pop[cur]), cr, x, y, z, m);
   const Tables &tb = *b.tab;
   double Tn;
   node_temperature<M>(tb, m, b.T[n], Tn);
@@ -898,7 +1034,7 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, cons
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const int64_t N = g.N, NPAD = g.NPAD;
   const ST *pop = static_cast<const ST *>(b.pop[cur]);
-  const Corr<RT> cr{static_cast<const RT *>(b.corr), static_cast<const RT *>(b.corr) + 3 * N, N};
+  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
   const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
   const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
   const AxisSrc az = axis_src(z, g.nz, g.per[2]);
@@ -910,11 +1046,10 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, cons
       constexpr int cx = kx - 1;
       const int i = kx + 3 * kyz;
       const Src r = make_src(g, ax, ay, az, kx, ky, kz);
-      const RT w3 = RT(3.0 * w1(cx) * w1(cy) * w1(cz));
+      const double w3 = 3.0 * w1(cx) * w1(cy) * w1(cz);
       out[((int64_t)(M - 1) * Q + i) * nn + k] =
-          (double)pull_f<cx, ST, RT>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-      out[((int64_t)M * Q + i) * nn + k] =
-          (double)pull_g<cx, ST, RT>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w3);
+          pull_f<cx, ST, ST>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
+      out[((int64_t)M * Q + i) * nn + k] = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w3);
       for (int a = 0; a < M - 1; ++a)
         out[((int64_t)a * Q + i) * nn + k] = (double)ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
     });
@@ -945,16 +1080,23 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 }
 
 template <int M, typename ST, typename RT>
-struct RunMain {
+struct RunIslands {
   static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_main<M, ST, RT>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b, cur);
+    hipLaunchKernelGGL((k_islands<M, ST>), dim3(blocks_for(g.N, MAIN_BLOCK)), dim3(MAIN_BLOCK), 0, st, g, b, cur);
+    return hipGetLastError();
+  }
+};
+template <int M, typename ST, typename RT>
+struct RunCollide {
+  static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
+    hipLaunchKernelGGL((k_collide<M, ST>), dim3(blocks_for(g.N, MAIN_BLOCK)), dim3(MAIN_BLOCK), 0, st, g, b, cur);
     return hipGetLastError();
   }
 };
 template <int M, typename ST, typename RT>
 struct RunCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
-    hipLaunchKernelGGL((k_corr<M, RT>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    hipLaunchKernelGGL((k_corr<M, RT, ST>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
     return hipGetLastError();
   }
 };
@@ -998,8 +1140,12 @@ struct RunExport {
 
 }  // namespace
 
-hipError_t launch_main(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
-  return dispatch<RunMain>(g.M, store, g, b, cur, st);
+hipError_t launch_islands(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
+  return dispatch<RunIslands>(g.M, store, g, b, cur, st);
+}
+
+hipError_t launch_collide(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
+  return dispatch<RunCollide>(g.M, store, g, b, cur, st);
 }
 
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {

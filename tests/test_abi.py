@@ -57,9 +57,13 @@ def test_workspace_size_config1(lib):
     d, keep = _desc(prob)
     st, n, _ = _ws(lib, d)
     assert st == 0
-    S, N = 4, 512
+    S, N, M = 4, 512, 3
     pops = 2 * S * 27 * N * 8
-    assert pops < n < pops + 200_000
+    # beyond the two population copies: temperature, side channel (2M + 7 words),
+    # psi (3), corrections (6), collision record (15 + 2(M-1) + 5M-1) words per node,
+    # plus the constant tables
+    per_node = 8 * (1 + 2 * M + 7 + 3 + 6 + 15 + 2 * (M - 1) + 5 * M - 1)
+    assert pops + per_node * N < n < pops + per_node * N + 200_000
 
 
 def test_workspace_grows_with_ghost_layer(lib):
