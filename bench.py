@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "reactive MLUPS & % of HBM peak at stated error vs FP64; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_main_sphere3d_256.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_collide_sphere3d_256.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01702_amd", "csrc", "lbm_device.hip")
 
 
@@ -31,14 +31,14 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the main kernel from committed rocprofv3 counters, or
-    None when the kernel source changed since they were taken."""
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counters, or None
+    when they cover another kernel or the kernel source changed since."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha") != kernel_source_sha():
+    if rec.get("kernel") != kernel or rec.get("kernel_source_sha") != kernel_source_sha():
         return None
     return rec
 
@@ -156,7 +156,7 @@ def main():
     dominant = max(kernel_ms, key=kernel_ms.get)
     dom_ms = kernel_ms[dominant] / args.steps
     achieved = alg_bytes_node * N / (dom_ms * 1e-3) / 1e9
-    rec = recorded_traffic()
+    rec = recorded_traffic(f"k_{dominant}")
     traffic = rec["traffic_bytes_per_launch"] if (rec and args.n == 256 and storage == W.STORE_F32) else None
     roofline = {"bound": "hbm", "kernel": f"k_{dominant}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
