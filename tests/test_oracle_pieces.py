@@ -4,6 +4,7 @@ Each test checks an identity, closed form or invariant stated or implied by the
 paper; none re-types the oracle's formula.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -11,6 +12,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2101_01702_amd import workloads as W
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 C = np.array([[i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1] for i in range(27)], dtype=np.float64)
 
 
@@ -60,12 +62,21 @@ def test_grad_form_moments(oracle_lib, seed):
     np.testing.assert_allclose(m2, Rt, rtol=0, atol=1e-14 * scale)
 
 
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
 def test_grad_weights_are_d3q27(oracle_lib):
-    """The weights are the products of w0 = 2/3, w1 = 1/6 (8/27, 2/27, 1/54, 1/216)."""
+    """The weights are the products of the paper's one-dimensional weights
+    (tests/golden/d3q27_weights.txt: 8/27, 2/27, 1/54, 1/216 by |c|^2)."""
     g = orc.grad_form(1.0, np.zeros(3), np.eye(3) / 3.0)   # R = rhoE theta I: only the weight remains
-    expect = {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}
-    for i in range(27):
-        assert g[i] == pytest.approx(expect[int(np.abs(C[i]).sum())], rel=1e-15)
+    rows = _golden("d3q27_weights.txt")
+    assert len(rows) == 27
+    for i, cx, cy, cz, num, den in rows:
+        i = int(i)
+        assert (int(cx), int(cy), int(cz)) == tuple(C[i].astype(int))
+        assert g[i] == pytest.approx(int(num) / int(den), rel=1e-15)
 
 
 # --- thermodynamics (eq. specHa, Umix) ---------------------------------------------------
@@ -96,13 +107,16 @@ def test_nasa7_enthalpy_is_integral_of_cp(oracle_lib, a):
 def test_formation_enthalpy_and_entropy_at_reference(oracle_lib):
     """The thermo data reproduce the formation enthalpy and entropy they were built
     from at T0 = 298.15 K (Sec. 4 reference state)."""
+    ref = {k: float(v) for k, v in _golden("standard_state.txt")}
+    T0 = ref["T0_K"]
+    assert W.T_REF == T0 and W.P_ATM == ref["P0_Pa"]
     mech = W.abc_mechanism(h_f=(0.0, 1.0e4, -5.0e4), s0=(150.0, 200.0, 250.0), cp=(2.5, 3.5, 4.5))
     prob = W.config1()
     prob.mech = mech
     sim = orc.OracleSim(prob)
     for a, (hf, s0) in enumerate([(0.0, 150.0), (1.0e4, 200.0), (-5.0e4, 250.0)]):
-        t = sim.thermo(a, W.T_REF)
-        assert t["h_RT"] * W.R_U * W.T_REF == pytest.approx(hf, abs=1e-6)
+        t = sim.thermo(a, T0)
+        assert t["h_RT"] * W.R_U * T0 == pytest.approx(hf, abs=1e-6)
         assert t["s_R"] * W.R_U == pytest.approx(s0, rel=1e-13)
 
 
