@@ -149,18 +149,21 @@ def main():
 
     mlups = N * args.steps / wall / 1e6
     ms_per_step = wall * 1e3 / args.steps
-    # Algorithmic bytes per node: every population of the M+1 sets read once and
-    # written once.  The dominant kernel (collide-and-stream) moves exactly these
-    # bytes; its per-node collision record and deferred corrections are overhead.
+    # Algorithmic bytes per node of the step: every population of the M+1 sets read
+    # once and written once.  Per kernel: the collide-and-stream kernel moves exactly
+    # these; the node-local kernel has to read the populations once; the stencil and
+    # ghost kernels move no population of the method (their bytes are overhead).
     alg_bytes_node = 2 * 27 * (M + 1) * word
+    kernel_alg_bytes = {"collide": alg_bytes_node, "islands": 27 * (M + 1) * word}
     dominant = max(kernel_ms, key=kernel_ms.get)
     dom_ms = kernel_ms[dominant] / args.steps
-    achieved = alg_bytes_node * N / (dom_ms * 1e-3) / 1e9
+    dom_bytes = kernel_alg_bytes.get(dominant, 0)
+    achieved = dom_bytes * N / (dom_ms * 1e-3) / 1e9
     rec = recorded_traffic(f"k_{dominant}")
     traffic = rec["traffic_bytes_per_launch"] if (rec and args.n == 256 and storage == W.STORE_F32) else None
     roofline = {"bound": "hbm", "kernel": f"k_{dominant}", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_node": alg_bytes_node}
+                "alg_bytes_per_node": dom_bytes}
 
     out = {
         "metric": METRIC,

@@ -111,7 +111,7 @@ typedef struct {
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost
  * layer on open axes, temperature, a side channel of node fields for the
  * gradient stencils, the deferred corrections, a per-node collision record
- * (15 + 2(M-1) FP64 words and 5M-1 storage words) written by the node-local
+ * (15 + (M-1) FP64 words and 6M-2 storage words) written by the node-local
  * kernel and read by the collide kernel, the constant tables and a status word. */
 lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 

@@ -71,9 +71,9 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.psi = take(3 * N * ct);
   L.corr_bytes = 6 * N * st;   // deferred corrections in the storage precision
   L.corr = take(L.corr_bytes);
-  // collision record: 15 + 2 (M - 1) FP64 words and 5 M - 1 words in the storage precision
-  L.rec_d = take((15 + 2 * (M - 1)) * N * 8);
-  L.rec_f = take((5 * M - 1) * N * st);
+  // collision record: 15 + (M - 1) FP64 words and 6 M - 2 words in the storage precision
+  L.rec_d = take((15 + (M - 1)) * N * 8);
+  L.rec_f = take((6 * M - 2) * N * st);
   L.total = off;
   return L;
 }
@@ -207,6 +207,7 @@ struct lbm_ctx {
   Geom g{};
   Layout L{};
   Buffers b{};
+  CollideConsts kc{};
   int cur = 0;
   int device = 0;
   std::string err;
@@ -307,6 +308,12 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   b.rec_f = ws + L.rec_f;
   Tables t;
   build_tables(h->d, t);
+  h->kc.omega = t.omega;
+  for (int a = 0; a < MAXM; ++a) h->kc.Ra[a] = t.Ra[a];
+  for (int k = 0; k < MAXM * (MAXM - 1) / 2; ++k) {
+    h->kc.invDp[k] = t.invDp[k];
+    h->kc.invDpf[k] = t.invDpf[k];
+  }
   e = hipMemcpy(ws + L.tables, &t, sizeof(Tables), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     uint32_t zero[16] = {0};
@@ -366,7 +373,7 @@ static lbm_status run_steps(lbm_handle h, int32_t n_steps, hipStream_t st, float
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     const int cur = h->cur;
     e = timed(0, [&] { return launch_islands(h->g, h->b, store, cur, st); });
-    if (e == hipSuccess) e = timed(4, [&] { return launch_collide(h->g, h->b, store, cur, st); });
+    if (e == hipSuccess) e = timed(4, [&] { return launch_collide(h->g, h->b, h->kc, store, cur, st); });
     if (e == hipSuccess) e = timed(3, [&] { return launch_ghost(h->g, h->b, store, cur, st); });
     if (e == hipSuccess) e = timed(1, [&] { return launch_psi(h->g, h->b, store, st); });
     if (e == hipSuccess) e = timed(2, [&] { return launch_corr(h->g, h->b, store, st); });

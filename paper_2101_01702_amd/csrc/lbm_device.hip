@@ -119,6 +119,18 @@ __device__ __forceinline__ void st(T *__restrict__ base, uint32_t idx, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (uint32_t)sizeof(T)) = v;
 }
 
+// An empty asm statement that claims to modify v.  Values derived from v inside a loop
+// are then recomputed in every iteration instead of being hoisted and kept live, and
+// loads through a pointer passed through it stay after it.
+template <typename T>
+__device__ __forceinline__ void opaque(T &v) {
+  asm volatile("" : "+v"(v));
+}
+template <typename T>
+__device__ __forceinline__ void opaque_uniform(T *&p) {
+  asm volatile("" : "+s"(p));
+}
+
 // neighbour for the isotropic gradient: periodic wrap or clamp at open faces
 __device__ __forceinline__ int nb_coord(int x, int c, int n, bool periodic) {
   int s = x + c;
@@ -321,6 +333,7 @@ struct StashLayout {
 };
 constexpr int MAIN_BLOCK = 256;
 
+
 // The accesses are volatile: a thread reads back only its own words, and without it
 // the compiler forwards the stored values and keeps them in registers.
 struct Stash {
@@ -339,9 +352,10 @@ template <int M, typename F>
 struct CollCoef {
   double u0, u1, u2, rho, zeta;
   double gA0, gA1[3], gA2[6];
-  double zb[M];
+  double T;                     // temperature: R_b T = Ra[b] T
   F dv[M][3], tbw[M];
-  double omb[M - 1], ca[M - 1];
+  F omb[M - 1];                 // 1 - 2 beta_a
+  double ca[M - 1];             // (1 - omb_a) rho_a + rho_dot_a: exact species mass
   F rcoef[M - 1];
 };
 
@@ -530,6 +544,7 @@ __device__ __forceinline__ void node_islands(const Tables &tb, const Buffers &b,
   cc.u2 = sh.r(SL::U + 2);
   cc.rho = rho;
   cc.zeta = zeta;
+  cc.T = T;
   {
     const double invT = 1.0 / T;
     double hyd[3] = {0.0, 0.0, 0.0};
@@ -554,77 +569,93 @@ __device__ __forceinline__ void node_islands(const Tables &tb, const Buffers &b,
   for (int a = 0; a < M; ++a) {
     const double za = tb.Ra[a] * T;
     const double ra = sh.r(SL::RS + a);
-    cc.zb[a] = za;
     cc.tbw[a] = F(ra * za);
     cc.dv[a][0] = F(du[a][0]);
     cc.dv[a][1] = F(du[a][1]);
     cc.dv[a][2] = F(du[a][2]);
     if (a < M - 1) {
       const double bt = sh.r(SL::BETA + a);
-      cc.omb[a] = 1.0 - 2.0 * bt;
-      cc.ca[a] = 2.0 * bt * ra + sh.r(SL::RD + a);
+      // with omb rounded to F, ca takes 2 beta_a from the rounded value, so that
+      // sum_i f_ai' = omb rho_a + ca = rho_a + rho_dot_a holds exactly
+      cc.omb[a] = F(1.0 - 2.0 * bt);
+      if constexpr (sizeof(F) == 4)
+        cc.ca[a] = (1.0 - double(cc.omb[a])) * ra + sh.r(SL::RD + a);
+      else
+        cc.ca[a] = 2.0 * bt * ra + sh.r(SL::RD + a);
       cc.rcoef[a] = F((bt - 1.0) * ra * inv_rho * za * inv_zeta);
     }
   }
 }
 
-// O7 for one direction: f, g and the species a < M-1; fa(a) returns the pulled
-// species population, store(set, value) writes the post-collision population
-template <int M, typename F, typename FaFn, typename StFn>
-__device__ __forceinline__ void collide_dir(const Tables &tb, const CollCoef<M, F> &cc, int cx, int cy, int cz,
-                                            double f, double gv, FaFn &&fa, StFn &&store) {
-  const double om = tb.omega;
+// O7 for one direction, mixture f and energy g (eqs. f, g); A_i.X and the q^corr
+// part are added by the next pull
+template <int M, typename F, typename StFn>
+__device__ __forceinline__ void collide_fg(const CollideConsts &kc, const CollCoef<M, F> &cc, int cx, int cy,
+                                           int cz, double f, double gv, StFn &&store) {
+  const double om = kc.omega;
   const double fcx = cx, fcy = cy, fcz = cz;
   const double wi = w1(cx) * w1(cy) * w1(cz);
   const double u0 = cc.u0, u1 = cc.u1, u2 = cc.u2;
-  // mixture f (eq. f); A_i.X is added by the next pull
-  {
-    const double feq = cc.rho * psi_c<double>(cx, u0, u0 * u0 + cc.zeta) * psi_c<double>(cy, u1, u1 * u1 + cc.zeta) *
-                       psi_c<double>(cz, u2, u2 * u2 + cc.zeta);
-    store(M - 1, (1.0 - om) * f + om * feq);
-  }
-  // energy g; the q^corr part is added by the next pull
-  {
-    const double acc = cc.gA0 + fcx * cc.gA1[0] + fcy * cc.gA1[1] + fcz * cc.gA1[2] + fcx * fcx * cc.gA2[0] +
-                       fcy * fcy * cc.gA2[1] + fcz * fcz * cc.gA2[2] + fcx * fcy * cc.gA2[3] + fcx * fcz * cc.gA2[4] +
-                       fcy * fcz * cc.gA2[5];
-    store(M, (1.0 - om) * gv + wi * acc);
-  }
-  // species: Phi_b(u) - Phi_b(u + du_b) by telescoping the three axis factors, each
-  // factor difference in closed form, so the difference keeps relative precision.
-  // Axis factor of species b: Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.
-  double phe[M];
-  F dd[M];
-  const double Bx = cx == 0 ? -1.0 : 0.5, By = cy == 0 ? -1.0 : 0.5, Bz = cz == 0 ? -1.0 : 0.5;
-  const double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
-               Az = psi_c<double>(cz, u2, u2 * u2);
+  const double feq = cc.rho * psi_c<double>(cx, u0, u0 * u0 + cc.zeta) * psi_c<double>(cy, u1, u1 * u1 + cc.zeta) *
+                     psi_c<double>(cz, u2, u2 * u2 + cc.zeta);
+  store(M - 1, (1.0 - om) * f + om * feq);
+  const double acc = cc.gA0 + fcx * cc.gA1[0] + fcy * cc.gA1[1] + fcz * cc.gA1[2] + fcx * fcx * cc.gA2[0] +
+                     fcy * fcy * cc.gA2[1] + fcz * fcz * cc.gA2[2] + fcx * fcy * cc.gA2[3] + fcx * fcz * cc.gA2[4] +
+                     fcy * fcz * cc.gA2[5];
+  store(M, (1.0 - om) * gv + wi * acc);
+}
+
+// O7 for one direction, the stored species a < M-1 (eq. finalNumericalEquations with
+// F_ai of eq. fStar); fa(a) returns the pulled population, store(a, v) writes it.
+// Phi_b(u) - Phi_b(u + du_b) is telescoped over the three axis factors, each factor
+// difference in closed form, so the difference keeps relative precision.  Axis factor
+// of species b: Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.
+template <int M, typename F, typename FaFn, typename StFn>
+__device__ __forceinline__ void collide_species(const CollideConsts &kc, const CollCoef<M, F> &cc, int cx, int cy,
+                                                int cz, FaFn &&fa, StFn &&store) {
+  const double u0 = cc.u0, u1 = cc.u1, u2 = cc.u2;
+  // B_c is -1 or 1/2, so (B_c T) R_b equals B_c (R_b T) exactly
+  double BxT = (cx == 0 ? -1.0 : 0.5) * cc.T, ByT = (cy == 0 ? -1.0 : 0.5) * cc.T,
+         BzT = (cz == 0 ? -1.0 : 0.5) * cc.T;
+  double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
+         Az = psi_c<double>(cz, u2, u2 * u2);
   const F u0f = F(u0), u1f = F(u1), u2f = F(u2);
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const double z = cc.zb[a];
-    const double ex = Ax + Bx * z, ey = Ay + By * z, ez = Az + Bz * z;
-    phe[a] = ex * ey * ez;
-    const F dx = psi_diff<F>(cx, u0f, cc.dv[a][0]), dy = psi_diff<F>(cy, u1f, cc.dv[a][1]),
-            dz = psi_diff<F>(cz, u2f, cc.dv[a][2]);
-    const F exf = F(ex), eyf = F(ey), ezf = F(ez);
-    const F sx = exf - dx, sy = eyf - dy;
-    dd[a] = cc.tbw[a] * (dx * eyf * ezf + sx * dy * ezf + sx * sy * dz);
-  }
+  // F_a = sum_b invD_ab dd_b, accumulated over b in increasing order
   F Fa[M - 1];
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a)
+  for (int b = 0; b < M; ++b) {
+    const double Rb = kc.Ra[b];
+    const double ex = Ax + BxT * Rb, ey = Ay + ByT * Rb, ez = Az + BzT * Rb;
+    const F dx = psi_diff<F>(cx, u0f, cc.dv[b][0]), dy = psi_diff<F>(cy, u1f, cc.dv[b][1]),
+            dz = psi_diff<F>(cz, u2f, cc.dv[b][2]);
+    const F exf = F(ex), eyf = F(ey), ezf = F(ez);
+    const F sx = exf - dx, sy = eyf - dy;
+    const F dd = cc.tbw[b] * (dx * eyf * ezf + sx * dy * ezf + sx * sy * dz);
 #pragma unroll
-    for (int bb = a + 1; bb < M; ++bb) {
-      const int k = a * M - a * (a + 1) / 2 + (bb - a - 1);
+    for (int a = 0; a < M - 1; ++a) {
+      if (a == b) continue;
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      const int k = lo * M - lo * (lo + 1) / 2 + (hi - lo - 1);
       F c;
-      if constexpr (sizeof(F) == 4) c = tb.invDpf[k]; else c = F(tb.invDp[k]);
-      Fa[a] += c * dd[bb];
-      if (bb < M - 1) Fa[bb] += c * dd[a];
+      if constexpr (sizeof(F) == 4) c = kc.invDpf[k]; else c = F(kc.invDp[k]);
+      Fa[a] += c * dd;
     }
+  }
+  // the axis factors are recomputed below rather than kept from the loop above
+  opaque(Ax);
+  opaque(Ay);
+  opaque(Az);
+  opaque(BxT);
+  opaque(ByT);
+  opaque(BzT);
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) store(a, cc.omb[a] * fa(a) + cc.ca[a] * phe[a] + double(cc.rcoef[a] * Fa[a]));
+  for (int a = 0; a < M - 1; ++a) {
+    const double Ra = kc.Ra[a];
+    const double phe = (Ax + BxT * Ra) * (Ay + ByT * Ra) * (Az + BzT * Ra);
+    store(a, double(cc.omb[a]) * fa(a) + cc.ca[a] * phe + double(cc.rcoef[a] * Fa[a]));
+  }
 }
 
 // ---- per-node collision record (written by k_islands, read by k_collide) ---------
@@ -633,10 +664,10 @@ __device__ __forceinline__ void collide_dir(const Tables &tb, const CollCoef<M, 
 // rho_dot_a); the remaining words are in the precision F of the inter-species term.
 template <int M>
 struct RecLayout {
-  static constexpr int RHO = 0, U = 1, ZETA = 4, GA0 = 5, GA1 = 6, GA2 = 9, OMB = 15, CA = OMB + M - 1;
+  static constexpr int RHO = 0, U = 1, ZETA = 4, GA0 = 5, GA1 = 6, GA2 = 9, CA = 15;
   static constexpr int DWORDS = CA + M - 1;
-  static constexpr int DV = 0, TBW = 3 * M, RC = 4 * M;
-  static constexpr int FWORDS = RC + M - 1;
+  static constexpr int DV = 0, TBW = 3 * M, RC = 4 * M, OMB = 5 * M - 1;
+  static constexpr int FWORDS = OMB + M - 1;
 };
 
 template <int M, typename F>
@@ -656,7 +687,7 @@ __device__ __forceinline__ void store_record(const Buffers &b, int64_t n, int64_
   for (int k = 0; k < 6; ++k) rd[(RL::GA2 + k) * N + n] = cc.gA2[k];
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) {
-    rd[(RL::OMB + a) * N + n] = cc.omb[a];
+    rf[(RL::OMB + a) * N + n] = cc.omb[a];
     rd[(RL::CA + a) * N + n] = cc.ca[a];
     rf[(RL::RC + a) * N + n] = cc.rcoef[a];
   }
@@ -668,12 +699,11 @@ __device__ __forceinline__ void store_record(const Buffers &b, int64_t n, int64_
   }
 }
 
+// the words of the record that the f and g collision uses
 template <int M, typename F>
-__device__ __forceinline__ void load_record(const Tables &tb, const Buffers &b, int64_t n, int64_t N,
-                                            CollCoef<M, F> &cc) {
+__device__ __forceinline__ void load_record_fg(const Buffers &b, int64_t n, int64_t N, CollCoef<M, F> &cc) {
   using RL = RecLayout<M>;
   const double *rd = static_cast<const double *>(b.rec_d);
-  const F *rf = static_cast<const F *>(b.rec_f);
   const uint32_t i = (uint32_t)n;
   cc.rho = ld(rd + RL::RHO * N, i);
   cc.u0 = ld(rd + (RL::U + 0) * N, i);
@@ -685,16 +715,33 @@ __device__ __forceinline__ void load_record(const Tables &tb, const Buffers &b, 
   for (int d = 0; d < 3; ++d) cc.gA1[d] = ld(rd + (RL::GA1 + d) * N, i);
 #pragma unroll
   for (int k = 0; k < 6; ++k) cc.gA2[k] = ld(rd + (RL::GA2 + k) * N, i);
-  const double T = ld(b.T, i);
+}
+
+// the words of the record that the species collision uses; R_a T from the stored T
+template <int M, typename F>
+__device__ __forceinline__ void load_record_species(const CollideConsts &kc, const Buffers &b, int64_t n, int64_t N,
+                                                    CollCoef<M, F> &cc) {
+  using RL = RecLayout<M>;
+  const double *rd = static_cast<const double *>(b.rec_d);
+  const F *rf = static_cast<const F *>(b.rec_f);
+  const double *Tp = b.T;
+  // issued here, not hoisted above the f and g pass
+  opaque_uniform(rd);
+  opaque_uniform(rf);
+  opaque_uniform(Tp);
+  const uint32_t i = (uint32_t)n;
+  cc.u0 = ld(rd + (RL::U + 0) * N, i);
+  cc.u1 = ld(rd + (RL::U + 1) * N, i);
+  cc.u2 = ld(rd + (RL::U + 2) * N, i);
+  cc.T = ld(Tp, i);
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) {
-    cc.omb[a] = ld(rd + (RL::OMB + a) * N, i);
+    cc.omb[a] = ld(rf + (RL::OMB + a) * N, i);
     cc.ca[a] = ld(rd + (RL::CA + a) * N, i);
     cc.rcoef[a] = ld(rf + (RL::RC + a) * N, i);
   }
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    cc.zb[a] = tb.Ra[a] * T;
 #pragma unroll
     for (int d = 0; d < 3; ++d) cc.dv[a][d] = ld(rf + (RL::DV + 3 * a + d) * N, i);
     cc.tbw[a] = ld(rf + (RL::TBW + a) * N, i);
@@ -727,53 +774,155 @@ __global__ __launch_bounds__(MAIN_BLOCK) void k_islands(Geom g, Buffers b, int c
   store_record<M, F>(b, n, N, cc);
 }
 
-// Step, part 2: one streaming pass, each population pulled, collided and stored.
+// Source of the pull along direction i: padded index of the source cell, and whether
+// it is an interior node (then the deferred corrections at it apply) with its index.
+struct DirSrc {
+  uint32_t ps;
+  uint32_t nc;    // interior index of the source, 0 for a ghost source
+  bool inner;
+};
+
+__device__ __forceinline__ DirSrc dir_src(const Geom &g, int x, int y, int z, int i) {
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+  const RowSrc row = row_src(g, y, z, cy, cz);
+  int sx = x - cx;
+  if (g.per[0]) sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+  const bool outx = sx < 0 || sx >= g.nx;
+  DirSrc d;
+  d.ps = row.prow + (uint32_t)(sx + g.px);
+  d.inner = !(row.nrow < 0 || outx);
+  d.nc = d.inner ? (uint32_t)(row.nrow + sx) : 0u;
+  return d;
+}
+
+// Values of f and g pulled along one direction, with the deferred corrections at the
+// source; all loads without branches, so that they are issued together (a ghost
+// source reads the corrections of node 0 and discards them).
+template <typename ST>
+struct PulledFG {
+  ST f, g, x, cg[3];
+  bool inner;
+};
+
 template <int M, typename ST>
-__global__ __launch_bounds__(MAIN_BLOCK) void k_collide(Geom g, Buffers b, int cur) {
+__device__ __forceinline__ void pull_fg(const Geom &g, const ST *__restrict__ src, const ST *__restrict__ corr,
+                                        int x, int y, int z, int i, PulledFG<ST> &p) {
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1;
+  const DirSrc d = dir_src(g, x, y, z, i);
+  const int64_t NPAD = g.NPAD, N = g.N;
+  p.inner = d.inner;
+  p.f = ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, d.ps);
+  p.g = ld(src + ((int64_t)M * Q + i) * NPAD, d.ps);
+  const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
+  p.x = ld(corr + axis * N, d.nc);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) p.cg[k] = ld(corr + (3 + k) * N, d.nc);
+}
+
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void collide_pulled_fg(const CollideConsts &kc, const CollCoef<M, F> &cc, int i,
+                                                  const PulledFG<ST> &p, ST *__restrict__ dst, int64_t NPAD,
+                                                  uint32_t pself) {
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+  // deferred A_i.X on the axis directions (eq. Ai), rounded to the storage precision
+  const double xs = (cx * cx + cy * cy + cz * cz) == 1 ? 0.5 * double(cx + cy + cz) : 0.0;
+  const double xc = double(ST(xs * double(p.x)));
+  const double f = double(p.f) + (p.inner ? xc : 0.0);
+  // deferred Fourier-correction flux 3 w_i c_i . Cg (eq. corrFourier)
+  const double w3 = 3.0 * (w1(cx) * w1(cy) * w1(cz));
+  const double d = double(cx) * double(p.cg[0]) + double(cy) * double(p.cg[1]) + double(cz) * double(p.cg[2]);
+  const double gc = double(ST(w3 * d));
+  const double gv = double(p.g) + (p.inner ? gc : 0.0);
+  collide_fg<M, F>(kc, cc, cx, cy, cz, f, gv,
+                   [&](int set, double v) { st(dst + ((int64_t)set * Q + i) * NPAD, pself, ST(v)); });
+}
+
+template <int M, typename ST>
+struct PulledS {
+  ST fa[M - 1];
+};
+
+template <int M, typename ST>
+__device__ __forceinline__ void pull_species(const Geom &g, const ST *__restrict__ src, int x, int y, int z, int i,
+                                             PulledS<M, ST> &p) {
+  const DirSrc d = dir_src(g, x, y, z, i);
+  const int64_t NPAD = g.NPAD;
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) p.fa[a] = ld(src + ((int64_t)a * Q + i) * NPAD, d.ps);
+}
+
+template <int M, typename F>
+__device__ __forceinline__ void opaque_species(CollCoef<M, F> &cc) {
+  opaque(cc.u0);
+  opaque(cc.u1);
+  opaque(cc.u2);
+  opaque(cc.T);
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    opaque(cc.tbw[a]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) opaque(cc.dv[a][d]);
+  }
+}
+
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void collide_pulled_species(const CollideConsts &kc, const CollCoef<M, F> &cc, int i,
+                                                       const PulledS<M, ST> &p, ST *__restrict__ dst, int64_t NPAD,
+                                                       uint32_t pself) {
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+  collide_species<M, F>(
+      kc, cc, cx, cy, cz, [&](int a) { return double(p.fa[a]); },
+      [&](int a, double v) { st(dst + ((int64_t)a * Q + i) * NPAD, pself, ST(v)); });
+}
+
+// Step, part 2: one streaming pass, each population pulled, collided and stored; first
+// f and g over the 27 directions, then the species, so that each pass holds only its
+// own coefficients.  The loads of direction i+1 are in flight while direction i is
+// collided; the loops are unrolled twice so that the two sets of pulled values
+// alternate in registers.
+template <int M, typename ST>
+__global__ __launch_bounds__(MAIN_BLOCK) void k_collide(Geom g, Buffers b, CollideConsts kc, int cur) {
   using F = FT<ST>;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
-  const Tables &tb = *b.tab;
   const int x = (int)(n % g.nx);
   const int y = (int)((n / g.nx) % g.ny);
   const int z = (int)(n / ((int64_t)g.nx * g.ny));
   const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
   ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
+  const ST *__restrict__ corr = static_cast<const ST *>(b.corr);
   const int64_t N = g.N, NPAD = g.NPAD;
-  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
-  CollCoef<M, F> cc;
-  load_record<M, F>(tb, b, n, N, cc);
   const uint32_t pself = ((uint32_t)(z + g.pz) * (uint32_t)g.NY + (uint32_t)(y + g.py)) * (uint32_t)g.NX +
                          (uint32_t)(x + g.px);
+  {
+    CollCoef<M, F> cc;
+    load_record_fg<M, F>(b, n, N, cc);
+    PulledFG<ST> pa, pb;
+    pull_fg<M, ST>(g, src, corr, x, y, z, 0, pa);
 #pragma unroll 1
-  for (int i = 0; i < 27; ++i) {
-    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-    const RowSrc row = row_src(g, y, z, cy, cz);
-    Src r;
-    {
-      int sx = x - cx;
-      if (g.per[0]) sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
-      const bool outx = sx < 0 || sx >= g.nx;
-      r.ps = row.prow + (uint32_t)(sx + g.px);
-      r.ns = (row.nrow < 0 || outx) ? -1 : row.nrow + sx;
+    for (int i = 0; i < Q - 1; i += 2) {
+      pull_fg<M, ST>(g, src, corr, x, y, z, i + 1, pb);
+      collide_pulled_fg<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
+      pull_fg<M, ST>(g, src, corr, x, y, z, i + 2, pa);
+      collide_pulled_fg<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
     }
-    double f = (double)ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, r.ps);
-    if (r.ns >= 0 && (cx * cx + cy * cy + cz * cz) == 1) {
-      const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
-      f += double(ST(0.5 * double(cx + cy + cz) * double(ld(cr.X + axis * N, (uint32_t)r.ns))));
+    collide_pulled_fg<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
+  }
+  {
+    CollCoef<M, F> cc;
+    load_record_species<M, F>(kc, b, n, N, cc);
+    PulledS<M, ST> pa, pb;
+    pull_species<M, ST>(g, src, x, y, z, 0, pa);
+#pragma unroll 1
+    for (int i = 0; i < Q - 1; i += 2) {
+      pull_species<M, ST>(g, src, x, y, z, i + 1, pb);
+      opaque_species<M, F>(cc);
+      collide_pulled_species<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
+      pull_species<M, ST>(g, src, x, y, z, i + 2, pa);
+      opaque_species<M, F>(cc);
+      collide_pulled_species<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
     }
-    double gv = (double)ld(src + ((int64_t)M * Q + i) * NPAD, r.ps);
-    if (r.ns >= 0) {
-      const uint32_t ns = (uint32_t)r.ns;
-      double d = 0.0;
-      if (cx != 0) d += cx * double(ld(cr.Cg, ns));
-      if (cy != 0) d += cy * double(ld(cr.Cg + N, ns));
-      if (cz != 0) d += cz * double(ld(cr.Cg + 2 * N, ns));
-      gv += double(ST(3.0 * (w1(cx) * w1(cy) * w1(cz)) * d));
-    }
-    collide_dir<M, F>(
-        tb, cc, cx, cy, cz, f, gv, [&](int a) { return (double)ld(src + ((int64_t)a * Q + i) * NPAD, r.ps); },
-        [&](int set, double v) { st(dst + ((int64_t)set * Q + i) * NPAD, pself, ST(v)); });
+    collide_pulled_species<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
   }
 }
 
@@ -1088,8 +1237,9 @@ struct RunIslands {
 };
 template <int M, typename ST, typename RT>
 struct RunCollide {
-  static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_collide<M, ST>), dim3(blocks_for(g.N, MAIN_BLOCK)), dim3(MAIN_BLOCK), 0, st, g, b, cur);
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
+    hipLaunchKernelGGL((k_collide<M, ST>), dim3(blocks_for(g.N, MAIN_BLOCK)), dim3(MAIN_BLOCK), 0, st, g, b, kc,
+                       cur);
     return hipGetLastError();
   }
 };
@@ -1144,8 +1294,9 @@ hipError_t launch_islands(const Geom &g, const Buffers &b, int store, int cur, h
   return dispatch<RunIslands>(g.M, store, g, b, cur, st);
 }
 
-hipError_t launch_collide(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
-  return dispatch<RunCollide>(g.M, store, g, b, cur, st);
+hipError_t launch_collide(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                          hipStream_t st) {
+  return dispatch<RunCollide>(g.M, store, g, b, kc, cur, st);
 }
 
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {

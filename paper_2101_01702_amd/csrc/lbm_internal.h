@@ -35,6 +35,16 @@ struct Tables {
   double omega, omega1;
 };
 
+// Constants of the collision passed as kernel arguments: they are read with
+// scalar loads from the argument segment, which stays valid after the kernel's
+// first store to global memory.
+struct CollideConsts {
+  double omega;
+  double Ra[MAXM];                       // lattice gas constants kappa R_U / m_a
+  double invDp[MAXM * (MAXM - 1) / 2];   // 1 / D_ab for a < b, row-major pairs
+  float invDpf[MAXM * (MAXM - 1) / 2];
+};
+
 struct Geom {
   int32_t M;                  // species
   int32_t nx, ny, nz;
@@ -66,7 +76,8 @@ struct Buffers {
 hipError_t launch_init(const Geom &g, const Buffers &b, int store, const double *rho, const double *u,
                        const double *T, const double *Y, int cur, hipStream_t st);
 hipError_t launch_islands(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
-hipError_t launch_collide(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
+hipError_t launch_collide(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                          hipStream_t st);
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_ghost(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
