@@ -65,6 +65,7 @@ enum {
 
 #define LBM_MAX_SPECIES 10
 #define LBM_MAX_REACTIONS 64
+#define LBM_MAX_ORDER 8      /* molecules on one side of a reaction */
 
 /*
  * Statement of the problem (Sec. 2-4).  Host arrays, copied by lbm_create.
@@ -78,7 +79,8 @@ enum {
  *                   entropy constant a7); eq. specHa
  *   diff_ab[M][M]   binary diffusivities D_ab in lattice units, symmetric, > 0
  *                   off the diagonal (eqs. stefanMaxwell, tauab)
- *   nu_reac[R][M], nu_prod[R][M]   stoichiometric coefficients, 0..3
+ *   nu_reac[R][M], nu_prod[R][M]   stoichiometric coefficients, 0..3, at most
+ *                   LBM_MAX_ORDER molecules on each side
  *   arrhenius[R][3] A (CGS mol, cm^3, s), temperature exponent b, activation
  *                   temperature Ta (K): k_f = A T^b exp(-Ta/T)
  *   reversible[R]   nonzero: reverse rate k_f / K_c, K_c from the NASA-7 Gibbs

@@ -121,12 +121,17 @@ bool validate(const lbm_desc *d, std::string *err) {
   }
   for (int k = 0; k < R; ++k) {
     double mass_in = 0.0, mass_out = 0.0;
+    int ord_in = 0, ord_out = 0;
     for (int a = 0; a < M; ++a) {
       const int nr = d->nu_reac[k * M + a], np = d->nu_prod[k * M + a];
       if (nr < 0 || nr > 3 || np < 0 || np > 3) return fail(err, "reaction %d: stoichiometric coefficients must be in 0..3", k);
       mass_in += nr * d->molar_mass[a];
       mass_out += np * d->molar_mass[a];
+      ord_in += nr;
+      ord_out += np;
     }
+    if (ord_in > LBM_MAX_ORDER || ord_out > LBM_MAX_ORDER)
+      return fail(err, "reaction %d: more than %d molecules on one side", k, LBM_MAX_ORDER);
     if (std::fabs(mass_in - mass_out) > 1e-9 * (mass_in + mass_out))
       return fail(err, "reaction %d does not conserve mass", k);
     const double A = d->arrhenius[k * 3], b = d->arrhenius[k * 3 + 1], Ta = d->arrhenius[k * 3 + 2];
@@ -188,8 +193,20 @@ void build_tables(const lbm_desc &d, Tables &t) {
       t.nu_r[k][a] = d.nu_reac[k * M + a];
       t.nu_p[k][a] = d.nu_prod[k * M + a];
       dn += t.nu_p[k][a] - t.nu_r[k][a];
+      t.dnu_a[k][a] = double(t.nu_p[k][a] - t.nu_r[k][a]);
     }
     t.dnu[k] = dn;
+    // species of each side repeated by their coefficient, ascending; unused slots
+    // point at the constant 1 that follows the concentrations
+    int nr = 0, np = 0;
+    for (int a = 0; a < M; ++a) {
+      for (int r = 0; r < t.nu_r[k][a]; ++r) t.reac_idx[k][nr++] = a;
+      for (int r = 0; r < t.nu_p[k][a]; ++r) t.prod_idx[k][np++] = a;
+    }
+    t.nreac[k] = nr;
+    t.nprod[k] = np;
+    for (int r = nr; r < MAXORD; ++r) t.reac_idx[k][r] = M;
+    for (int r = np; r < MAXORD; ++r) t.prod_idx[k][r] = M;
   }
   t.ln_c0_const = std::log(d.p0 * 1e-6 / R_UNIV);
   t.omega = d.omega;

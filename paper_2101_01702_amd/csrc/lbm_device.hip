@@ -167,7 +167,8 @@ __device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src 
 // pulled value of g with the deferred Fourier-correction flux 3 w_i c_i . Cg
 template <int CX, typename ST, typename CT>
 __device__ __forceinline__ double pull_g(const ST *__restrict__ base, const Src &r, const Corr<CT> &cr, int cy,
-                                         int cz, double w3) {
+                                         int cz) {
+  const double w3 = 3.0 * (w1(CX) * w1(cy) * w1(cz));
   double v = double(ld(base, r.ps));
   if (r.ns >= 0) {
     const uint32_t ns = (uint32_t)r.ns;
@@ -222,7 +223,6 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
   for (int kyz = 0; kyz < 9; ++kyz) {
     const int ky = kyz % 3, kz = kyz / 3;
     const int cy = ky - 1, cz = kz - 1;
-    const double wyz3 = 3.0 * w1(cy) * w1(cz);
     const RowSrc row = row_src(g, y, z, cy, cz);
     static_for<3>([&](auto Kx) {
       constexpr int kx = decltype(Kx)::value;
@@ -230,7 +230,7 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
       const int i = kx + 3 * kyz;
       const Src r = src_from_row(g, row, ax, kx);
       const double f = pull_f<cx, ST, ST>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-      const double gg = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w1(cx) * wyz3);
+      const double gg = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz);
       rho += f;
       rE += gg;
       if constexpr (cx != 0) {
@@ -319,27 +319,31 @@ __device__ __forceinline__ void store_rt(void *base, int64_t idx, RT v) {
 }
 
 // ---- the step --------------------------------------------------------------------
-// Per-thread LDS stash of the values that live across the Stefan-Maxwell solve, so
-// that the solve holds only its matrix in registers.  Word-major layout (word w of
-// thread t at w * blockDim + t): conflict-free.
+constexpr int MAIN_BLOCK = 256;   // collide kernel
+constexpr int ISL_BLOCK = 128;    // node-local kernel
+
+// Per-thread LDS words of the node-local kernel (word w of thread t at w * ISL_BLOCK
+// + t: conflict-free).  Values that live across the chemistry and the Stefan-Maxwell
+// solve are parked here so that those hold only their own state in registers.  At most
+// 40 words for M = 10, so that 512 threads per CU fit in 160 KB.
 template <int M>
-struct StashLayout {
-  static constexpr int RS = 0;            // species densities [M]
-  static constexpr int U = RS + M;        // velocity [3]
-  static constexpr int G = U + 3;         // g coefficients [10]: A0, A1[3], A2[6]
-  static constexpr int RD = G + 10;       // production rates [M-1]
-  static constexpr int BETA = RD + M - 1; // relaxation parameters beta_a [M-1]
+struct IslWords {
+  static constexpr int RS = 0;             // species densities [M]
+  static constexpr int G = RS + M;         // g coefficients [10]: A0, A1[3], A2[6]
+  static constexpr int C = G + 10;         // concentrations [M], then 1.0; production rates [M-1] after the chemistry
+  static constexpr int RD = C;
+  static constexpr int BETA = C + M + 1;   // beta_a [M-1]
   static constexpr int WORDS = BETA + M - 1;
 };
-constexpr int MAIN_BLOCK = 256;
 
-
-// The accesses are volatile: a thread reads back only its own words, and without it
-// the compiler forwards the stored values and keeps them in registers.
-struct Stash {
-  volatile double *p;   // &stash[tid]
-  __device__ __forceinline__ void w(int k, double v) const { p[k * MAIN_BLOCK] = v; }
-  __device__ __forceinline__ double r(int k) const { return p[k * MAIN_BLOCK]; }
+// The accesses are volatile, through an LDS pointer: the compiler then neither keeps
+// the stored values in registers instead of reading them back, nor takes the LDS
+// stores for stores that could change the constant tables in global memory.
+typedef __attribute__((address_space(3))) volatile double lds_double;
+struct IslStash {
+  lds_double *p;   // &words[tid]
+  __device__ __forceinline__ void w(int k, double v) const { p[k * ISL_BLOCK] = v; }
+  __device__ __forceinline__ double r(int k) const { return p[k * ISL_BLOCK]; }
 };
 
 // Precision of the inter-species term F of eq. fStar (a correction whose sum over
@@ -358,234 +362,6 @@ struct CollCoef {
   double ca[M - 1];             // (1 - omb_a) rho_a + rho_dot_a: exact species mass
   F rcoef[M - 1];
 };
-
-// O2-O5 and the collision coefficients of one node from its moments: temperature,
-// side channel, g coefficients, production rates, Stefan-Maxwell solve.
-template <int M, typename RT, typename F>
-__device__ __forceinline__ void node_islands(const Tables &tb, const Buffers &b, int64_t n, int64_t N,
-                                             const Macro<M> &m, const Stash &sh, CollCoef<M, F> &cc) {
-  using SL = StashLayout<M>;
-  uint32_t anom = 0;
-  const double rho = m.rho;
-  double T, zeta;
-  double du[M][3];   // right-hand side u_a - u of eq. transform1, then its solution
-  {
-    if (!(rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
-    const double inv_rho = 1.0 / rho;
-#pragma unroll
-    for (int a = 0; a < M; ++a)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) du[a][d] = m.du0[a][d];
-
-    // O2: temperature, mixture gas constant, enthalpies
-    if (!node_temperature<M>(tb, m, b.T[n], T)) anom |= LBM_ANOM_NEWTON;
-    const double invT = 1.0 / T;
-    zeta = 0.0;
-#pragma unroll
-    for (int a = 0; a < M; ++a) zeta += m.rs[a] * inv_rho * tb.Ra[a];
-    zeta *= T;
-    const double P = rho * zeta;
-    double Hmix = 0.0;
-    {
-      const double wc = 0.5 * (2.0 - tb.omega1) * P;
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        const double Ya = m.rs[a] * inv_rho;
-        const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
-        Hmix += Ya * Ha;
-        store_rt<RT>(b.side_Y, a * N + n, RT(Ya));
-        store_rt<RT>(b.side_w, a * N + n, RT(wc * Ha));
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double u = m.u[d];
-        store_rt<RT>(b.side_phi, d * N + n, RT(rho * u * (1.0 - 3.0 * zeta) - rho * u * u * u));
-      }
-      if (tb.open_any) {
-        store_rt<RT>(b.side_rho, n, RT(rho));
-#pragma unroll
-        for (int d = 0; d < 3; ++d) store_rt<RT>(b.side_u, d * N + n, RT(m.u[d]));
-      }
-      b.T[n] = T;
-      if (!isfinite(T) || !isfinite(rho) || !isfinite(m.rhoE)) anom |= LBM_ANOM_NONFINITE;
-      if (anom) atomicOr(b.status, anom);
-    }
-
-    // g collision coefficients (eq. g folded with eqs. gieq, geq1mom, geq2mom,
-    // gstareq1mom): g' = (1-omega) g + w_i [A0 + A1.c + A2 : c c] with
-    // A1 = 3 omega q^eq + 3 V, V = (omega-omega1)(q - u.(P - P^eq) - q^eq)
-    //      + omega1 rho sum_a H_a Y_a du_a (the last term is added after the solve)
-    {
-      const double usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-      const double h2 = Hmix + 0.5 * usq;
-      const double *u = m.u;
-      double qeq[3], Peq[6], Req[6];
-      for (int d = 0; d < 3; ++d) qeq[d] = h2 * rho * u[d];
-      const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        Peq[k] = (k < 3 ? rho * zeta : 0.0) + rho * u[ia[k]] * u[ib[k]];
-        Req[k] = h2 * Peq[k] + P * u[ia[k]] * u[ib[k]];
-      }
-      const double om_d = tb.omega, om1 = tb.omega1;
-      const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-      const double trR = Req[0] + Req[1] + Req[2];
-      sh.w(SL::G + 0, om_d * (2.5 * m.rhoE - 1.5 * trR));
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double uP = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) uP += u[c] * (m.P6[sym[c][d]] - Peq[sym[c][d]]);
-        sh.w(SL::G + 1 + d, om_d * 3.0 * qeq[d] + 3.0 * (om_d - om1) * (m.q[d] - uP - qeq[d]));
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-        sh.w(SL::G + 4 + k, om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal twice
-    }
-
-    // O3: production rates (mass action, K_c from the NASA-7 Gibbs function)
-    {
-      const double lnT = log(T);
-      double c[M], wd[M], gib[M];
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        c[a] = m.rs[a] * tb.conc_scale[a];
-        wd[a] = 0.0;
-        gib[a] = h_RT(tb.nasa[a], T, invT) - s_R(tb.nasa[a], T, lnT);
-      }
-      const double ln_c0 = tb.ln_c0_const - lnT;
-      for (int k = 0; k < tb.R; ++k) {
-        const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
-        double fwd = exp(lnkf);
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-          for (int r = 0; r < tb.nu_r[k][a]; ++r) fwd *= c[a];
-        double rev = 0.0;
-        if (tb.rev[k]) {
-          double dG = 0.0;
-#pragma unroll
-          for (int a = 0; a < M; ++a) dG += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * gib[a];
-          const double lnKc = -dG + tb.dnu[k] * ln_c0;
-          rev = exp(lnkf - lnKc);
-#pragma unroll
-          for (int a = 0; a < M; ++a)
-            for (int r = 0; r < tb.nu_p[k][a]; ++r) rev *= c[a];
-        }
-        const double qk = fwd - rev;
-#pragma unroll
-        for (int a = 0; a < M; ++a) wd[a] += double(tb.nu_p[k][a] - tb.nu_r[k][a]) * qk;
-      }
-#pragma unroll
-      for (int a = 0; a < M - 1; ++a) sh.w(SL::RD + a, tb.rdot_scale[a] * wd[a]);
-    }
-#pragma unroll
-    for (int a = 0; a < M; ++a) sh.w(SL::RS + a, m.rs[a]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) sh.w(SL::U + d, m.u[d]);
-  }
-
-  // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1),
-  // Gaussian elimination on the row-diagonally dominant matrix.  1/tau_ab =
-  // (R_a T)(R_b T) / ((R T) D_ab) is symmetric: built from the pair table.
-  const double inv_rho = 1.0 / rho, inv_zeta = 1.0 / zeta;
-  {
-    double A[M][M], Yb[M], zl[M], it[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-      Yb[a] = sh.r(SL::RS + a) * inv_rho;
-      zl[a] = tb.Ra[a] * T;
-      it[a] = 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < M; ++a)
-#pragma unroll
-      for (int bb = a + 1; bb < M; ++bb) {
-        const int k = a * M - a * (a + 1) / 2 + (bb - a - 1);
-        const double K = zl[a] * zl[bb] * tb.invDp[k] * inv_zeta;
-        A[a][bb] = -0.5 * K * Yb[bb];
-        A[bb][a] = -0.5 * K * Yb[a];
-        it[a] += Yb[bb] * K;
-        it[bb] += Yb[a] * K;
-      }
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-      A[a][a] = 1.0 + 0.5 * it[a];
-      // beta_a = dt / (2 tau_a + dt) with 1/tau_a = sum_b Y_b / tau_ab (eq. fStar, tauab)
-      if (a < M - 1) sh.w(SL::BETA + a, it[a] / (it[a] + 2.0));
-    }
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const double piv = 1.0 / A[k][k];
-#pragma unroll
-      for (int r = k + 1; r < M; ++r) {
-        const double l = A[r][k] * piv;
-#pragma unroll
-        for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) du[r][d] -= l * du[k][d];
-      }
-    }
-#pragma unroll
-    for (int r = M - 1; r >= 0; --r) {
-      const double inv = 1.0 / A[r][r];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double v = du[r][d];
-#pragma unroll
-        for (int c = r + 1; c < M; ++c) v -= A[r][c] * du[c][d];
-        du[r][d] = v * inv;
-      }
-    }
-  }
-
-  // O7: collision coefficients
-  cc.u0 = sh.r(SL::U + 0);
-  cc.u1 = sh.r(SL::U + 1);
-  cc.u2 = sh.r(SL::U + 2);
-  cc.rho = rho;
-  cc.zeta = zeta;
-  cc.T = T;
-  {
-    const double invT = 1.0 / T;
-    double hyd[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-      const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
-      const double HY = Ha * sh.r(SL::RS + a) * inv_rho;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) hyd[d] += HY * du[a][d];
-    }
-    cc.gA0 = sh.r(SL::G + 0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) cc.gA1[d] = sh.r(SL::G + 1 + d) + 3.0 * tb.omega1 * rho * hyd[d];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) cc.gA2[k] = sh.r(SL::G + 4 + k);
-  }
-  // species a < M-1 (eq. finalNumericalEquations with F_ai of eq. fStar):
-  // f_ai' = (1 - 2 beta_a) f_ai + (2 beta_a rho_a + rho_dot_a) Phi_a(u)
-  //         + (beta_a - 1) (Y_a zeta_a / zeta) sum_b invD_ab rho_b zeta_b (Phi_b(u) - Phi_b(u + du_b))
-  // with Phi_b(v) the unit-density product form at zeta_b (eqs. feq, fstar, fsource)
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const double za = tb.Ra[a] * T;
-    const double ra = sh.r(SL::RS + a);
-    cc.tbw[a] = F(ra * za);
-    cc.dv[a][0] = F(du[a][0]);
-    cc.dv[a][1] = F(du[a][1]);
-    cc.dv[a][2] = F(du[a][2]);
-    if (a < M - 1) {
-      const double bt = sh.r(SL::BETA + a);
-      // with omb rounded to F, ca takes 2 beta_a from the rounded value, so that
-      // sum_i f_ai' = omb rho_a + ca = rho_a + rho_dot_a holds exactly
-      cc.omb[a] = F(1.0 - 2.0 * bt);
-      if constexpr (sizeof(F) == 4)
-        cc.ca[a] = (1.0 - double(cc.omb[a])) * ra + sh.r(SL::RD + a);
-      else
-        cc.ca[a] = 2.0 * bt * ra + sh.r(SL::RD + a);
-      cc.rcoef[a] = F((bt - 1.0) * ra * inv_rho * za * inv_zeta);
-    }
-  }
-}
 
 // O7 for one direction, mixture f and energy g (eqs. f, g); A_i.X and the q^corr
 // part are added by the next pull
@@ -670,35 +446,6 @@ struct RecLayout {
   static constexpr int FWORDS = OMB + M - 1;
 };
 
-template <int M, typename F>
-__device__ __forceinline__ void store_record(const Buffers &b, int64_t n, int64_t N, const CollCoef<M, F> &cc) {
-  using RL = RecLayout<M>;
-  double *rd = static_cast<double *>(b.rec_d);
-  F *rf = static_cast<F *>(b.rec_f);
-  rd[RL::RHO * N + n] = cc.rho;
-  rd[(RL::U + 0) * N + n] = cc.u0;
-  rd[(RL::U + 1) * N + n] = cc.u1;
-  rd[(RL::U + 2) * N + n] = cc.u2;
-  rd[RL::ZETA * N + n] = cc.zeta;
-  rd[RL::GA0 * N + n] = cc.gA0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) rd[(RL::GA1 + d) * N + n] = cc.gA1[d];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) rd[(RL::GA2 + k) * N + n] = cc.gA2[k];
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    rf[(RL::OMB + a) * N + n] = cc.omb[a];
-    rd[(RL::CA + a) * N + n] = cc.ca[a];
-    rf[(RL::RC + a) * N + n] = cc.rcoef[a];
-  }
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) rf[(RL::DV + 3 * a + d) * N + n] = cc.dv[a][d];
-    rf[(RL::TBW + a) * N + n] = cc.tbw[a];
-  }
-}
-
 // the words of the record that the f and g collision uses
 template <int M, typename F>
 __device__ __forceinline__ void load_record_fg(const Buffers &b, int64_t n, int64_t N, CollCoef<M, F> &cc) {
@@ -746,32 +493,6 @@ __device__ __forceinline__ void load_record_species(const CollideConsts &kc, con
     for (int d = 0; d < 3; ++d) cc.dv[a][d] = ld(rf + (RL::DV + 3 * a + d) * N, i);
     cc.tbw[a] = ld(rf + (RL::TBW + a) * N, i);
   }
-}
-
-// Step, part 1: moments of the pulled state and everything of the collision that is
-// local to the node (temperature, production rates, Stefan-Maxwell solve).
-template <int M, typename ST>
-__global__ __launch_bounds__(MAIN_BLOCK) void k_islands(Geom g, Buffers b, int cur) {
-  using SL = StashLayout<M>;
-  using F = FT<ST>;
-  __shared__ double stash[SL::WORDS * MAIN_BLOCK];
-  const Stash sh{&stash[threadIdx.x]};
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= g.N) return;
-  const Tables &tb = *b.tab;
-  const int x = (int)(n % g.nx);
-  const int y = (int)((n / g.nx) % g.ny);
-  const int z = (int)(n / ((int64_t)g.nx * g.ny));
-  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
-  const int64_t N = g.N;
-  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
-  CollCoef<M, F> cc;
-  {
-    Macro<M> m;
-    node_moments<M, ST>(g, src, cr, x, y, z, m);
-    node_islands<M, double, F>(tb, b, n, N, m, sh, cc);
-  }
-  store_record<M, F>(b, n, N, cc);
 }
 
 // Source of the pull along direction i: padded index of the source cell, and whether
@@ -873,6 +594,375 @@ __device__ __forceinline__ void collide_pulled_species(const CollideConsts &kc, 
   collide_species<M, F>(
       kc, cc, cx, cy, cz, [&](int a) { return double(p.fa[a]); },
       [&](int a, double v) { st(dst + ((int64_t)a * Q + i) * NPAD, pself, ST(v)); });
+}
+
+// ---- step, part 1: the node-local kernel ----------------------------------------------
+// Values of all stored sets pulled along one direction, with the deferred corrections
+// at the source (branch-free, so that the loads are issued together).
+template <int M, typename ST>
+struct PulledAll {
+  ST f, g, x, cg[3], fa[M - 1];
+  bool inner;
+};
+
+template <int M, typename ST>
+__device__ __forceinline__ void pull_all(const Geom &g, const ST *__restrict__ src, const ST *__restrict__ corr,
+                                         int x, int y, int z, int i, PulledAll<M, ST> &p) {
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1;
+  const DirSrc d = dir_src(g, x, y, z, i);
+  const int64_t NPAD = g.NPAD, N = g.N;
+  p.inner = d.inner;
+  p.f = ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, d.ps);
+  p.g = ld(src + ((int64_t)M * Q + i) * NPAD, d.ps);
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) p.fa[a] = ld(src + ((int64_t)a * Q + i) * NPAD, d.ps);
+  const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
+  p.x = ld(corr + axis * N, d.nc);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) p.cg[k] = ld(corr + (3 + k) * N, d.nc);
+}
+
+// O1 (eqs. Pa, sumfDotc, g0momTotalEnergy): add direction i to the moments
+template <int M, typename ST>
+__device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, double (&mo)[14],
+                                            double (&sp)[M - 1][4]) {
+  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+  const double xs = (cx * cx + cy * cy + cz * cz) == 1 ? 0.5 * double(cx + cy + cz) : 0.0;
+  const double xc = double(ST(xs * double(p.x)));
+  const double f = double(p.f) + (p.inner ? xc : 0.0);
+  const double w3 = 3.0 * (w1(cx) * w1(cy) * w1(cz));
+  const double d = double(cx) * double(p.cg[0]) + double(cy) * double(p.cg[1]) + double(cz) * double(p.cg[2]);
+  const double gc = double(ST(w3 * d));
+  const double gv = double(p.g) + (p.inner ? gc : 0.0);
+  const double fx = cx, fy = cy, fz = cz;
+  // rho, j (3), P (xx yy zz xy xz yz), rho E, q (3)
+  mo[0] += f;
+  mo[1] += fx * f;
+  mo[2] += fy * f;
+  mo[3] += fz * f;
+  mo[4] += (fx * fx) * f;
+  mo[5] += (fy * fy) * f;
+  mo[6] += (fz * fz) * f;
+  mo[7] += (fx * fy) * f;
+  mo[8] += (fx * fz) * f;
+  mo[9] += (fy * fz) * f;
+  mo[10] += gv;
+  mo[11] += fx * gv;
+  mo[12] += fy * gv;
+  mo[13] += fz * gv;
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    const double fa = double(p.fa[a]);
+    sp[a][0] += fa;
+    sp[a][1] += fx * fa;
+    sp[a][2] += fy * fa;
+    sp[a][3] += fz * fa;
+  }
+}
+
+// Step, part 1: moments of the pulled state (O1) and everything of the collision that
+// is local to the node: temperature (O2), production rates (O3), Stefan-Maxwell
+// solve (O4), the collision coefficients, and the side channel of the stencils (O5).
+// No global store happens before the end of the kernel, so that the constant tables
+// are read with scalar loads throughout.
+template <int M, typename ST>
+__global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cur) {
+  using SW = IslWords<M>;
+  using F = FT<ST>;
+  __shared__ double words[SW::WORDS * ISL_BLOCK];
+  const IslStash sh{(lds_double *)&words[threadIdx.x]};
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const Tables &tb = *b.tab;
+  const int x = (int)(n % g.nx);
+  const int y = (int)((n / g.nx) % g.ny);
+  const int z = (int)(n / ((int64_t)g.nx * g.ny));
+  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
+  const ST *__restrict__ corr = static_cast<const ST *>(b.corr);
+  const int64_t N = g.N;
+  const double T0 = b.T[n];
+
+  // O1: moments; the loads of direction i+1 are in flight while direction i is summed
+  Macro<M> m;
+  {
+    double mo[14], sp[M - 1][4];
+#pragma unroll
+    for (int k = 0; k < 14; ++k) mo[k] = 0.0;
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sp[a][k] = 0.0;
+    PulledAll<M, ST> pa, pb;
+    pull_all<M, ST>(g, src, corr, x, y, z, 0, pa);
+#pragma unroll 1
+    for (int i = 0; i < Q - 1; i += 2) {
+      pull_all<M, ST>(g, src, corr, x, y, z, i + 1, pb);
+      add_moments<M, ST>(i, pa, mo, sp);
+      pull_all<M, ST>(g, src, corr, x, y, z, i + 2, pa);
+      add_moments<M, ST>(i + 1, pb, mo, sp);
+    }
+    add_moments<M, ST>(Q - 1, pa, mo, sp);
+    m.rho = mo[0];
+    const double inv_rho = 1.0 / mo[0];
+    m.u[0] = mo[1] * inv_rho;
+    m.u[1] = mo[2] * inv_rho;
+    m.u[2] = mo[3] * inv_rho;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.P6[k] = mo[4 + k];
+    m.rhoE = mo[10];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) m.q[d] = mo[11 + d];
+    // species a < M-1, and the slaved species M-1 (eq. strongest); u_a - u guarded
+    double rsum = 0, jsx = 0, jsy = 0, jsz = 0;
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) {
+      m.rs[a] = sp[a][0];
+      rsum += sp[a][0]; jsx += sp[a][1]; jsy += sp[a][2]; jsz += sp[a][3];
+      const bool tiny = fabs(sp[a][0]) < 1e-300;
+      const double inv = tiny ? 0.0 : 1.0 / sp[a][0];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) m.du0[a][d] = tiny ? 0.0 : sp[a][1 + d] * inv - m.u[d];
+    }
+    const double rM = mo[0] - rsum;
+    const double jM[3] = {mo[1] - jsx, mo[2] - jsy, mo[3] - jsz};
+    m.rs[M - 1] = rM;
+    const bool tiny = fabs(rM) < 1e-300;
+    const double inv = tiny ? 0.0 : 1.0 / rM;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) m.du0[M - 1][d] = tiny ? 0.0 : jM[d] * inv - m.u[d];
+  }
+
+  uint32_t anom = 0;
+  const double rho = m.rho;
+  const double inv_rho = 1.0 / rho;
+  if (!(rho > 0.0) || !(m.rs[M - 1] > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
+  // O2: temperature, mixture gas constant, pressure, enthalpies
+  double T;
+  if (!node_temperature<M>(tb, m, T0, T)) anom |= LBM_ANOM_NEWTON;
+  if (!isfinite(T) || !isfinite(rho) || !isfinite(m.rhoE)) anom |= LBM_ANOM_NONFINITE;
+  const double invT = 1.0 / T;
+  double zeta = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) zeta += m.rs[a] * inv_rho * tb.Ra[a];
+  zeta *= T;
+  const double P = rho * zeta;
+  double Hmix = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double Ha = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
+    Hmix += m.rs[a] * inv_rho * Ha;
+    sh.w(SW::RS + a, m.rs[a]);
+  }
+  const double u0 = m.u[0], u1 = m.u[1], u2 = m.u[2];
+  // g collision coefficients (eq. g folded with eqs. gieq, geq1mom, geq2mom,
+  // gstareq1mom): g' = (1-omega) g + w_i [A0 + A1.c + A2 : c c] with
+  // A1 = 3 omega q^eq + 3 V, V = (omega-omega1)(q - u.(P - P^eq) - q^eq)
+  //      + omega1 rho sum_a H_a Y_a du_a (the last term is added after the solve)
+  {
+    const double usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+    const double h2 = Hmix + 0.5 * usq;
+    const double *u = m.u;
+    double qeq[3], Peq[6], Req[6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) qeq[d] = h2 * rho * u[d];
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      Peq[k] = (k < 3 ? rho * zeta : 0.0) + rho * u[ia[k]] * u[ib[k]];
+      Req[k] = h2 * Peq[k] + P * u[ia[k]] * u[ib[k]];
+    }
+    const double om_d = tb.omega, om1 = tb.omega1;
+    const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    const double trR = Req[0] + Req[1] + Req[2];
+    sh.w(SW::G + 0, om_d * (2.5 * m.rhoE - 1.5 * trR));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double uP = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uP += u[c] * (m.P6[sym[c][d]] - Peq[sym[c][d]]);
+      sh.w(SW::G + 1 + d, om_d * 3.0 * qeq[d] + 3.0 * (om_d - om1) * (m.q[d] - uP - qeq[d]));
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      sh.w(SW::G + 4 + k, om_d * (k < 3 ? 4.5 * Req[k] - 1.5 * m.rhoE : 9.0 * Req[k]));  // off-diagonal twice
+  }
+  // right-hand side u_a - u of eq. transform1, kept in registers for the solve
+  double du[M][3];
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) du[a][d] = m.du0[a][d];
+
+  // O3: production rates (mass action, K_c from the NASA-7 Gibbs function).  The
+  // concentrations sit in LDS with a constant 1 after them, so that each side of a
+  // reaction is a product over a padded list of species indices.
+  {
+    const double lnT = log(T);
+    double gib[M], wd[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      sh.w(SW::C + a, sh.r(SW::RS + a) * tb.conc_scale[a]);
+      wd[a] = 0.0;
+      gib[a] = h_RT(tb.nasa[a], T, invT) - s_R(tb.nasa[a], T, lnT);
+    }
+    sh.w(SW::C + M, 1.0);
+    const double ln_c0 = tb.ln_c0_const - lnT;
+    for (int k = 0; k < tb.R; ++k) {
+      const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
+      double fwd = exp(lnkf);
+      for (int r = 0; r < tb.nreac[k]; ++r) fwd *= sh.r(SW::C + tb.reac_idx[k][r]);
+      double rev = 0.0;
+      if (tb.rev[k]) {
+        double dG = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) dG += tb.dnu_a[k][a] * gib[a];
+        const double lnKc = -dG + tb.dnu[k] * ln_c0;
+        rev = exp(lnkf - lnKc);
+        for (int r = 0; r < tb.nprod[k]; ++r) rev *= sh.r(SW::C + tb.prod_idx[k][r]);
+      }
+      const double qk = fwd - rev;
+#pragma unroll
+      for (int a = 0; a < M; ++a) wd[a] += tb.dnu_a[k][a] * qk;
+    }
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) sh.w(SW::RD + a, tb.rdot_scale[a] * wd[a]);
+  }
+
+  // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1).
+  // The matrix is A_ab = -K_ab Y_b / 2 (a != b), A_aa = 1 + 1/(2 tau_a), with the
+  // symmetric 1/tau_ab = K_ab = (R_a T)(R_b T) / ((R T) D_ab).  A = B diag(Y) with B
+  // symmetric, and every Schur complement of Gaussian elimination on A keeps that
+  // form, so the elimination (no pivoting: A is strictly row-diagonally dominant) runs
+  // on the lower triangle of B and the diagonal of A, with the multipliers of the
+  // elimination on A itself.
+  {
+    constexpr int NP = M * (M - 1) / 2;
+    double Bl[NP], Ad[M], Yb[M], zl[M];
+    const double inv_zeta = 1.0 / zeta;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      Yb[a] = sh.r(SW::RS + a) * inv_rho;
+      zl[a] = tb.Ra[a] * T;
+      Ad[a] = 0.0;
+    }
+    // packed lower triangle: (r, c), c < r, at r (r - 1) / 2 + c
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int c = a + 1; c < M; ++c) {
+        const int k = a * M - a * (a + 1) / 2 + (c - a - 1);
+        const double K = zl[a] * zl[c] * tb.invDp[k] * inv_zeta;
+        Bl[c * (c - 1) / 2 + a] = -0.5 * K;
+        Ad[a] += Yb[c] * K;
+        Ad[c] += Yb[a] * K;
+      }
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      // beta_a = dt / (2 tau_a + dt) with 1/tau_a = sum_b Y_b / tau_ab (eqs. fStar, tauab)
+      if (a < M - 1) sh.w(SW::BETA + a, Ad[a] / (Ad[a] + 2.0));
+      Ad[a] = 1.0 + 0.5 * Ad[a];
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const double piv = 1.0 / Ad[k];
+#pragma unroll
+      for (int r = k + 1; r < M; ++r) {
+        const double brk = Bl[r * (r - 1) / 2 + k];
+        const double l = brk * Yb[k] * piv;      // A_rk / A_kk
+#pragma unroll
+        for (int c = k + 1; c < r; ++c) Bl[r * (r - 1) / 2 + c] -= l * Bl[c * (c - 1) / 2 + k];
+        Ad[r] -= l * (brk * Yb[r]);               // A_rr -= l A_kr, A_kr = B_rk Y_r
+#pragma unroll
+        for (int d = 0; d < 3; ++d) du[r][d] -= l * du[k][d];
+      }
+    }
+#pragma unroll
+    for (int r = M - 1; r >= 0; --r) {
+      const double inv = 1.0 / Ad[r];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double v = du[r][d];
+#pragma unroll
+        for (int c = r + 1; c < M; ++c) v -= (Bl[c * (c - 1) / 2 + r] * Yb[c]) * du[c][d];
+        du[r][d] = v * inv;
+      }
+    }
+  }
+
+  // O7: collision coefficients, written to the record together with the side channel.
+  // Everything taken from the constant tables is read before the first store.
+  double Ha[M], za[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    za[a] = tb.Ra[a] * T;
+    Ha[a] = za[a] * h_RT(tb.nasa[a], T, invT);
+  }
+  const double om1 = tb.omega1;
+  const bool open_any = tb.open_any != 0;
+  using RL = RecLayout<M>;
+  double *rd = static_cast<double *>(b.rec_d);
+  F *rf = static_cast<F *>(b.rec_f);
+  {
+    const double inv_zeta = 1.0 / zeta;
+    double hyd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const double ra = sh.r(SW::RS + a);
+      const double HY = Ha[a] * ra * inv_rho;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        hyd[d] += HY * du[a][d];
+        rf[(RL::DV + 3 * a + d) * N + n] = F(du[a][d]);
+      }
+      rf[(RL::TBW + a) * N + n] = F(ra * za[a]);
+      if (a < M - 1) {
+        const double bt = sh.r(SW::BETA + a);
+        const double rdot = sh.r(SW::RD + a);
+        // with 1 - 2 beta_a rounded to F, the source coefficient takes 2 beta_a from
+        // the rounded value, so that sum_i f_ai' = rho_a + rho_dot_a holds exactly
+        const F omb = F(1.0 - 2.0 * bt);
+        double ca;
+        if constexpr (sizeof(F) == 4)
+          ca = (1.0 - double(omb)) * ra + rdot;
+        else
+          ca = 2.0 * bt * ra + rdot;
+        rf[(RL::OMB + a) * N + n] = omb;
+        rd[(RL::CA + a) * N + n] = ca;
+        rf[(RL::RC + a) * N + n] = F((bt - 1.0) * ra * inv_rho * za[a] * inv_zeta);
+      }
+    }
+    rd[RL::RHO * N + n] = rho;
+    rd[(RL::U + 0) * N + n] = u0;
+    rd[(RL::U + 1) * N + n] = u1;
+    rd[(RL::U + 2) * N + n] = u2;
+    rd[RL::ZETA * N + n] = zeta;
+    rd[RL::GA0 * N + n] = sh.r(SW::G + 0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rd[(RL::GA1 + d) * N + n] = sh.r(SW::G + 1 + d) + 3.0 * om1 * rho * hyd[d];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rd[(RL::GA2 + k) * N + n] = sh.r(SW::G + 4 + k);
+  }
+  // O5: side channel of the stencils and the ghosts
+  {
+    double *sY = static_cast<double *>(b.side_Y), *sw = static_cast<double *>(b.side_w);
+    double *sphi = static_cast<double *>(b.side_phi);
+    const double wc = 0.5 * (2.0 - om1) * P;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      sY[a * N + n] = sh.r(SW::RS + a) * inv_rho;
+      sw[a * N + n] = wc * Ha[a];
+    }
+    const double uu[3] = {u0, u1, u2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sphi[d * N + n] = rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d];
+    if (open_any) {
+      static_cast<double *>(b.side_rho)[n] = rho;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) static_cast<double *>(b.side_u)[d * N + n] = uu[d];
+    }
+    b.T[n] = T;
+    if (anom) atomicOr(b.status, anom);
+  }
 }
 
 // Step, part 2: one streaming pass, each population pulled, collided and stored; first
@@ -1195,10 +1285,9 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, cons
       constexpr int cx = kx - 1;
       const int i = kx + 3 * kyz;
       const Src r = make_src(g, ax, ay, az, kx, ky, kz);
-      const double w3 = 3.0 * w1(cx) * w1(cy) * w1(cz);
       out[((int64_t)(M - 1) * Q + i) * nn + k] =
           pull_f<cx, ST, ST>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-      out[((int64_t)M * Q + i) * nn + k] = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, w3);
+      out[((int64_t)M * Q + i) * nn + k] = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz);
       for (int a = 0; a < M - 1; ++a)
         out[((int64_t)a * Q + i) * nn + k] = (double)ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
     });
@@ -1231,7 +1320,7 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 template <int M, typename ST, typename RT>
 struct RunIslands {
   static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_islands<M, ST>), dim3(blocks_for(g.N, MAIN_BLOCK)), dim3(MAIN_BLOCK), 0, st, g, b, cur);
+    hipLaunchKernelGGL((k_islands<M, ST>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b, cur);
     return hipGetLastError();
   }
 };

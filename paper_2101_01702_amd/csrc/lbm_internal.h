@@ -12,6 +12,7 @@ namespace lbm {
 constexpr int Q = 27;
 constexpr int MAXM = LBM_MAX_SPECIES;
 constexpr int MAXR = LBM_MAX_REACTIONS;
+constexpr int MAXORD = LBM_MAX_ORDER;
 
 // Read-only constant tables, uploaded into the workspace at create time and read
 // with uniform loads by every kernel.
@@ -31,6 +32,10 @@ struct Tables {
   int32_t rev[MAXR];
   int32_t nu_r[MAXR][MAXM];
   int32_t nu_p[MAXR][MAXM];
+  double dnu_a[MAXR][MAXM];             // nu'' - nu' per species
+  int32_t nreac[MAXR], nprod[MAXR];     // molecules on each side
+  int32_t reac_idx[MAXR][MAXORD];       // their species, repeated by coefficient
+  int32_t prod_idx[MAXR][MAXORD];
   double ln_c0_const;         // ln(p0 * 1e-6 / R_U): ln c0(T) = ln_c0_const - ln T (mol/cm^3)
   double omega, omega1;
 };
