@@ -117,6 +117,27 @@ def test_mass_unbalanced_reaction_rejected(lib):
     assert st == -1 and "mass" in msg
 
 
+def test_reaction_order_limit(lib):
+    """Stoichiometric coefficients 0..3 and at most LBM_MAX_ORDER (8) molecules on
+    each side of a reaction (the checks do not need the reaction to be physical)."""
+    prob = W.config1()
+    prob.mech.nu_reac = np.array([[3, 3, 0]], np.int32)
+    prob.mech.nu_prod = np.array([[0, 0, 3]], np.int32)
+    d, keep = _desc(prob)
+    st, _, msg = _ws(lib, d)
+    assert st == 0, msg
+    prob.mech.nu_reac = np.array([[3, 3, 3]], np.int32)
+    prob.mech.nu_prod = np.array([[0, 0, 6]], np.int32)
+    d, keep = _desc(prob)
+    st, _, msg = _ws(lib, d)
+    assert st == -1 and "coefficients" in msg      # 6 exceeds the per-species 0..3
+    prob.mech.nu_reac = np.array([[3, 3, 3]], np.int32)
+    prob.mech.nu_prod = np.array([[3, 3, 3]], np.int32)      # 9 molecules on each side
+    d, keep = _desc(prob)
+    st, _, msg = _ws(lib, d)
+    assert st == -1 and "molecules" in msg
+
+
 def test_create_rejects_bad_workspace_without_device(lib):
     d, keep = _desc(W.config1())
     h = C.c_void_p()
