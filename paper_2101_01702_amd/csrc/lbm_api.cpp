@@ -326,7 +326,10 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   Tables t;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
-  for (int a = 0; a < MAXM; ++a) h->kc.Ra[a] = t.Ra[a];
+  for (int a = 0; a < MAXM; ++a) {
+    h->kc.Ra[a] = t.Ra[a];
+    h->kc.Raf[a] = (float)t.Ra[a];
+  }
   for (int k = 0; k < MAXM * (MAXM - 1) / 2; ++k) {
     h->kc.invDp[k] = t.invDp[k];
     h->kc.invDpf[k] = t.invDpf[k];

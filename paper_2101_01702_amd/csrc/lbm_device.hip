@@ -384,8 +384,11 @@ __device__ __forceinline__ void collide_fg(const CollideConsts &kc, const CollCo
 // O7 for one direction, the stored species a < M-1 (eq. finalNumericalEquations with
 // F_ai of eq. fStar); fa(a) returns the pulled population, store(a, v) writes it.
 // Phi_b(u) - Phi_b(u + du_b) is telescoped over the three axis factors, each factor
-// difference in closed form, so the difference keeps relative precision.  Axis factor
-// of species b: Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.
+// difference in closed form, so the difference keeps relative precision:
+// Psi_c(xi) - Psi_c(xi + d) = d (s_c (2 xi + d) + t_c), with s_0 = 1, t_0 = 0 and
+// s_c = -1/2, t_c = -c/2 for c = +-1 (eq. phis).  Axis factor of species b:
+// Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.  The inter-species term is
+// evaluated in F; the equilibria that carry the species mass in FP64.
 template <int M, typename F, typename FaFn, typename StFn>
 __device__ __forceinline__ void collide_species(const CollideConsts &kc, const CollCoef<M, F> &cc, int cx, int cy,
                                                 int cz, FaFn &&fa, StFn &&store) {
@@ -395,20 +398,23 @@ __device__ __forceinline__ void collide_species(const CollideConsts &kc, const C
          BzT = (cz == 0 ? -1.0 : 0.5) * cc.T;
   double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
          Az = psi_c<double>(cz, u2, u2 * u2);
-  const F u0f = F(u0), u1f = F(u1), u2f = F(u2);
+  const F Axf = F(Ax), Ayf = F(Ay), Azf = F(Az), BxTf = F(BxT), ByTf = F(ByT), BzTf = F(BzT);
+  const F sx = cx == 0 ? F(1) : F(-0.5), sy = cy == 0 ? F(1) : F(-0.5), sz = cz == 0 ? F(1) : F(-0.5);
+  const F tx = F(-0.5) * F(cx), ty = F(-0.5) * F(cy), tz = F(-0.5) * F(cz);
+  const F x2 = F(2) * F(u0), y2 = F(2) * F(u1), z2 = F(2) * F(u2);
   // F_a = sum_b invD_ab dd_b, accumulated over b in increasing order
   F Fa[M - 1];
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
 #pragma unroll
   for (int b = 0; b < M; ++b) {
-    const double Rb = kc.Ra[b];
-    const double ex = Ax + BxT * Rb, ey = Ay + ByT * Rb, ez = Az + BzT * Rb;
-    const F dx = psi_diff<F>(cx, u0f, cc.dv[b][0]), dy = psi_diff<F>(cy, u1f, cc.dv[b][1]),
-            dz = psi_diff<F>(cz, u2f, cc.dv[b][2]);
-    const F exf = F(ex), eyf = F(ey), ezf = F(ez);
-    const F sx = exf - dx, sy = eyf - dy;
-    const F dd = cc.tbw[b] * (dx * eyf * ezf + sx * dy * ezf + sx * sy * dz);
+    F Rb;
+    if constexpr (sizeof(F) == 4) Rb = kc.Raf[b]; else Rb = F(kc.Ra[b]);
+    const F ex = Axf + BxTf * Rb, ey = Ayf + ByTf * Rb, ez = Azf + BzTf * Rb;
+    const F d0 = cc.dv[b][0], d1 = cc.dv[b][1], d2 = cc.dv[b][2];
+    const F dx = d0 * (sx * (x2 + d0) + tx), dy = d1 * (sy * (y2 + d1) + ty), dz = d2 * (sz * (z2 + d2) + tz);
+    const F rx = ex - dx, ry = ey - dy;
+    const F dd = cc.tbw[b] * (dx * ey * ez + rx * dy * ez + rx * ry * dz);
 #pragma unroll
     for (int a = 0; a < M - 1; ++a) {
       if (a == b) continue;
@@ -419,7 +425,7 @@ __device__ __forceinline__ void collide_species(const CollideConsts &kc, const C
       Fa[a] += c * dd;
     }
   }
-  // the axis factors are recomputed below rather than kept from the loop above
+  // the FP64 axis factors are recomputed below rather than kept from above
   opaque(Ax);
   opaque(Ay);
   opaque(Az);
@@ -1225,9 +1231,19 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, int cur, int64
 #pragma unroll
   for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
   const int64_t p = ((int64_t)(gz + g.pz) * g.NY + (gy + g.py)) * g.NX + (gx + g.px);
+  // only the directions along which an interior node pulls from this ghost cell
   int64_t pidx[27];
 #pragma unroll
-  for (int i = 0; i < 27; ++i) pidx[i] = p;
+  for (int i = 0; i < 27; ++i) {
+    const int c[3] = {cx_of(i), cy_of(i), cz_of(i)};
+    bool need = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int t = gc[d] + c[d];
+      need = need && (g.per[d] || (t >= 0 && t < nn[d]));
+    }
+    pidx[i] = need ? p : -1;
+  }
   write_equilibria<M, ST>(*b.tab, static_cast<ST *>(b.pop[cur ^ 1]), g.NPAD, pidx, double(srho[na]), u,
                           b.T[na], Y);
 }

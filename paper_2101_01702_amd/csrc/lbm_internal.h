@@ -46,6 +46,7 @@ struct Tables {
 struct CollideConsts {
   double omega;
   double Ra[MAXM];                       // lattice gas constants kappa R_U / m_a
+  float Raf[MAXM];
   double invDp[MAXM * (MAXM - 1) / 2];   // 1 / D_ab for a < b, row-major pairs
   float invDpf[MAXM * (MAXM - 1) / 2];
 };
