@@ -48,7 +48,7 @@ Geom make_geom(const lbm_desc &d) {
 
 Layout make_layout(const lbm_desc &d, const Geom &g) {
   const size_t st = d.storage == LBM_STORE_F64 ? 8 : 4;   // population storage word size
-  const size_t ct = 8;                                      // compute word size (side channel)
+  const size_t ct = st;                                     // side channel: storage precision
   const size_t S = (size_t)d.n_species + 1;
   const size_t N = (size_t)g.N, M = (size_t)d.n_species;
   Layout L{};

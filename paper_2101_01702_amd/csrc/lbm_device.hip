@@ -131,6 +131,19 @@ __device__ __forceinline__ void opaque_uniform(T *&p) {
   asm volatile("" : "+s"(p));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its own
+// L2.  The lattice kernels read rows y-1, y, y+1 of the side fields and corrections,
+// so the workgroup -> tile mapping gives each XCD a contiguous range of tiles: rows
+// that neighbour each other then share an L2.  A bijection on [0, gridDim.x): the
+// first 8 * floor(G / 8) workgroups are regrouped, the rest keep their index.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int64_t xcd_tile() {
+  const int64_t G = gridDim.x, k = blockIdx.x;
+  const int64_t q = G / NUM_XCD;
+  if (k >= q * NUM_XCD) return k;
+  return (k % NUM_XCD) * q + k / NUM_XCD;
+}
+
 // neighbour for the isotropic gradient: periodic wrap or clamp at open faces
 __device__ __forceinline__ int nb_coord(int x, int c, int n, bool periodic) {
   int s = x + c;
@@ -677,7 +690,7 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
   using F = FT<ST>;
   __shared__ double words[SW::WORDS * ISL_BLOCK];
   const IslStash sh{(lds_double *)&words[threadIdx.x]};
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const Tables &tb = *b.tab;
   const int x = (int)(n % g.nx);
@@ -950,21 +963,23 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
   }
   // O5: side channel of the stencils and the ghosts
   {
-    double *sY = static_cast<double *>(b.side_Y), *sw = static_cast<double *>(b.side_w);
-    double *sphi = static_cast<double *>(b.side_phi);
+    // in the storage precision: the corrections computed from them are stored in it
+    ST *sY = static_cast<ST *>(b.side_Y), *sw = static_cast<ST *>(b.side_w);
+    ST *sphi = static_cast<ST *>(b.side_phi);
     const double wc = 0.5 * (2.0 - om1) * P;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      sY[a * N + n] = sh.r(SW::RS + a) * inv_rho;
-      sw[a * N + n] = wc * Ha[a];
+      sY[a * N + n] = ST(sh.r(SW::RS + a) * inv_rho);
+      sw[a * N + n] = ST(wc * Ha[a]);
     }
     const double uu[3] = {u0, u1, u2};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) sphi[d * N + n] = rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d];
+    for (int d = 0; d < 3; ++d)
+      sphi[d * N + n] = ST(rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d]);
     if (open_any) {
-      static_cast<double *>(b.side_rho)[n] = rho;
+      static_cast<ST *>(b.side_rho)[n] = ST(rho);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) static_cast<double *>(b.side_u)[d * N + n] = uu[d];
+      for (int d = 0; d < 3; ++d) static_cast<ST *>(b.side_u)[d * N + n] = ST(uu[d]);
     }
     b.T[n] = T;
     if (anom) atomicOr(b.status, anom);
@@ -979,7 +994,7 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
 template <int M, typename ST>
 __global__ __launch_bounds__(MAIN_BLOCK) void k_collide(Geom g, Buffers b, CollideConsts kc, int cur) {
   using F = FT<ST>;
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx);
   const int y = (int)((n / g.nx) % g.ny);
@@ -1025,12 +1040,12 @@ __global__ __launch_bounds__(MAIN_BLOCK) void k_collide(Geom g, Buffers b, Colli
 // ---- psi_alpha = (1/omega - 1/2) d_alpha phi_alpha (isotropic gradient) ------------
 template <typename RT>
 __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const RT *phi = static_cast<const RT *>(b.side_phi);
   const int64_t N = g.N;
-  const RT coef = RT(1.0 / b.tab->omega - 0.5);
+  const double coef = 1.0 / b.tab->omega - 0.5;
   int xs[3], ys[3], zs[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1038,25 +1053,25 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
     ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
     zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
   }
-  RT acc[3] = {0, 0, 0};
+  double acc[3] = {0, 0, 0};
   static_for<27>([&](auto Ic) {
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
-    constexpr RT w = RT(3.0 * wgt(I));
-    if constexpr (cx != 0) acc[0] += (cx * w) * phi[0 * N + nn];
-    if constexpr (cy != 0) acc[1] += (cy * w) * phi[1 * N + nn];
-    if constexpr (cz != 0) acc[2] += (cz * w) * phi[2 * N + nn];
+    constexpr double w = 3.0 * wgt(I);
+    if constexpr (cx != 0) acc[0] += (cx * w) * double(phi[0 * N + nn]);
+    if constexpr (cy != 0) acc[1] += (cy * w) * double(phi[1 * N + nn]);
+    if constexpr (cz != 0) acc[2] += (cz * w) * double(phi[2 * N + nn]);
   });
   RT *psi = static_cast<RT *>(b.psi);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) psi[d * N + n] = coef * acc[d];
+  for (int d = 0; d < 3; ++d) psi[d * N + n] = RT(coef * acc[d]);
 }
 
 // ---- X_alpha = -d_alpha psi_alpha; Cg = sum_a w_a grad Y_a ---------------------------
 template <int M, typename RT, typename CT>
 __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const RT *psi = static_cast<const RT *>(b.psi);
@@ -1070,22 +1085,23 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
     ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
     zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
   }
-  RT wa[M];
+  // side fields in RT, sums in FP64
+  double wa[M];
 #pragma unroll
-  for (int a = 0; a < M; ++a) wa[a] = wf[a * N + n];
-  RT X[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+  for (int a = 0; a < M; ++a) wa[a] = double(wf[a * N + n]);
+  double X[3] = {0, 0, 0}, C[3] = {0, 0, 0};
   static_for<27>([&](auto Ic) {
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     if constexpr (I != 13) {
       const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
-      constexpr RT w = RT(3.0 * wgt(I));
-      if constexpr (cx != 0) X[0] -= (cx * w) * psi[0 * N + nn];
-      if constexpr (cy != 0) X[1] -= (cy * w) * psi[1 * N + nn];
-      if constexpr (cz != 0) X[2] -= (cz * w) * psi[2 * N + nn];
-      RT hy = RT(0);
+      constexpr double w = 3.0 * wgt(I);
+      if constexpr (cx != 0) X[0] -= (cx * w) * double(psi[0 * N + nn]);
+      if constexpr (cy != 0) X[1] -= (cy * w) * double(psi[1 * N + nn]);
+      if constexpr (cz != 0) X[2] -= (cz * w) * double(psi[2 * N + nn]);
+      double hy = 0.0;
 #pragma unroll
-      for (int a = 0; a < M; ++a) hy += wa[a] * Yf[a * N + nn];
+      for (int a = 0; a < M; ++a) hy += wa[a] * double(Yf[a * N + nn]);
       if constexpr (cx != 0) C[0] += (cx * w) * hy;
       if constexpr (cy != 0) C[1] += (cy * w) * hy;
       if constexpr (cz != 0) C[2] += (cz * w) * hy;
@@ -1324,7 +1340,7 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 #define LBM_CASE(MM)                                                              \
   case MM:                                                                        \
     return store == LBM_STORE_F64 ? K<MM, double, double>::run(args...)           \
-                                  : K<MM, float, double>::run(args...);
+                                  : K<MM, float, float>::run(args...);
   switch (M) {
     LBM_CASE(2) LBM_CASE(3) LBM_CASE(4) LBM_CASE(5) LBM_CASE(6) LBM_CASE(7) LBM_CASE(8) LBM_CASE(9)
     LBM_CASE(10)
@@ -1405,8 +1421,10 @@ hipError_t launch_collide(const Geom &g, const Buffers &b, const CollideConsts &
 }
 
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {
-  (void)store;
-  hipLaunchKernelGGL((k_psi<double>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+  if (store == LBM_STORE_F64)
+    hipLaunchKernelGGL((k_psi<double>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+  else
+    hipLaunchKernelGGL((k_psi<float>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
   return hipGetLastError();
 }
 

@@ -67,7 +67,7 @@ struct Buffers {
   const Tables *tab;
   void *pop[2];               // [S][27][NPAD] storage type
   double *T;                  // [N] stored temperature
-  void *side_Y;               // [M][N] compute type: mass fractions
+  void *side_Y;               // [M][N] storage type: mass fractions
   void *side_w;               // [M][N]: (2 - omega1)/2 * P * H_a
   void *side_phi;             // [3][N]: argument of the isotropy correction
   void *side_rho;             // [N]   density (ghost equilibria)
