@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "reactive MLUPS & % of HBM peak at stated error vs FP64; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_collide_sphere3d_256.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_sphere3d_256.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01702_amd", "csrc", "lbm_device.hip")
 
 
@@ -150,11 +150,10 @@ def main():
     mlups = N * args.steps / wall / 1e6
     ms_per_step = wall * 1e3 / args.steps
     # Algorithmic bytes per node of the step: every population of the M+1 sets read
-    # once and written once.  Per kernel: the collide-and-stream kernel moves exactly
-    # these; the node-local kernel has to read the populations once; the stencil and
-    # ghost kernels move no population of the method (their bytes are overhead).
+    # once and written once.  The stream-and-collide kernel moves exactly these; the
+    # stencil and ghost kernels move no population of the method (overhead).
     alg_bytes_node = 2 * 27 * (M + 1) * word
-    kernel_alg_bytes = {"collide": alg_bytes_node, "islands": 27 * (M + 1) * word}
+    kernel_alg_bytes = {"step": alg_bytes_node}
     dominant = max(kernel_ms, key=kernel_ms.get)
     dom_ms = kernel_ms[dominant] / args.steps
     dom_bytes = kernel_alg_bytes.get(dominant, 0)

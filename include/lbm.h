@@ -111,10 +111,10 @@ typedef struct {
 } lbm_desc;
 
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost
- * layer on open axes, temperature, a side channel of node fields for the
- * gradient stencils, the deferred corrections, a per-node collision record
- * (15 + (M-1) FP64 words and 6M-2 storage words) written by the node-local
- * kernel and read by the collide kernel, the constant tables and a status word. */
+ * layer on open axes, temperature (FP64), a side channel of node fields for the
+ * gradient stencils and the ghosts (2M + 7 words) and psi (3 words), the deferred
+ * corrections (6 words), all in the storage precision, the constant tables and a
+ * status word. */
 lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 
 /* Validate the descriptor, copy it, and upload its tables into the caller's
@@ -138,8 +138,8 @@ lbm_status lbm_step(lbm_handle h, int32_t n_steps, void *stream);
 
 /* Same as lbm_step, then waits and returns the summed device time of each kernel
  * kind in ms_out[LBM_NUM_KERNELS] (HIP events around every launch). */
-#define LBM_NUM_KERNELS 5 /* 0 node-local part (moments, temperature, chemistry, Stefan-Maxwell),
-                             1 psi stencil, 2 correction stencil, 3 ghosts, 4 collide and stream */
+#define LBM_NUM_KERNELS 4 /* 0 stream and collide (moments, temperature, chemistry, Stefan-Maxwell,
+                             collision of all sets), 1 psi stencil, 2 correction stencil, 3 ghosts */
 lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms_out);
 
 /* Macroscopic fields of the current (pre-collision) state into device FP64

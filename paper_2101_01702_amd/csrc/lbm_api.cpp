@@ -24,7 +24,7 @@ thread_local std::string g_last_error;
 size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t status, tables, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, rec_d, rec_f, total;
+  size_t status, tables, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, total;
   size_t corr_bytes;
 };
 
@@ -71,9 +71,6 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.psi = take(3 * N * ct);
   L.corr_bytes = 6 * N * st;   // deferred corrections in the storage precision
   L.corr = take(L.corr_bytes);
-  // collision record: 15 + (M - 1) FP64 words and 6 M - 2 words in the storage precision
-  L.rec_d = take((15 + (M - 1)) * N * 8);
-  L.rec_f = take((6 * M - 2) * N * st);
   L.total = off;
   return L;
 }
@@ -321,8 +318,6 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   b.side_u = ws + L.side_u;
   b.psi = ws + L.psi;
   b.corr = ws + L.corr;
-  b.rec_d = ws + L.rec_d;
-  b.rec_f = ws + L.rec_f;
   Tables t;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
@@ -392,8 +387,7 @@ static lbm_status run_steps(lbm_handle h, int32_t n_steps, hipStream_t st, float
   hipError_t e = hipSuccess;
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     const int cur = h->cur;
-    e = timed(0, [&] { return launch_islands(h->g, h->b, store, cur, st); });
-    if (e == hipSuccess) e = timed(4, [&] { return launch_collide(h->g, h->b, h->kc, store, cur, st); });
+    e = timed(0, [&] { return launch_step(h->g, h->b, h->kc, store, cur, st); });
     if (e == hipSuccess) e = timed(3, [&] { return launch_ghost(h->g, h->b, store, cur, st); });
     if (e == hipSuccess) e = timed(1, [&] { return launch_psi(h->g, h->b, store, st); });
     if (e == hipSuccess) e = timed(2, [&] { return launch_corr(h->g, h->b, store, st); });

@@ -332,8 +332,7 @@ __device__ __forceinline__ void store_rt(void *base, int64_t idx, RT v) {
 }
 
 // ---- the step --------------------------------------------------------------------
-constexpr int MAIN_BLOCK = 256;   // collide kernel
-constexpr int ISL_BLOCK = 128;    // node-local kernel
+constexpr int ISL_BLOCK = 128;    // step kernel
 
 // Per-thread LDS words of the node-local kernel (word w of thread t at w * ISL_BLOCK
 // + t: conflict-free).  Values that live across the chemistry and the Stefan-Maxwell
@@ -353,6 +352,11 @@ struct IslWords {
 // the stored values in registers instead of reading them back, nor takes the LDS
 // stores for stores that could change the constant tables in global memory.
 typedef __attribute__((address_space(3))) volatile double lds_double;
+
+// Phase boundary for the instruction scheduler (emits no instruction): the values a
+// later phase reads back from LDS are not pulled up into an earlier one, where they
+// would stay live across its register-heavy work.
+__device__ __forceinline__ void phase_boundary() { __builtin_amdgcn_sched_barrier(0); }
 struct IslStash {
   lds_double *p;   // &words[tid]
   __device__ __forceinline__ void w(int k, double v) const { p[k * ISL_BLOCK] = v; }
@@ -450,67 +454,6 @@ __device__ __forceinline__ void collide_species(const CollideConsts &kc, const C
     const double Ra = kc.Ra[a];
     const double phe = (Ax + BxT * Ra) * (Ay + ByT * Ra) * (Az + BzT * Ra);
     store(a, double(cc.omb[a]) * fa(a) + cc.ca[a] * phe + double(cc.rcoef[a] * Fa[a]));
-  }
-}
-
-// ---- per-node collision record (written by k_islands, read by k_collide) ---------
-// SoA, N entries per word.  FP64 words keep the zeroth moments exact: rho, u, R T and
-// the g coefficients that enter sum_i g_i', and (1 - 2 beta_a), (2 beta_a rho_a +
-// rho_dot_a); the remaining words are in the precision F of the inter-species term.
-template <int M>
-struct RecLayout {
-  static constexpr int RHO = 0, U = 1, ZETA = 4, GA0 = 5, GA1 = 6, GA2 = 9, CA = 15;
-  static constexpr int DWORDS = CA + M - 1;
-  static constexpr int DV = 0, TBW = 3 * M, RC = 4 * M, OMB = 5 * M - 1;
-  static constexpr int FWORDS = OMB + M - 1;
-};
-
-// the words of the record that the f and g collision uses
-template <int M, typename F>
-__device__ __forceinline__ void load_record_fg(const Buffers &b, int64_t n, int64_t N, CollCoef<M, F> &cc) {
-  using RL = RecLayout<M>;
-  const double *rd = static_cast<const double *>(b.rec_d);
-  const uint32_t i = (uint32_t)n;
-  cc.rho = ld(rd + RL::RHO * N, i);
-  cc.u0 = ld(rd + (RL::U + 0) * N, i);
-  cc.u1 = ld(rd + (RL::U + 1) * N, i);
-  cc.u2 = ld(rd + (RL::U + 2) * N, i);
-  cc.zeta = ld(rd + RL::ZETA * N, i);
-  cc.gA0 = ld(rd + RL::GA0 * N, i);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) cc.gA1[d] = ld(rd + (RL::GA1 + d) * N, i);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) cc.gA2[k] = ld(rd + (RL::GA2 + k) * N, i);
-}
-
-// the words of the record that the species collision uses; R_a T from the stored T
-template <int M, typename F>
-__device__ __forceinline__ void load_record_species(const CollideConsts &kc, const Buffers &b, int64_t n, int64_t N,
-                                                    CollCoef<M, F> &cc) {
-  using RL = RecLayout<M>;
-  const double *rd = static_cast<const double *>(b.rec_d);
-  const F *rf = static_cast<const F *>(b.rec_f);
-  const double *Tp = b.T;
-  // issued here, not hoisted above the f and g pass
-  opaque_uniform(rd);
-  opaque_uniform(rf);
-  opaque_uniform(Tp);
-  const uint32_t i = (uint32_t)n;
-  cc.u0 = ld(rd + (RL::U + 0) * N, i);
-  cc.u1 = ld(rd + (RL::U + 1) * N, i);
-  cc.u2 = ld(rd + (RL::U + 2) * N, i);
-  cc.T = ld(Tp, i);
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    cc.omb[a] = ld(rf + (RL::OMB + a) * N, i);
-    cc.ca[a] = ld(rd + (RL::CA + a) * N, i);
-    cc.rcoef[a] = ld(rf + (RL::RC + a) * N, i);
-  }
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) cc.dv[a][d] = ld(rf + (RL::DV + 3 * a + d) * N, i);
-    cc.tbw[a] = ld(rf + (RL::TBW + a) * N, i);
   }
 }
 
@@ -679,27 +622,22 @@ __device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, do
   }
 }
 
-// Step, part 1: moments of the pulled state (O1) and everything of the collision that
-// is local to the node: temperature (O2), production rates (O3), Stefan-Maxwell
-// solve (O4), the collision coefficients, and the side channel of the stencils (O5).
-// No global store happens before the end of the kernel, so that the constant tables
-// are read with scalar loads throughout.
+// Moments of the pulled state (O1) and everything of the collision that is local to the
+// node: temperature (O2), production rates (O3), Stefan-Maxwell solve (O4), the
+// collision coefficients cc, and the side channel of the stencils (O5).  No global
+// store happens before the side channel at the end, so that the constant tables are
+// read with scalar loads throughout.
 template <int M, typename ST>
-__global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cur) {
+__device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, const IslStash &sh, int64_t n, int x,
+                                           int y, int z, int cur, CollCoef<M, FT<ST>> &cc) {
   using SW = IslWords<M>;
   using F = FT<ST>;
-  __shared__ double words[SW::WORDS * ISL_BLOCK];
-  const IslStash sh{(lds_double *)&words[threadIdx.x]};
-  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
-  if (n >= g.N) return;
   const Tables &tb = *b.tab;
-  const int x = (int)(n % g.nx);
-  const int y = (int)((n / g.nx) % g.ny);
-  const int z = (int)(n / ((int64_t)g.nx * g.ny));
   const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
   const ST *__restrict__ corr = static_cast<const ST *>(b.corr);
   const int64_t N = g.N;
   const double T0 = b.T[n];
+  (void)N;
 
   // O1: moments; the loads of direction i+1 are in flight while direction i is summed
   Macro<M> m;
@@ -751,6 +689,7 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
     for (int d = 0; d < 3; ++d) m.du0[M - 1][d] = tiny ? 0.0 : jM[d] * inv - m.u[d];
   }
 
+  phase_boundary();
   uint32_t anom = 0;
   const double rho = m.rho;
   const double inv_rho = 1.0 / rho;
@@ -812,6 +751,7 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
 #pragma unroll
     for (int d = 0; d < 3; ++d) du[a][d] = m.du0[a][d];
 
+  phase_boundary();
   // O3: production rates (mass action, K_c from the NASA-7 Gibbs function).  The
   // concentrations sit in LDS with a constant 1 after them, so that each side of a
   // reaction is a product over a padded list of species indices.
@@ -847,6 +787,7 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
     for (int a = 0; a < M - 1; ++a) sh.w(SW::RD + a, tb.rdot_scale[a] * wd[a]);
   }
 
+  phase_boundary();
   // O4: Stefan-Maxwell relaxation and diffusion velocities (eqs. tauab, transform1).
   // The matrix is A_ab = -K_ab Y_b / 2 (a != b), A_aa = 1 + 1/(2 tau_a), with the
   // symmetric 1/tau_ab = K_ab = (R_a T)(R_b T) / ((R T) D_ab).  A = B diag(Y) with B
@@ -908,133 +849,147 @@ __global__ __launch_bounds__(ISL_BLOCK) void k_islands(Geom g, Buffers b, int cu
     }
   }
 
-  // O7: collision coefficients, written to the record together with the side channel.
-  // Everything taken from the constant tables is read before the first store.
-  double Ha[M], za[M];
+  // the solution is materialised here: otherwise the solve is sunk into its uses below
+  // and its whole working set stays live into the coefficient phase
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
-    za[a] = tb.Ra[a] * T;
-    Ha[a] = za[a] * h_RT(tb.nasa[a], T, invT);
-  }
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) opaque(du[a][d]);
+  phase_boundary();
+  // O7: collision coefficients.  Everything taken from the constant tables is read
+  // before the first store.
+  double Ha[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) Ha[a] = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
   const double om1 = tb.omega1;
   const bool open_any = tb.open_any != 0;
-  using RL = RecLayout<M>;
-  double *rd = static_cast<double *>(b.rec_d);
-  F *rf = static_cast<F *>(b.rec_f);
   {
     const double inv_zeta = 1.0 / zeta;
     double hyd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
+      const double za = tb.Ra[a] * T;
       const double ra = sh.r(SW::RS + a);
       const double HY = Ha[a] * ra * inv_rho;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         hyd[d] += HY * du[a][d];
-        rf[(RL::DV + 3 * a + d) * N + n] = F(du[a][d]);
+        cc.dv[a][d] = F(du[a][d]);
       }
-      rf[(RL::TBW + a) * N + n] = F(ra * za[a]);
+      cc.tbw[a] = F(ra * za);
       if (a < M - 1) {
         const double bt = sh.r(SW::BETA + a);
         const double rdot = sh.r(SW::RD + a);
         // with 1 - 2 beta_a rounded to F, the source coefficient takes 2 beta_a from
         // the rounded value, so that sum_i f_ai' = rho_a + rho_dot_a holds exactly
-        const F omb = F(1.0 - 2.0 * bt);
-        double ca;
+        cc.omb[a] = F(1.0 - 2.0 * bt);
         if constexpr (sizeof(F) == 4)
-          ca = (1.0 - double(omb)) * ra + rdot;
+          cc.ca[a] = (1.0 - double(cc.omb[a])) * ra + rdot;
         else
-          ca = 2.0 * bt * ra + rdot;
-        rf[(RL::OMB + a) * N + n] = omb;
-        rd[(RL::CA + a) * N + n] = ca;
-        rf[(RL::RC + a) * N + n] = F((bt - 1.0) * ra * inv_rho * za[a] * inv_zeta);
+          cc.ca[a] = 2.0 * bt * ra + rdot;
+        cc.rcoef[a] = F((bt - 1.0) * ra * inv_rho * za * inv_zeta);
       }
     }
-    rd[RL::RHO * N + n] = rho;
-    rd[(RL::U + 0) * N + n] = u0;
-    rd[(RL::U + 1) * N + n] = u1;
-    rd[(RL::U + 2) * N + n] = u2;
-    rd[RL::ZETA * N + n] = zeta;
-    rd[RL::GA0 * N + n] = sh.r(SW::G + 0);
+    cc.rho = rho;
+    cc.u0 = u0;
+    cc.u1 = u1;
+    cc.u2 = u2;
+    cc.zeta = zeta;
+    cc.T = T;
+    cc.gA0 = sh.r(SW::G + 0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) rd[(RL::GA1 + d) * N + n] = sh.r(SW::G + 1 + d) + 3.0 * om1 * rho * hyd[d];
+    for (int d = 0; d < 3; ++d) cc.gA1[d] = sh.r(SW::G + 1 + d) + 3.0 * om1 * rho * hyd[d];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) rd[(RL::GA2 + k) * N + n] = sh.r(SW::G + 4 + k);
+    for (int k = 0; k < 6; ++k) cc.gA2[k] = sh.r(SW::G + 4 + k);
   }
   // O5: side channel of the stencils and the ghosts
   {
     // in the storage precision: the corrections computed from them are stored in it
     ST *sY = static_cast<ST *>(b.side_Y), *sw = static_cast<ST *>(b.side_w);
     ST *sphi = static_cast<ST *>(b.side_phi);
+    const uint32_t i = (uint32_t)n;
     const double wc = 0.5 * (2.0 - om1) * P;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      sY[a * N + n] = ST(sh.r(SW::RS + a) * inv_rho);
-      sw[a * N + n] = ST(wc * Ha[a]);
+      st(sY + a * N, i, ST(sh.r(SW::RS + a) * inv_rho));
+      st(sw + a * N, i, ST(wc * Ha[a]));
     }
     const double uu[3] = {u0, u1, u2};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      sphi[d * N + n] = ST(rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d]);
+      st(sphi + d * N, i, ST(rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d]));
     if (open_any) {
-      static_cast<ST *>(b.side_rho)[n] = ST(rho);
+      st(static_cast<ST *>(b.side_rho), i, ST(rho));
 #pragma unroll
-      for (int d = 0; d < 3; ++d) static_cast<ST *>(b.side_u)[d * N + n] = ST(uu[d]);
+      for (int d = 0; d < 3; ++d) st(static_cast<ST *>(b.side_u) + d * N, i, ST(uu[d]));
     }
-    b.T[n] = T;
+    st(b.T, i, T);
     if (anom) atomicOr(b.status, anom);
   }
 }
 
-// Step, part 2: one streaming pass, each population pulled, collided and stored; first
-// f and g over the 27 directions, then the species, so that each pass holds only its
-// own coefficients.  The loads of direction i+1 are in flight while direction i is
-// collided; the loops are unrolled twice so that the two sets of pulled values
+// O7 + O8 for f and g over the 27 directions: the loads of direction i+1 are in flight
+// while direction i is collided; unrolled twice so that the two sets of pulled values
 // alternate in registers.
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void fg_pass(const Geom &g, const ST *__restrict__ src, ST *__restrict__ dst,
+                                        const ST *__restrict__ corr, const CollideConsts &kc,
+                                        const CollCoef<M, F> &cc, int x, int y, int z, uint32_t pself) {
+  const int64_t NPAD = g.NPAD;
+  PulledFG<ST> pa, pb;
+  pull_fg<M, ST>(g, src, corr, x, y, z, 0, pa);
+#pragma unroll 1
+  for (int i = 0; i < Q - 1; i += 2) {
+    pull_fg<M, ST>(g, src, corr, x, y, z, i + 1, pb);
+    collide_pulled_fg<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
+    pull_fg<M, ST>(g, src, corr, x, y, z, i + 2, pa);
+    collide_pulled_fg<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
+  }
+  collide_pulled_fg<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
+}
+
+// O7 + O8 for the stored species, pipelined like fg_pass
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void species_pass(const Geom &g, const ST *__restrict__ src, ST *__restrict__ dst,
+                                             const CollideConsts &kc, CollCoef<M, F> &cc, int x, int y, int z,
+                                             uint32_t pself) {
+  const int64_t NPAD = g.NPAD;
+  PulledS<M, ST> pa, pb;
+  pull_species<M, ST>(g, src, x, y, z, 0, pa);
+#pragma unroll 1
+  for (int i = 0; i < Q - 1; i += 2) {
+    pull_species<M, ST>(g, src, x, y, z, i + 1, pb);
+    opaque_species<M, F>(cc);
+    collide_pulled_species<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
+    pull_species<M, ST>(g, src, x, y, z, i + 2, pa);
+    opaque_species<M, F>(cc);
+    collide_pulled_species<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
+  }
+  collide_pulled_species<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
+}
+
+// Fused step: the node-local part, then the collide passes from the coefficients in
+// registers.  The populations are read twice, the second time mostly from cache, and
+// no record goes through memory.
 template <int M, typename ST>
-__global__ __launch_bounds__(MAIN_BLOCK) void k_collide(Geom g, Buffers b, CollideConsts kc, int cur) {
+__global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, CollideConsts kc, int cur) {
   using F = FT<ST>;
+  __shared__ double words[IslWords<M>::WORDS * ISL_BLOCK];
+  const IslStash sh{(lds_double *)&words[threadIdx.x]};
   const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx);
   const int y = (int)((n / g.nx) % g.ny);
   const int z = (int)(n / ((int64_t)g.nx * g.ny));
+  CollCoef<M, F> cc;
+  node_local<M, ST>(g, b, sh, n, x, y, z, cur, cc);
   const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
   ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
   const ST *__restrict__ corr = static_cast<const ST *>(b.corr);
-  const int64_t N = g.N, NPAD = g.NPAD;
   const uint32_t pself = ((uint32_t)(z + g.pz) * (uint32_t)g.NY + (uint32_t)(y + g.py)) * (uint32_t)g.NX +
                          (uint32_t)(x + g.px);
-  {
-    CollCoef<M, F> cc;
-    load_record_fg<M, F>(b, n, N, cc);
-    PulledFG<ST> pa, pb;
-    pull_fg<M, ST>(g, src, corr, x, y, z, 0, pa);
-#pragma unroll 1
-    for (int i = 0; i < Q - 1; i += 2) {
-      pull_fg<M, ST>(g, src, corr, x, y, z, i + 1, pb);
-      collide_pulled_fg<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
-      pull_fg<M, ST>(g, src, corr, x, y, z, i + 2, pa);
-      collide_pulled_fg<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
-    }
-    collide_pulled_fg<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
-  }
-  {
-    CollCoef<M, F> cc;
-    load_record_species<M, F>(kc, b, n, N, cc);
-    PulledS<M, ST> pa, pb;
-    pull_species<M, ST>(g, src, x, y, z, 0, pa);
-#pragma unroll 1
-    for (int i = 0; i < Q - 1; i += 2) {
-      pull_species<M, ST>(g, src, x, y, z, i + 1, pb);
-      opaque_species<M, F>(cc);
-      collide_pulled_species<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
-      pull_species<M, ST>(g, src, x, y, z, i + 2, pa);
-      opaque_species<M, F>(cc);
-      collide_pulled_species<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
-    }
-    collide_pulled_species<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
-  }
+  fg_pass<M, ST, F>(g, src, dst, corr, kc, cc, x, y, z, pself);
+  species_pass<M, ST, F>(g, src, dst, kc, cc, x, y, z, pself);
 }
 
 // ---- psi_alpha = (1/omega - 1/2) d_alpha phi_alpha (isotropic gradient) ------------
@@ -1350,17 +1305,9 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 }
 
 template <int M, typename ST, typename RT>
-struct RunIslands {
-  static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_islands<M, ST>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b, cur);
-    return hipGetLastError();
-  }
-};
-template <int M, typename ST, typename RT>
-struct RunCollide {
+struct RunStep {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_collide<M, ST>), dim3(blocks_for(g.N, MAIN_BLOCK)), dim3(MAIN_BLOCK), 0, st, g, b, kc,
-                       cur);
+    hipLaunchKernelGGL((k_step<M, ST>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b, kc, cur);
     return hipGetLastError();
   }
 };
@@ -1411,13 +1358,9 @@ struct RunExport {
 
 }  // namespace
 
-hipError_t launch_islands(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
-  return dispatch<RunIslands>(g.M, store, g, b, cur, st);
-}
-
-hipError_t launch_collide(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
-                          hipStream_t st) {
-  return dispatch<RunCollide>(g.M, store, g, b, kc, cur, st);
+hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                       hipStream_t st) {
+  return dispatch<RunStep>(g.M, store, g, b, kc, cur, st);
 }
 
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {

@@ -74,16 +74,13 @@ struct Buffers {
   void *side_u;               // [3][N] velocity (ghost equilibria)
   void *psi;                  // [3][N]
   void *corr;                 // [6][N]: X (3), then the energy-flux correction (3)
-  void *rec_d;                // per-node collision record, FP64 words
-  void *rec_f;                // per-node collision record, words in the storage precision
 };
 
 // launchers (lbm_device.hip)
 hipError_t launch_init(const Geom &g, const Buffers &b, int store, const double *rho, const double *u,
                        const double *T, const double *Y, int cur, hipStream_t st);
-hipError_t launch_islands(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
-hipError_t launch_collide(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
-                          hipStream_t st);
+hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                       hipStream_t st);
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_ghost(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);

@@ -19,8 +19,8 @@ LBM_OK = 0
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP",
                 -4: "LBM_ERR_WORKSPACE", -5: "LBM_ERR_DEVICE_ANOMALY"}
 STORE_F64, STORE_F32 = 0, 1
-NUM_KERNELS = 5
-KERNEL_NAMES = ("islands", "psi", "corr", "ghost", "collide")
+NUM_KERNELS = 4
+KERNEL_NAMES = ("step", "psi", "corr", "ghost")
 ANOM_NONFINITE, ANOM_NEWTON, ANOM_NEG_DENSITY = 1, 2, 4
 MAX_SPECIES = 10
 MAX_REACTIONS = 64

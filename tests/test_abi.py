@@ -60,9 +60,8 @@ def test_workspace_size_config1(lib):
     S, N, M = 4, 512, 3
     pops = 2 * S * 27 * N * 8
     # beyond the two population copies: temperature, side channel (2M + 7 words),
-    # psi (3), corrections (6), collision record (15 + (M-1) + 6M-2) words per node,
-    # plus the constant tables
-    per_node = 8 * (1 + 2 * M + 7 + 3 + 6 + 15 + (M - 1) + 6 * M - 2)
+    # psi (3) and corrections (6) words per node, plus the constant tables
+    per_node = 8 * (1 + 2 * M + 7 + 3 + 6)
     assert pops + per_node * N < n < pops + per_node * N + 200_000
 
 

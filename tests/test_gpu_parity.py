@@ -188,7 +188,8 @@ def test_timed_step_matches_step(lbm_mod):
     b = lbm_mod.Solver(prob, storage=W.STORE_F32).init()
     a.step(20)
     ms = b.step_timed(20)
-    assert ms["islands"] > 0 and ms["collide"] > 0
+    assert set(ms) == {"step", "psi", "corr", "ghost"}
+    assert ms["step"] > 0 and all(v >= 0 for v in ms.values())
     np.testing.assert_array_equal(a.populations(np.arange(prob.N))[0], b.populations(np.arange(prob.N))[0])
 
 
