@@ -76,17 +76,18 @@ def cpu_baseline(seconds=12.0):
             "sample": f"32^3 crop of the same spherical flame (M=9, R=19, FP64), {steps} steps, {dt:.1f} s"}
 
 
-def error_vs_f64(lbm, W, steps=100):
-    """Normwise field error of FP32 storage against FP64 storage on a 32^3 crop."""
+def error_vs_f64(lbm, W, storage, steps=100):
+    """Normwise field error of the benchmarked storage against FP64 storage on a 32^3
+    crop."""
     import numpy as np
     prob = W.sphere3d(shape=(32, 32, 32))
     out = {}
-    for st in (W.STORE_F64, W.STORE_F32):
+    for st in (W.STORE_F64, storage):
         s = lbm.Solver(prob, storage=st).init()
         s.step(steps)
         out[st] = s.macros()
         s.close()
-    a, b = out[W.STORE_F32], out[W.STORE_F64]
+    a, b = out[storage], out[W.STORE_F64]
     zeta = prob.kappa * W.R_U * prob.T.min() / (1e-3 / (prob.Y[:, 0] / prob.mech.molar_mass).sum())
     errs = {}
     for k in ("rho", "T", "P"):
@@ -104,7 +105,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256, help="lattice edge (256 = the benchmarked workload)")
-    ap.add_argument("--storage", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--storage", choices=("f32", "f64", "f16dev", "bf16dev"), default="f32",
+                    help="population storage (f16dev/bf16dev: 16-bit deviations from the reference state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--copy-only", action="store_true", help="run only the copy kernel (counter calibration)")
@@ -125,8 +127,9 @@ def main():
         print(json.dumps({"copy_ceiling_GBps": round(copy_ceiling_gbs(torch, dev), 1), "bytes": 2 * (4 << 30)}))
         return
 
-    storage = W.STORE_F32 if args.storage == "f32" else W.STORE_F64
-    word = 4 if storage == W.STORE_F32 else 8
+    storage = {"f32": W.STORE_F32, "f64": W.STORE_F64, "f16dev": W.STORE_F16_DEV,
+               "bf16dev": W.STORE_BF16_DEV}[args.storage]
+    word = {W.STORE_F64: 8, W.STORE_F32: 4}.get(storage, 2)
     prob = W.sphere3d(n=args.n, storage=storage)
     M = prob.M
     N = prob.N
@@ -178,7 +181,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"spherical flame {args.n}^3 D3Q27, 9 species, 19 reversible reactions, "
-                               f"{args.storage} population storage, FP64 arithmetic",
+                               f"{args.storage} population storage, FP64 node-local arithmetic",
                    "lattice": [args.n] * 3, "species": M, "reactions": 19, "storage": args.storage,
                    "parallelism": "single GPU"},
         "roofline": roofline,
@@ -187,7 +190,7 @@ def main():
         "anomaly_bits": anomaly,
     }
     if not args.no_error_check:
-        out["error_vs_f64"] = error_vs_f64(lbm, W)
+        out["error_vs_f64"] = error_vs_f64(lbm, W, storage)
     out["copy_ceiling_GBps"] = round(copy_ceiling_gbs(torch, dev), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

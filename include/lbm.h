@@ -52,9 +52,13 @@ enum {
   LBM_BC_OPEN_EQ_U0 = 2 /* same with ghost velocity 0                            */
 };
 
-/* population storage; FP64 islands (temperature inversion, thermo, production
- * rates, Stefan-Maxwell solve) are double precision in both */
-enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1 };
+/* population storage; the node-local work (temperature inversion, thermo,
+ * production rates, Stefan-Maxwell solve) is double precision in all of them.
+ * The deviation formats store (f_i - f_ref,i) / sc per population in 16 bits,
+ * with f_ref the equilibrium of each set at the caller's quiescent reference state
+ * (lbm_desc.ref_state) and sc the reference magnitude of the set; their side
+ * fields and corrections are FP32. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16_DEV = 2, LBM_STORE_BF16_DEV = 3 };
 
 /* anomaly bits latched on the device, read by lbm_status_sync */
 enum {
@@ -91,6 +95,9 @@ enum {
  *   rho_ref         g/cm^3 per lattice density unit (chemistry)
  *   p0              standard pressure of the thermo data, Pa (Sec. 4: 1 atm)
  *   storage         LBM_STORE_*
+ *   ref_state       [2 + M] host array (rho in lattice units, T in K, Y[M] mass
+ *                   fractions summing to 1) of the reference state at rest of the
+ *                   deviation formats; may be NULL for LBM_STORE_F64 / _F32
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -108,6 +115,7 @@ typedef struct {
   double kappa, dt_phys, rho_ref, p0;
   int32_t storage;
   int32_t reserved;
+  const double *ref_state;
 } lbm_desc;
 
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost

@@ -47,8 +47,8 @@ Geom make_geom(const lbm_desc &d) {
 }
 
 Layout make_layout(const lbm_desc &d, const Geom &g) {
-  const size_t st = d.storage == LBM_STORE_F64 ? 8 : 4;   // population storage word size
-  const size_t ct = st;                                     // side channel: storage precision
+  const size_t st = d.storage == LBM_STORE_F64 ? 8 : (d.storage == LBM_STORE_F32 ? 4 : 2);  // populations
+  const size_t ct = d.storage == LBM_STORE_F64 ? 8 : 4;   // side channel, psi and corrections
   const size_t S = (size_t)d.n_species + 1;
   const size_t N = (size_t)g.N, M = (size_t)d.n_species;
   Layout L{};
@@ -69,7 +69,7 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.side_rho = take(N * ct);
   L.side_u = take(3 * N * ct);
   L.psi = take(3 * N * ct);
-  L.corr_bytes = 6 * N * st;   // deferred corrections in the storage precision
+  L.corr_bytes = 6 * N * ct;   // deferred corrections
   L.corr = take(L.corr_bytes);
   L.total = off;
   return L;
@@ -141,8 +141,20 @@ bool validate(const lbm_desc *d, std::string *err) {
   if (!(d->dt_phys >= 0.0) || !std::isfinite(d->dt_phys)) return fail(err, "dt_phys must be >= 0");
   if (!(d->rho_ref > 0.0) || !std::isfinite(d->rho_ref)) return fail(err, "rho_ref must be > 0");
   if (!(d->p0 > 0.0) || !std::isfinite(d->p0)) return fail(err, "p0 must be > 0");
-  if (d->storage != LBM_STORE_F64 && d->storage != LBM_STORE_F32)
+  if (d->storage < LBM_STORE_F64 || d->storage > LBM_STORE_BF16_DEV)
     return fail(err, "storage = %d is not supported", d->storage);
+  if (d->storage == LBM_STORE_F16_DEV || d->storage == LBM_STORE_BF16_DEV) {
+    if (!d->ref_state) return fail(err, "the deviation formats need ref_state");
+    const double *r = d->ref_state;
+    if (!(r[0] > 0.0) || !std::isfinite(r[0])) return fail(err, "ref_state: density must be > 0");
+    if (!(r[1] > 0.0) || !std::isfinite(r[1])) return fail(err, "ref_state: temperature must be > 0");
+    double ys = 0.0;
+    for (int a = 0; a < M; ++a) {
+      if (!(r[2 + a] >= 0.0) || !std::isfinite(r[2 + a])) return fail(err, "ref_state: Y[%d] must be >= 0", a);
+      ys += r[2 + a];
+    }
+    if (std::fabs(ys - 1.0) > 1e-9) return fail(err, "ref_state: mass fractions sum to %.17g, not 1", ys);
+  }
   return true;
 }
 
@@ -210,6 +222,53 @@ void build_tables(const lbm_desc &d, Tables &t) {
   t.omega1 = d.omega1;
 }
 
+// Reference populations of the deviation formats: the equilibria (eqs. feq, gieq) of
+// every set at the caller's reference state at rest, and per set the scale of the
+// stored deviations.  The scale is 1e-3 of the set's reference magnitude (the mixture
+// density for f and for every species, so that a species absent from the reference
+// can still grow to the mixture density without leaving the 16-bit range).
+void build_reference(const lbm_desc &d, const Tables &t, CollideConsts &kc) {
+  const int M = d.n_species;
+  for (int s = 0; s <= MAXM; ++s) {
+    kc.sc[s] = 1.0f;
+    kc.isc[s] = 1.0f;
+    for (int i = 0; i < Q; ++i) kc.ref[s][i] = 0.0f;
+  }
+  if (d.storage != LBM_STORE_F16_DEV && d.storage != LBM_STORE_BF16_DEV) return;
+  const double rho = d.ref_state[0], T = d.ref_state[1];
+  const double *Y = d.ref_state + 2;
+  double zeta = 0.0, U = 0.0, H = 0.0, za[MAXM];
+  for (int a = 0; a < M; ++a) {
+    const double *n = t.nasa[a];
+    za[a] = t.Ra[a] * T;
+    const double hRT = n[0] + n[1] * T / 2.0 + n[2] * T * T / 3.0 + n[3] * T * T * T / 4.0 +
+                       n[4] * T * T * T * T / 5.0 + n[5] / T;
+    zeta += Y[a] * za[a];
+    U += Y[a] * za[a] * (hRT - 1.0);
+    H += Y[a] * za[a] * hRT;
+  }
+  auto psi0 = [](int c, double z) { return c == 0 ? 1.0 - z : 0.5 * z; };
+  auto w1 = [](int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; };
+  const double theta = 1.0 / 3.0, rhoE = rho * U;
+  double gmag = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    for (int a = 0; a < M - 1; ++a)
+      kc.ref[a][i] = (float)(rho * Y[a] * psi0(cx, za[a]) * psi0(cy, za[a]) * psi0(cz, za[a]));
+    kc.ref[M - 1][i] = (float)(rho * psi0(cx, zeta) * psi0(cy, zeta) * psi0(cz, zeta));
+    // Grad form at rest: R^eq = H rho zeta I, so (R^eq - rho E theta I) : (c c - theta I)
+    // = (H rho zeta - rho E theta)(c^2 - 3 theta)
+    const double c2 = cx * cx + cy * cy + cz * cz;
+    const double g = w1(cx) * w1(cy) * w1(cz) *
+                     (rhoE + (H * rho * zeta - rhoE * theta) * (c2 - 3.0 * theta) / (2.0 * theta * theta));
+    kc.ref[M][i] = (float)g;
+    gmag += std::fabs(g);
+  }
+  for (int s = 0; s < M; ++s) kc.sc[s] = (float)(1e-3 * rho);
+  kc.sc[M] = (float)(1e-3 * gmag);
+  for (int s = 0; s <= M; ++s) kc.isc[s] = 1.0f / kc.sc[s];
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -218,6 +277,7 @@ struct lbm_ctx {
   std::vector<int32_t> nu_r, nu_p;
   std::vector<double> arrh;
   std::vector<uint8_t> rev;
+  std::vector<double> ref_state;
   Geom g{};
   Layout L{};
   Buffers b{};
@@ -288,6 +348,10 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   h->d.nu_prod = R ? h->nu_p.data() : nullptr;
   h->d.arrhenius = R ? h->arrh.data() : nullptr;
   h->d.reversible = R ? h->rev.data() : nullptr;
+  if (desc->ref_state) {
+    h->ref_state.assign(desc->ref_state, desc->ref_state + 2 + M);
+    h->d.ref_state = h->ref_state.data();
+  }
   h->g = make_geom(h->d);
   h->L = make_layout(h->d, h->g);
   if (bytes < h->L.total) {
@@ -325,6 +389,7 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
     h->kc.Ra[a] = t.Ra[a];
     h->kc.Raf[a] = (float)t.Ra[a];
   }
+  build_reference(h->d, t, h->kc);
   for (int k = 0; k < MAXM * (MAXM - 1) / 2; ++k) {
     h->kc.invDp[k] = t.invDp[k];
     h->kc.invDpf[k] = t.invDpf[k];
@@ -356,7 +421,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *d_rho, const double *d_u,
   h->cur = 0;
   hipError_t e = launch_zero(h->b.corr, (int64_t)(h->L.corr_bytes / 4), st);
   if (e == hipSuccess) e = launch_zero(h->b.status, 16, st);
-  if (e == hipSuccess) e = launch_init(h->g, h->b, h->d.storage, d_rho, d_u, d_T, d_Y, h->cur, st);
+  if (e == hipSuccess) e = launch_init(h->g, h->b, h->kc, h->d.storage, d_rho, d_u, d_T, d_Y, h->cur, st);
   if (e != hipSuccess) return hip_fail(h, e, "init");
   return LBM_OK;
 }
@@ -388,7 +453,7 @@ static lbm_status run_steps(lbm_handle h, int32_t n_steps, hipStream_t st, float
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     const int cur = h->cur;
     e = timed(0, [&] { return launch_step(h->g, h->b, h->kc, store, cur, st); });
-    if (e == hipSuccess) e = timed(3, [&] { return launch_ghost(h->g, h->b, store, cur, st); });
+    if (e == hipSuccess) e = timed(3, [&] { return launch_ghost(h->g, h->b, h->kc, store, cur, st); });
     if (e == hipSuccess) e = timed(1, [&] { return launch_psi(h->g, h->b, store, st); });
     if (e == hipSuccess) e = timed(2, [&] { return launch_corr(h->g, h->b, store, st); });
     if (e == hipSuccess) h->cur ^= 1;
@@ -417,7 +482,7 @@ lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms
 lbm_status lbm_macros(lbm_handle h, double *d_rho, double *d_u, double *d_T, double *d_P, double *d_Y,
                       void *stream) {
   if (!h) return arg_fail(nullptr, "handle is NULL");
-  hipError_t e = launch_macros(h->g, h->b, h->d.storage, h->cur, d_rho, d_u, d_T, d_P, d_Y,
+  hipError_t e = launch_macros(h->g, h->b, h->kc, h->d.storage, h->cur, d_rho, d_u, d_T, d_P, d_Y,
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(h, e, "macros");
   return LBM_OK;
@@ -428,7 +493,7 @@ lbm_status lbm_populations(lbm_handle h, const int64_t *d_nodes, int64_t n_nodes
   if (!h) return arg_fail(nullptr, "handle is NULL");
   if (n_nodes < 0) return arg_fail(h, "n_nodes must be >= 0");
   if (n_nodes > 0 && (!d_nodes || !d_out)) return arg_fail(h, "node list and output must not be NULL");
-  hipError_t e = launch_export(h->g, h->b, h->d.storage, h->cur, d_nodes, n_nodes, d_out, d_T_out,
+  hipError_t e = launch_export(h->g, h->b, h->kc, h->d.storage, h->cur, d_nodes, n_nodes, d_out, d_T_out,
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(h, e, "populations");
   return LBM_OK;

@@ -131,6 +131,46 @@ __device__ __forceinline__ void opaque_uniform(T *&p) {
   asm volatile("" : "+s"(p));
 }
 
+// ---- storage formats -------------------------------------------------------------
+// Populations are stored as ST; side fields, psi and corrections as Side; the
+// inter-species term is evaluated in F.  The 16-bit formats store deviations from the
+// reference populations: stored = (f - ref[s][i]) / sc[s].
+template <typename ST>
+struct Fmt {
+  using Side = ST;
+  using F = ST;
+  static constexpr bool dev = false;
+};
+template <>
+struct Fmt<_Float16> {
+  using Side = float;
+  using F = float;
+  static constexpr bool dev = true;
+};
+template <>
+struct Fmt<__bf16> {
+  using Side = float;
+  using F = float;
+  static constexpr bool dev = true;
+};
+
+// value of a stored population of set s along direction i
+template <typename ST>
+__device__ __forceinline__ double pop_val(ST raw, int s, int i, const CollideConsts &kc) {
+  if constexpr (Fmt<ST>::dev)
+    return double(fmaf(kc.sc[s], float(raw), kc.ref[s][i]));
+  else
+    return double(raw);
+}
+// stored form of the population value v of set s along direction i
+template <typename ST>
+__device__ __forceinline__ ST pop_enc(double v, int s, int i, const CollideConsts &kc) {
+  if constexpr (Fmt<ST>::dev)
+    return ST(float((v - double(kc.ref[s][i])) * double(kc.isc[s])));
+  else
+    return ST(v);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its own
 // L2.  The lattice kernels read rows y-1, y, y+1 of the side fields and corrections,
 // so the workgroup -> tile mapping gives each XCD a contiguous range of tiles: rows
@@ -163,15 +203,15 @@ struct Corr {
 // way in every kernel that pulls
 template <int CX, typename ST, typename CT>
 __device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src &r, const Corr<CT> &cr, int cy,
-                                         int cz) {
-  double v = double(ld(base, r.ps));
+                                         int cz, int s, int i, const CollideConsts &kc) {
+  double v = pop_val(ld(base, r.ps), s, i, kc);
   if (r.ns >= 0) {
     const uint32_t ns = (uint32_t)r.ns;
     if constexpr (CX != 0) {
-      if (cy == 0 && cz == 0) v += double(ST(0.5 * CX * double(ld(cr.X, ns))));
+      if (cy == 0 && cz == 0) v += double(CT(0.5 * CX * double(ld(cr.X, ns))));
     } else {
-      if (cy != 0 && cz == 0) v += double(ST(0.5 * cy * double(ld(cr.X + cr.N, ns))));
-      if (cy == 0 && cz != 0) v += double(ST(0.5 * cz * double(ld(cr.X + 2 * cr.N, ns))));
+      if (cy != 0 && cz == 0) v += double(CT(0.5 * cy * double(ld(cr.X + cr.N, ns))));
+      if (cy == 0 && cz != 0) v += double(CT(0.5 * cz * double(ld(cr.X + 2 * cr.N, ns))));
     }
   }
   return v;
@@ -180,16 +220,16 @@ __device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src 
 // pulled value of g with the deferred Fourier-correction flux 3 w_i c_i . Cg
 template <int CX, typename ST, typename CT>
 __device__ __forceinline__ double pull_g(const ST *__restrict__ base, const Src &r, const Corr<CT> &cr, int cy,
-                                         int cz) {
+                                         int cz, int s, int i, const CollideConsts &kc) {
   const double w3 = 3.0 * (w1(CX) * w1(cy) * w1(cz));
-  double v = double(ld(base, r.ps));
+  double v = pop_val(ld(base, r.ps), s, i, kc);
   if (r.ns >= 0) {
     const uint32_t ns = (uint32_t)r.ns;
     double d = 0.0;
     if constexpr (CX != 0) d += CX * double(ld(cr.Cg, ns));
     if (cy != 0) d += cy * double(ld(cr.Cg + cr.N, ns));
     if (cz != 0) d += cz * double(ld(cr.Cg + 2 * cr.N, ns));
-    v += double(ST(w3 * d));
+    v += double(CT(w3 * d));
   }
   return v;
 }
@@ -223,8 +263,10 @@ struct Macro {
 };
 
 template <int M, typename ST>
-__device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict__ pop, const Corr<ST> &cr,
+__device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict__ pop,
+                                             const Corr<typename Fmt<ST>::Side> &cr, const CollideConsts &kc,
                                              int x, int y, int z, Macro<M> &m) {
+  using Side = typename Fmt<ST>::Side;
   const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
   const int64_t NPAD = g.NPAD;
   double rho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
@@ -242,8 +284,8 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
       constexpr int cx = kx - 1;
       const int i = kx + 3 * kyz;
       const Src r = src_from_row(g, row, ax, kx);
-      const double f = pull_f<cx, ST, ST>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-      const double gg = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz);
+      const double f = pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
+      const double gg = pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
       rho += f;
       rE += gg;
       if constexpr (cx != 0) {
@@ -255,7 +297,7 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
       pyz += (cy * cz) * f;
 #pragma unroll
       for (int a = 0; a < M - 1; ++a) {
-        const double fa = (double)ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
+        const double fa = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
         ra[a] += fa;
         if constexpr (cx != 0) jax[a] += cx * fa;
         jay[a] += cy * fa;
@@ -366,7 +408,7 @@ struct IslStash {
 // Precision of the inter-species term F of eq. fStar (a correction whose sum over
 // directions vanishes): FP64 for FP64 storage, FP32 for FP32 storage.
 template <typename ST>
-using FT = ST;
+using FT = typename Fmt<ST>::F;
 
 // coefficients of the collision of one node
 template <int M, typename F>
@@ -483,12 +525,14 @@ __device__ __forceinline__ DirSrc dir_src(const Geom &g, int x, int y, int z, in
 // source reads the corrections of node 0 and discards them).
 template <typename ST>
 struct PulledFG {
-  ST f, g, x, cg[3];
+  ST f, g;
+  typename Fmt<ST>::Side x, cg[3];
   bool inner;
 };
 
 template <int M, typename ST>
-__device__ __forceinline__ void pull_fg(const Geom &g, const ST *__restrict__ src, const ST *__restrict__ corr,
+__device__ __forceinline__ void pull_fg(const Geom &g, const ST *__restrict__ src,
+                                        const typename Fmt<ST>::Side *__restrict__ corr,
                                         int x, int y, int z, int i, PulledFG<ST> &p) {
   const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1;
   const DirSrc d = dir_src(g, x, y, z, i);
@@ -507,17 +551,19 @@ __device__ __forceinline__ void collide_pulled_fg(const CollideConsts &kc, const
                                                   const PulledFG<ST> &p, ST *__restrict__ dst, int64_t NPAD,
                                                   uint32_t pself) {
   const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-  // deferred A_i.X on the axis directions (eq. Ai), rounded to the storage precision
+  using Side = typename Fmt<ST>::Side;
+  // deferred A_i.X on the axis directions (eq. Ai), rounded to the side precision
   const double xs = (cx * cx + cy * cy + cz * cz) == 1 ? 0.5 * double(cx + cy + cz) : 0.0;
-  const double xc = double(ST(xs * double(p.x)));
-  const double f = double(p.f) + (p.inner ? xc : 0.0);
+  const double xc = double(Side(xs * double(p.x)));
+  const double f = pop_val(p.f, M - 1, i, kc) + (p.inner ? xc : 0.0);
   // deferred Fourier-correction flux 3 w_i c_i . Cg (eq. corrFourier)
   const double w3 = 3.0 * (w1(cx) * w1(cy) * w1(cz));
   const double d = double(cx) * double(p.cg[0]) + double(cy) * double(p.cg[1]) + double(cz) * double(p.cg[2]);
-  const double gc = double(ST(w3 * d));
-  const double gv = double(p.g) + (p.inner ? gc : 0.0);
-  collide_fg<M, F>(kc, cc, cx, cy, cz, f, gv,
-                   [&](int set, double v) { st(dst + ((int64_t)set * Q + i) * NPAD, pself, ST(v)); });
+  const double gc = double(Side(w3 * d));
+  const double gv = pop_val(p.g, M, i, kc) + (p.inner ? gc : 0.0);
+  collide_fg<M, F>(kc, cc, cx, cy, cz, f, gv, [&](int set, double v) {
+    st(dst + ((int64_t)set * Q + i) * NPAD, pself, pop_enc<ST>(v, set, i, kc));
+  });
 }
 
 template <int M, typename ST>
@@ -554,8 +600,8 @@ __device__ __forceinline__ void collide_pulled_species(const CollideConsts &kc, 
                                                        uint32_t pself) {
   const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
   collide_species<M, F>(
-      kc, cc, cx, cy, cz, [&](int a) { return double(p.fa[a]); },
-      [&](int a, double v) { st(dst + ((int64_t)a * Q + i) * NPAD, pself, ST(v)); });
+      kc, cc, cx, cy, cz, [&](int a) { return pop_val(p.fa[a], a, i, kc); },
+      [&](int a, double v) { st(dst + ((int64_t)a * Q + i) * NPAD, pself, pop_enc<ST>(v, a, i, kc)); });
 }
 
 // ---- step, part 1: the node-local kernel ----------------------------------------------
@@ -563,12 +609,14 @@ __device__ __forceinline__ void collide_pulled_species(const CollideConsts &kc, 
 // at the source (branch-free, so that the loads are issued together).
 template <int M, typename ST>
 struct PulledAll {
-  ST f, g, x, cg[3], fa[M - 1];
+  ST f, g, fa[M - 1];
+  typename Fmt<ST>::Side x, cg[3];
   bool inner;
 };
 
 template <int M, typename ST>
-__device__ __forceinline__ void pull_all(const Geom &g, const ST *__restrict__ src, const ST *__restrict__ corr,
+__device__ __forceinline__ void pull_all(const Geom &g, const ST *__restrict__ src,
+                                         const typename Fmt<ST>::Side *__restrict__ corr,
                                          int x, int y, int z, int i, PulledAll<M, ST> &p) {
   const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1;
   const DirSrc d = dir_src(g, x, y, z, i);
@@ -586,16 +634,17 @@ __device__ __forceinline__ void pull_all(const Geom &g, const ST *__restrict__ s
 
 // O1 (eqs. Pa, sumfDotc, g0momTotalEnergy): add direction i to the moments
 template <int M, typename ST>
-__device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, double (&mo)[14],
-                                            double (&sp)[M - 1][4]) {
+__device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, const CollideConsts &kc,
+                                            double (&mo)[14], double (&sp)[M - 1][4]) {
+  using Side = typename Fmt<ST>::Side;
   const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
   const double xs = (cx * cx + cy * cy + cz * cz) == 1 ? 0.5 * double(cx + cy + cz) : 0.0;
-  const double xc = double(ST(xs * double(p.x)));
-  const double f = double(p.f) + (p.inner ? xc : 0.0);
+  const double xc = double(Side(xs * double(p.x)));
+  const double f = pop_val(p.f, M - 1, i, kc) + (p.inner ? xc : 0.0);
   const double w3 = 3.0 * (w1(cx) * w1(cy) * w1(cz));
   const double d = double(cx) * double(p.cg[0]) + double(cy) * double(p.cg[1]) + double(cz) * double(p.cg[2]);
-  const double gc = double(ST(w3 * d));
-  const double gv = double(p.g) + (p.inner ? gc : 0.0);
+  const double gc = double(Side(w3 * d));
+  const double gv = pop_val(p.g, M, i, kc) + (p.inner ? gc : 0.0);
   const double fx = cx, fy = cy, fz = cz;
   // rho, j (3), P (xx yy zz xy xz yz), rho E, q (3)
   mo[0] += f;
@@ -614,7 +663,7 @@ __device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, do
   mo[13] += fz * gv;
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) {
-    const double fa = double(p.fa[a]);
+    const double fa = pop_val(p.fa[a], a, i, kc);
     sp[a][0] += fa;
     sp[a][1] += fx * fa;
     sp[a][2] += fy * fa;
@@ -628,13 +677,15 @@ __device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, do
 // store happens before the side channel at the end, so that the constant tables are
 // read with scalar loads throughout.
 template <int M, typename ST>
-__device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, const IslStash &sh, int64_t n, int x,
-                                           int y, int z, int cur, CollCoef<M, FT<ST>> &cc) {
+__device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, const CollideConsts &kc,
+                                           const IslStash &sh, int64_t n, int x, int y, int z, int cur,
+                                           CollCoef<M, FT<ST>> &cc) {
   using SW = IslWords<M>;
   using F = FT<ST>;
+  using Side = typename Fmt<ST>::Side;
   const Tables &tb = *b.tab;
   const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
-  const ST *__restrict__ corr = static_cast<const ST *>(b.corr);
+  const Side *__restrict__ corr = static_cast<const Side *>(b.corr);
   const int64_t N = g.N;
   const double T0 = b.T[n];
   (void)N;
@@ -654,11 +705,11 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, cons
 #pragma unroll 1
     for (int i = 0; i < Q - 1; i += 2) {
       pull_all<M, ST>(g, src, corr, x, y, z, i + 1, pb);
-      add_moments<M, ST>(i, pa, mo, sp);
+      add_moments<M, ST>(i, pa, kc, mo, sp);
       pull_all<M, ST>(g, src, corr, x, y, z, i + 2, pa);
-      add_moments<M, ST>(i + 1, pb, mo, sp);
+      add_moments<M, ST>(i + 1, pb, kc, mo, sp);
     }
-    add_moments<M, ST>(Q - 1, pa, mo, sp);
+    add_moments<M, ST>(Q - 1, pa, kc, mo, sp);
     m.rho = mo[0];
     const double inv_rho = 1.0 / mo[0];
     m.u[0] = mo[1] * inv_rho;
@@ -904,24 +955,24 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, cons
   }
   // O5: side channel of the stencils and the ghosts
   {
-    // in the storage precision: the corrections computed from them are stored in it
-    ST *sY = static_cast<ST *>(b.side_Y), *sw = static_cast<ST *>(b.side_w);
-    ST *sphi = static_cast<ST *>(b.side_phi);
+    // in the side precision: the corrections computed from them are held in it
+    Side *sY = static_cast<Side *>(b.side_Y), *sw = static_cast<Side *>(b.side_w);
+    Side *sphi = static_cast<Side *>(b.side_phi);
     const uint32_t i = (uint32_t)n;
     const double wc = 0.5 * (2.0 - om1) * P;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      st(sY + a * N, i, ST(sh.r(SW::RS + a) * inv_rho));
-      st(sw + a * N, i, ST(wc * Ha[a]));
+      st(sY + a * N, i, Side(sh.r(SW::RS + a) * inv_rho));
+      st(sw + a * N, i, Side(wc * Ha[a]));
     }
     const double uu[3] = {u0, u1, u2};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      st(sphi + d * N, i, ST(rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d]));
+      st(sphi + d * N, i, Side(rho * uu[d] * (1.0 - 3.0 * zeta) - rho * uu[d] * uu[d] * uu[d]));
     if (open_any) {
-      st(static_cast<ST *>(b.side_rho), i, ST(rho));
+      st(static_cast<Side *>(b.side_rho), i, Side(rho));
 #pragma unroll
-      for (int d = 0; d < 3; ++d) st(static_cast<ST *>(b.side_u) + d * N, i, ST(uu[d]));
+      for (int d = 0; d < 3; ++d) st(static_cast<Side *>(b.side_u) + d * N, i, Side(uu[d]));
     }
     st(b.T, i, T);
     if (anom) atomicOr(b.status, anom);
@@ -933,7 +984,7 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, cons
 // alternate in registers.
 template <int M, typename ST, typename F>
 __device__ __forceinline__ void fg_pass(const Geom &g, const ST *__restrict__ src, ST *__restrict__ dst,
-                                        const ST *__restrict__ corr, const CollideConsts &kc,
+                                        const typename Fmt<ST>::Side *__restrict__ corr, const CollideConsts &kc,
                                         const CollCoef<M, F> &cc, int x, int y, int z, uint32_t pself) {
   const int64_t NPAD = g.NPAD;
   PulledFG<ST> pa, pb;
@@ -982,10 +1033,10 @@ __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, Collid
   const int y = (int)((n / g.nx) % g.ny);
   const int z = (int)(n / ((int64_t)g.nx * g.ny));
   CollCoef<M, F> cc;
-  node_local<M, ST>(g, b, sh, n, x, y, z, cur, cc);
+  node_local<M, ST>(g, b, kc, sh, n, x, y, z, cur, cc);
   const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
   ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
-  const ST *__restrict__ corr = static_cast<const ST *>(b.corr);
+  const typename Fmt<ST>::Side *__restrict__ corr = static_cast<const typename Fmt<ST>::Side *>(b.corr);
   const uint32_t pself = ((uint32_t)(z + g.pz) * (uint32_t)g.NY + (uint32_t)(y + g.py)) * (uint32_t)g.NX +
                          (uint32_t)(x + g.px);
   fg_pass<M, ST, F>(g, src, dst, corr, kc, cc, x, y, z, pself);
@@ -1072,9 +1123,9 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
 
 // ---- equilibria of one state (init and ghosts) --------------------------------------
 template <int M, typename ST>
-__device__ __forceinline__ void write_equilibria(const Tables &tb, ST *__restrict__ dst, int64_t NPAD,
-                                                 const int64_t (&pidx)[27], double rho, const double *u,
-                                                 double T, const double *Y) {
+__device__ __forceinline__ void write_equilibria(const Tables &tb, const CollideConsts &kc,
+                                                 ST *__restrict__ dst, int64_t NPAD, const int64_t (&pidx)[27],
+                                                 double rho, const double *u, double T, const double *Y) {
   double zeta_a[M], zeta = 0.0, H = 0.0, U = 0.0;
   const double invT = 1.0 / T;
 #pragma unroll
@@ -1107,26 +1158,26 @@ __device__ __forceinline__ void write_equilibria(const Tables &tb, ST *__restric
     if (p < 0) return;
     const double fe = rho * psi_c<double>(cx, u[0], su[0] + zeta) * psi_c<double>(cy, u[1], su[1] + zeta) *
                       psi_c<double>(cz, u[2], su[2] + zeta);
-    dst[(int64_t)((M - 1) * Q + I) * NPAD + p] = ST(fe);
+    dst[(int64_t)((M - 1) * Q + I) * NPAD + p] = pop_enc<ST>(fe, M - 1, I, kc);
     double acc = A0 + 3.0 * (cx * qeq[0] + cy * qeq[1] + cz * qeq[2]);
     acc += cx * cx * (4.5 * Req[0] - 1.5 * rhoE) + cy * cy * (4.5 * Req[1] - 1.5 * rhoE) +
            cz * cz * (4.5 * Req[2] - 1.5 * rhoE);
     acc += 9.0 * (cx * cy * Req[3] + cx * cz * Req[4] + cy * cz * Req[5]);
-    dst[(int64_t)(M * Q + I) * NPAD + p] = ST(wgt(I) * acc);
+    dst[(int64_t)(M * Q + I) * NPAD + p] = pop_enc<ST>(wgt(I) * acc, M, I, kc);
 #pragma unroll
     for (int a = 0; a < M - 1; ++a) {
       const double z = zeta_a[a];
       const double fa = rho * Y[a] * psi_c<double>(cx, u[0], su[0] + z) * psi_c<double>(cy, u[1], su[1] + z) *
                         psi_c<double>(cz, u[2], su[2] + z);
-      dst[(int64_t)(a * Q + I) * NPAD + p] = ST(fa);
+      dst[(int64_t)(a * Q + I) * NPAD + p] = pop_enc<ST>(fa, a, I, kc);
     }
   });
 }
 
 // initial state: equilibria pushed to where the first pull reads them
 template <int M, typename ST>
-__global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, const double *rho, const double *u,
-                                              const double *T, const double *Y, int cur) {
+__global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, CollideConsts kc, const double *rho,
+                                              const double *u, const double *T, const double *Y, int cur) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
@@ -1143,13 +1194,14 @@ __global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, const double *r
   double Yl[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) Yl[a] = Y[a * N + n];
-  write_equilibria<M, ST>(*b.tab, static_cast<ST *>(b.pop[cur]), g.NPAD, pidx, rho[n], uu, T[n], Yl);
+  write_equilibria<M, ST>(*b.tab, kc, static_cast<ST *>(b.pop[cur]), g.NPAD, pidx, rho[n], uu, T[n], Yl);
   b.T[n] = T[n];
 }
 
 // ghost layer of open faces: equilibria at the adjacent boundary node (Sec. 5.1)
 template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, int cur, int64_t nx_slab, int64_t ny_slab,
+__global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts kc, int cur, int64_t nx_slab,
+                                               int64_t ny_slab,
                                                int64_t nz_slab) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int gx, gy, gz;
@@ -1215,21 +1267,22 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, int cur, int64
     }
     pidx[i] = need ? p : -1;
   }
-  write_equilibria<M, ST>(*b.tab, static_cast<ST *>(b.pop[cur ^ 1]), g.NPAD, pidx, double(srho[na]), u,
+  write_equilibria<M, ST>(*b.tab, kc, static_cast<ST *>(b.pop[cur ^ 1]), g.NPAD, pidx, double(srho[na]), u,
                           b.T[na], Y);
 }
 
 // macroscopic fields of the current state (no state change)
 template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, int cur, double *rho, double *u, double *T,
-                                                double *P, double *Y) {
+__global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, CollideConsts kc, int cur, double *rho,
+                                                double *u, double *T, double *P, double *Y) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const int64_t N = g.N;
-  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
+  using Side = typename Fmt<ST>::Side;
+  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * N, N};
   Macro<M> m;
-  node_moments<M, ST>(g, static_cast<const ST *>(b.pop[cur]), cr, x, y, z, m);
+  node_moments<M, ST>(g, static_cast<const ST *>(b.pop[cur]), cr, kc, x, y, z, m);
   const Tables &tb = *b.tab;
   double Tn;
   node_temperature<M>(tb, m, b.T[n], Tn);
@@ -1251,16 +1304,17 @@ __global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, int cur, doub
 
 // pre-collision populations at listed nodes
 template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, const int64_t *nodes, int64_t nn,
-                                                double *out, double *T_out) {
+__global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, CollideConsts kc, int cur,
+                                                const int64_t *nodes, int64_t nn, double *out, double *T_out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nn) return;
   const int64_t n = nodes[k];
   if (n < 0 || n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const int64_t N = g.N, NPAD = g.NPAD;
+  using Side = typename Fmt<ST>::Side;
   const ST *pop = static_cast<const ST *>(b.pop[cur]);
-  const Corr<ST> cr{static_cast<const ST *>(b.corr), static_cast<const ST *>(b.corr) + 3 * N, N};
+  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * N, N};
   const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
   const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
   const AxisSrc az = axis_src(z, g.nz, g.per[2]);
@@ -1273,10 +1327,11 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, int cur, cons
       const int i = kx + 3 * kyz;
       const Src r = make_src(g, ax, ay, az, kx, ky, kz);
       out[((int64_t)(M - 1) * Q + i) * nn + k] =
-          pull_f<cx, ST, ST>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz);
-      out[((int64_t)M * Q + i) * nn + k] = pull_g<cx, ST, ST>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz);
+          pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
+      out[((int64_t)M * Q + i) * nn + k] =
+          pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
       for (int a = 0; a < M - 1; ++a)
-        out[((int64_t)a * Q + i) * nn + k] = (double)ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
+        out[((int64_t)a * Q + i) * nn + k] = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
     });
   }
   if (T_out) T_out[k] = b.T[n];
@@ -1294,8 +1349,13 @@ template <template <int, typename, typename> class K, typename... Args>
 hipError_t dispatch(int M, int store, Args &&...args) {
 #define LBM_CASE(MM)                                                              \
   case MM:                                                                        \
-    return store == LBM_STORE_F64 ? K<MM, double, double>::run(args...)           \
-                                  : K<MM, float, float>::run(args...);
+    switch (store) {                                                              \
+      case LBM_STORE_F64: return K<MM, double, double>::run(args...);              \
+      case LBM_STORE_F32: return K<MM, float, float>::run(args...);                \
+      case LBM_STORE_F16_DEV: return K<MM, _Float16, float>::run(args...);         \
+      case LBM_STORE_BF16_DEV: return K<MM, __bf16, float>::run(args...);          \
+      default: return hipErrorInvalidValue;                                         \
+    }
   switch (M) {
     LBM_CASE(2) LBM_CASE(3) LBM_CASE(4) LBM_CASE(5) LBM_CASE(6) LBM_CASE(7) LBM_CASE(8) LBM_CASE(9)
     LBM_CASE(10)
@@ -1314,44 +1374,48 @@ struct RunStep {
 template <int M, typename ST, typename RT>
 struct RunCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
-    hipLaunchKernelGGL((k_corr<M, RT, ST>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    hipLaunchKernelGGL((k_corr<M, RT, RT>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
     return hipGetLastError();
   }
 };
 template <int M, typename ST, typename RT>
 struct RunInit {
-  static hipError_t run(const Geom &g, const Buffers &b, const double *rho, const double *u, const double *T,
-                        const double *Y, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_init<M, ST>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, rho, u, T, Y, cur);
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, const double *rho,
+                        const double *u, const double *T, const double *Y, int cur, hipStream_t st) {
+    hipLaunchKernelGGL((k_init<M, ST>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, kc, rho, u, T, Y,
+                       cur);
     return hipGetLastError();
   }
 };
 template <int M, typename ST, typename RT>
 struct RunGhost {
-  static hipError_t run(const Geom &g, const Buffers &b, int cur, hipStream_t st) {
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
     const int64_t sx = g.px ? 2LL * g.NY * g.NZ : 0;
     const int64_t sy = g.py ? 2LL * g.nx * g.NZ : 0;
     const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
     const int64_t tot = sx + sy + sz;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_ghost<M, ST, RT>), dim3(blocks_for(tot, 128)), dim3(128), 0, st, g, b, cur, sx, sy, sz);
+    hipLaunchKernelGGL((k_ghost<M, ST, RT>), dim3(blocks_for(tot, 128)), dim3(128), 0, st, g, b, kc, cur, sx, sy,
+                       sz);
     return hipGetLastError();
   }
 };
 template <int M, typename ST, typename RT>
 struct RunMacros {
-  static hipError_t run(const Geom &g, const Buffers &b, int cur, double *rho, double *u, double *T, double *P,
-                        double *Y, hipStream_t st) {
-    hipLaunchKernelGGL((k_macros<M, ST, RT>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, cur, rho, u, T, P, Y);
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double *rho,
+                        double *u, double *T, double *P, double *Y, hipStream_t st) {
+    hipLaunchKernelGGL((k_macros<M, ST, RT>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, kc, cur, rho, u,
+                       T, P, Y);
     return hipGetLastError();
   }
 };
 template <int M, typename ST, typename RT>
 struct RunExport {
-  static hipError_t run(const Geom &g, const Buffers &b, int cur, const int64_t *nodes, int64_t nn, double *out,
-                        double *T_out, hipStream_t st) {
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, const int64_t *nodes,
+                        int64_t nn, double *out, double *T_out, hipStream_t st) {
     if (nn == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_export<M, ST, RT>), dim3(blocks_for(nn, 128)), dim3(128), 0, st, g, b, cur, nodes, nn, out, T_out);
+    hipLaunchKernelGGL((k_export<M, ST, RT>), dim3(blocks_for(nn, 128)), dim3(128), 0, st, g, b, kc, cur, nodes,
+                       nn, out, T_out);
     return hipGetLastError();
   }
 };
@@ -1375,23 +1439,24 @@ hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t s
   return dispatch<RunCorr>(g.M, store, g, b, st);
 }
 
-hipError_t launch_init(const Geom &g, const Buffers &b, int store, const double *rho, const double *u,
-                       const double *T, const double *Y, int cur, hipStream_t st) {
-  return dispatch<RunInit>(g.M, store, g, b, rho, u, T, Y, cur, st);
+hipError_t launch_init(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, const double *rho,
+                       const double *u, const double *T, const double *Y, int cur, hipStream_t st) {
+  return dispatch<RunInit>(g.M, store, g, b, kc, rho, u, T, Y, cur, st);
 }
 
-hipError_t launch_ghost(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st) {
-  return dispatch<RunGhost>(g.M, store, g, b, cur, st);
+hipError_t launch_ghost(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                        hipStream_t st) {
+  return dispatch<RunGhost>(g.M, store, g, b, kc, cur, st);
 }
 
-hipError_t launch_macros(const Geom &g, const Buffers &b, int store, int cur, double *rho, double *u,
-                         double *T, double *P, double *Y, hipStream_t st) {
-  return dispatch<RunMacros>(g.M, store, g, b, cur, rho, u, T, P, Y, st);
+hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                         double *rho, double *u, double *T, double *P, double *Y, hipStream_t st) {
+  return dispatch<RunMacros>(g.M, store, g, b, kc, cur, rho, u, T, P, Y, st);
 }
 
-hipError_t launch_export(const Geom &g, const Buffers &b, int store, int cur, const int64_t *nodes,
-                         int64_t n_nodes, double *out, double *T_out, hipStream_t st) {
-  return dispatch<RunExport>(g.M, store, g, b, cur, nodes, n_nodes, out, T_out, st);
+hipError_t launch_export(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                         const int64_t *nodes, int64_t n_nodes, double *out, double *T_out, hipStream_t st) {
+  return dispatch<RunExport>(g.M, store, g, b, kc, cur, nodes, n_nodes, out, T_out, st);
 }
 
 hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st) {

@@ -40,15 +40,18 @@ struct Tables {
   double omega, omega1;
 };
 
-// Constants of the collision passed as kernel arguments: they are read with
-// scalar loads from the argument segment, which stays valid after the kernel's
-// first store to global memory.
+// Constants of the step passed as kernel arguments: they are read with scalar loads
+// from the argument segment, which stays valid after a kernel's first store to
+// global memory.
 struct CollideConsts {
   double omega;
   double Ra[MAXM];                       // lattice gas constants kappa R_U / m_a
   float Raf[MAXM];
   double invDp[MAXM * (MAXM - 1) / 2];   // 1 / D_ab for a < b, row-major pairs
   float invDpf[MAXM * (MAXM - 1) / 2];
+  // deviation formats: stored value = (f - ref[s][i]) * isc[s], f = ref[s][i] + sc[s] * stored
+  float ref[MAXM + 1][Q];
+  float sc[MAXM + 1], isc[MAXM + 1];
 };
 
 struct Geom {
@@ -77,17 +80,18 @@ struct Buffers {
 };
 
 // launchers (lbm_device.hip)
-hipError_t launch_init(const Geom &g, const Buffers &b, int store, const double *rho, const double *u,
-                       const double *T, const double *Y, int cur, hipStream_t st);
+hipError_t launch_init(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, const double *rho,
+                       const double *u, const double *T, const double *Y, int cur, hipStream_t st);
 hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
                        hipStream_t st);
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st);
-hipError_t launch_ghost(const Geom &g, const Buffers &b, int store, int cur, hipStream_t st);
-hipError_t launch_macros(const Geom &g, const Buffers &b, int store, int cur, double *rho, double *u,
-                         double *T, double *P, double *Y, hipStream_t st);
-hipError_t launch_export(const Geom &g, const Buffers &b, int store, int cur, const int64_t *nodes,
-                         int64_t n_nodes, double *out, double *T_out, hipStream_t st);
+hipError_t launch_ghost(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                        hipStream_t st);
+hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                         double *rho, double *u, double *T, double *P, double *Y, hipStream_t st);
+hipError_t launch_export(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                         const int64_t *nodes, int64_t n_nodes, double *out, double *T_out, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st);
 
 }  // namespace lbm

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK = 0
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_UNSUPPORTED", -3: "LBM_ERR_HIP",
                 -4: "LBM_ERR_WORKSPACE", -5: "LBM_ERR_DEVICE_ANOMALY"}
-STORE_F64, STORE_F32 = 0, 1
+STORE_F64, STORE_F32, STORE_F16_DEV, STORE_BF16_DEV = 0, 1, 2, 3
 NUM_KERNELS = 4
 KERNEL_NAMES = ("step", "psi", "corr", "ghost")
 ANOM_NONFINITE, ANOM_NEWTON, ANOM_NEG_DENSITY = 1, 2, 4
@@ -39,7 +39,7 @@ class LbmDesc(C.Structure):
         ("nu_reac", _ip), ("nu_prod", _ip), ("arrhenius", _dp), ("reversible", _up),
         ("omega", C.c_double), ("omega1", C.c_double),
         ("kappa", C.c_double), ("dt_phys", C.c_double), ("rho_ref", C.c_double), ("p0", C.c_double),
-        ("storage", C.c_int32), ("reserved", C.c_int32),
+        ("storage", C.c_int32), ("reserved", C.c_int32), ("ref_state", C.c_void_p),
     ]
 
 
@@ -113,6 +113,15 @@ def make_desc(prob, storage: Optional[int] = None):
     d.omega, d.omega1 = prob.omega, prob.omega1
     d.kappa, d.dt_phys, d.rho_ref, d.p0 = prob.kappa, prob.dt_phys, prob.rho_ref, prob.p0
     d.storage = prob.storage if storage is None else storage
+    if d.storage in (STORE_F16_DEV, STORE_BF16_DEV):
+        ref = prob.ref_state
+        if ref is None:
+            # mean state of the initial fields: density, temperature, mass-weighted Y
+            rho = np.asarray(prob.rho, np.float64)
+            Y = (np.asarray(prob.Y, np.float64) * rho).sum(axis=1) / rho.sum()
+            ref = np.concatenate([[rho.mean(), np.asarray(prob.T, np.float64).mean()], Y / Y.sum()])
+        keep["ref_state"] = _c64(ref)
+        d.ref_state = keep["ref_state"].ctypes.data_as(C.c_void_p)
     return d, keep
 
 
@@ -143,6 +152,7 @@ class Solver:
                        else torch.device("cuda", torch.cuda.current_device()))
         self.desc, self._keep = make_desc(prob, storage)
         self.storage = self.desc.storage
+        self.ref_state = self._keep.get("ref_state")
         n = C.c_size_t(0)
         self._check(self.lib.lbm_workspace_size(C.byref(self.desc), C.byref(n)), None)
         self.ws_bytes = int(n.value)

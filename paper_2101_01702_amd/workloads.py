@@ -36,6 +36,8 @@ BC_OPEN_U0 = 2             # same, ghost velocity set to zero
 
 STORE_F64 = 0
 STORE_F32 = 1
+STORE_F16_DEV = 2          # 16-bit deviations from the reference populations
+STORE_BF16_DEV = 3
 
 ELEMENTS = ("H", "O", "N")
 ATOMIC_MASS = {"H": 1.0, "O": 16.0, "N": 14.0}   # integer masses: exact sums
@@ -84,6 +86,8 @@ class Problem:
     Y: np.ndarray               # [M, N]
     steps: int = 0
     storage: int = STORE_F64
+    # quiescent reference state of the 16-bit deviation formats: [rho, T, Y_0..Y_M-1]
+    ref_state: Optional[np.ndarray] = None
 
     @property
     def N(self) -> int:
@@ -371,9 +375,11 @@ def flame1d(nx: int = 4096, seed: int = 7, phi: float = 1.0, T_u: float = 300.0,
     rho = lattice_density(np.full(nx, P_ATM), T, m, rho_ref)
     u = np.zeros((3, nx))
     D = _default_transport(M, rng, *diff_range)
+    Y_u = mole_to_mass(X_u, mech.molar_mass)
+    ref = np.concatenate([[lattice_density(P_ATM, T_u, m_u, rho_ref), T_u], Y_u])
     return Problem(f"flame1d_{nx}", nx, 1, 1, (BC_OPEN_U0, BC_OPEN, 0, 0, 0, 0), mech, D, omega,
                    omega1_from_prandtl(omega, prandtl), kappa, dt_phys, rho_ref, P_ATM,
-                   rho, u, T, Y, steps=steps, storage=storage)
+                   rho, u, T, Y, steps=steps, storage=storage, ref_state=ref)
 
 
 def sphere3d(n: int = 256, seed: int = 7, phi: float = 0.8, T_u: float = 300.0,
@@ -404,9 +410,11 @@ def sphere3d(n: int = 256, seed: int = 7, phi: float = 0.8, T_u: float = 300.0,
     Y = np.repeat(mole_to_mass(X_u, mech.molar_mass)[:, None], N, axis=1)
     u = np.zeros((3, N))
     D = _default_transport(M, np.random.default_rng(seed + 1000), *diff_range)
+    Y_u = mole_to_mass(X_u, mech.molar_mass)
+    ref = np.concatenate([[lattice_density(P_ATM, T_u, m_u, rho_ref), T_u], Y_u])
     return Problem(f"sphere3d_{nx}x{ny}x{nz}", nx, ny, nz, (BC_OPEN,) * 6, mech, D, omega,
                    omega1_from_prandtl(omega, prandtl), kappa, dt_phys, rho_ref, P_ATM,
-                   rho, u, T, Y, steps=5000, storage=storage)
+                   rho, u, T, Y, steps=5000, storage=storage, ref_state=ref)
 
 
 def perturb_velocity(prob: Problem, amp: float, seed: int) -> Problem:
