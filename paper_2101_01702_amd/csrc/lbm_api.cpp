@@ -48,7 +48,11 @@ Geom make_geom(const lbm_desc &d) {
 
 Layout make_layout(const lbm_desc &d, const Geom &g) {
   const size_t st = d.storage == LBM_STORE_F64 ? 8 : (d.storage == LBM_STORE_F32 ? 4 : 2);  // populations
-  const size_t ct = d.storage == LBM_STORE_F64 ? 8 : 4;   // side channel, psi and corrections
+#ifndef LBM_SIDE_F64_FOR_F32
+#define LBM_SIDE_F64_FOR_F32 0
+#endif
+  const size_t ct = (d.storage == LBM_STORE_F64 || (LBM_SIDE_F64_FOR_F32 && d.storage == LBM_STORE_F32))
+                        ? 8 : 4;   // side channel, psi and corrections
   const size_t S = (size_t)d.n_species + 1;
   const size_t N = (size_t)g.N, M = (size_t)d.n_species;
   Layout L{};

@@ -16,6 +16,7 @@
 // kernels compute them from a small side channel, and the next pull adds them back
 // to each population as it is read (deferred correction).  One step therefore moves
 // each population through HBM once in and once out.
+#include <type_traits>
 #include <utility>
 
 #include "lbm_internal.h"
@@ -135,10 +136,16 @@ __device__ __forceinline__ void opaque_uniform(T *&p) {
 // Populations are stored as ST; side fields, psi and corrections as Side; the
 // inter-species term is evaluated in F.  The 16-bit formats store deviations from the
 // reference populations: stored = (f - ref[s][i]) / sc[s].
+#ifndef LBM_SIDE_F64_FOR_F32
+#define LBM_SIDE_F64_FOR_F32 0
+#endif
+#ifndef LBM_FTERM_F64
+#define LBM_FTERM_F64 0
+#endif
 template <typename ST>
 struct Fmt {
-  using Side = ST;
-  using F = ST;
+  using Side = std::conditional_t<LBM_SIDE_F64_FOR_F32 && sizeof(ST) == 4, double, ST>;
+  using F = std::conditional_t<LBM_FTERM_F64 != 0, double, ST>;
   static constexpr bool dev = false;
 };
 template <>
@@ -1350,10 +1357,10 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 #define LBM_CASE(MM)                                                              \
   case MM:                                                                        \
     switch (store) {                                                              \
-      case LBM_STORE_F64: return K<MM, double, double>::run(args...);              \
-      case LBM_STORE_F32: return K<MM, float, float>::run(args...);                \
-      case LBM_STORE_F16_DEV: return K<MM, _Float16, float>::run(args...);         \
-      case LBM_STORE_BF16_DEV: return K<MM, __bf16, float>::run(args...);          \
+      case LBM_STORE_F64: return K<MM, double, Fmt<double>::Side>::run(args...);   \
+      case LBM_STORE_F32: return K<MM, float, Fmt<float>::Side>::run(args...);     \
+      case LBM_STORE_F16_DEV: return K<MM, _Float16, Fmt<_Float16>::Side>::run(args...); \
+      case LBM_STORE_BF16_DEV: return K<MM, __bf16, Fmt<__bf16>::Side>::run(args...);    \
       default: return hipErrorInvalidValue;                                         \
     }
   switch (M) {
@@ -1429,7 +1436,9 @@ hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc,
 
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {
   if (store == LBM_STORE_F64)
-    hipLaunchKernelGGL((k_psi<double>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    hipLaunchKernelGGL((k_psi<Fmt<double>::Side>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+  else if (store == LBM_STORE_F32)
+    hipLaunchKernelGGL((k_psi<Fmt<float>::Side>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
   else
     hipLaunchKernelGGL((k_psi<float>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
   return hipGetLastError();

@@ -267,7 +267,16 @@ def _connected(reacs, n_reactive, src, dst):
     return dst in seen
 
 
-def h2air_mechanism(seed: int = 7, n_reactions: int = 19) -> Mechanism:
+# Seed of the synthetic mechanism used by the flame workloads, screened on the oracle:
+# the homogeneous reactor at 1500 K ignites (above 2000 K within 3000 steps of 1e-9 s)
+# while the 300 K premixture stays inert over 20000 steps, and with 3e-10 s of chemistry
+# per step the quasi-1D flame propagates into the premixture at about 0.006 cells per
+# step (longer chemistry steps overshoot the oxygen depletion at the front: the source
+# is explicit).
+FLAME_SEED = 156
+
+
+def h2air_mechanism(seed: int = FLAME_SEED, n_reactions: int = 19) -> Mechanism:
     """Synthetic 9-species / 19-reaction reversible mechanism over the species set of
     the paper's hydrogen/air mechanism.  Reactions are sampled (seeded) from all
     element-balanced A+B<=>C+D and A+B<=>C templates over the 8 reactive species,
@@ -352,9 +361,9 @@ def _default_transport(M: int, rng: np.random.Generator, lo: float, hi: float) -
     return symmetric_uniform(rng, M, lo, hi)
 
 
-def flame1d(nx: int = 4096, seed: int = 7, phi: float = 1.0, T_u: float = 300.0,
+def flame1d(nx: int = 4096, seed: int = FLAME_SEED, phi: float = 1.0, T_u: float = 300.0,
             T_hot: float = 2000.0, hot_cells: int = 64, zeta_ref: float = 0.003,
-            omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 1e-12,
+            omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 3e-10,
             diff_range=(0.02, 0.08), steps: int = 20000, edge: float = 2.0,
             storage: int = STORE_F64, mech: Optional[Mechanism] = None) -> Problem:
     """Quasi-1D premixed flame: nx x 1 x 1, periodic y/z, zero-velocity open end at
@@ -382,9 +391,9 @@ def flame1d(nx: int = 4096, seed: int = 7, phi: float = 1.0, T_u: float = 300.0,
                    rho, u, T, Y, steps=steps, storage=storage, ref_state=ref)
 
 
-def sphere3d(n: int = 256, seed: int = 7, phi: float = 0.8, T_u: float = 300.0,
+def sphere3d(n: int = 256, seed: int = FLAME_SEED, phi: float = 0.8, T_u: float = 300.0,
              T_ig: float = 1500.0, radius: float = 12.0, zeta_ref: float = 0.003,
-             omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 1e-12,
+             omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 3e-10,
              diff_range=(0.02, 0.08), edge: float = 2.0, storage: int = STORE_F32,
              shape: Optional[Tuple[int, int, int]] = None,
              mech: Optional[Mechanism] = None) -> Problem:

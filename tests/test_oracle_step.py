@@ -446,3 +446,26 @@ def test_sound_damping_galilean_invariance():
     g0, g1 = sound_damping(0.0), sound_damping(0.1)
     assert g0 > 0
     assert abs(g1 / g0 - 1) < 0.15
+
+
+def test_flame_response_to_a_perturbation_is_bounded():
+    """The igniting quasi-1D flame responds linearly and boundedly to a small
+    perturbation: a random relative perturbation of the initial temperature of size
+    eps changes every field by at most 10 eps after 1000 steps (the FP32 parity bar of
+    the flame relies on this), and the response scales with eps."""
+    import copy
+    from gpu_cases import field_errors, zeta_of
+    prob = W.flame1d(nx=512, hot_cells=64)
+    base = orc.OracleSim(prob).init()
+    base.step(1000, 8)
+    ref = base.macros()
+    worst = []
+    for eps in (1e-10, 1e-8):
+        p2 = copy.copy(prob)
+        p2.T = prob.T * (1 + eps * np.random.default_rng(3).uniform(-1, 1, prob.N))
+        sim = orc.OracleSim(p2).init()
+        assert sim.step(1000, 8) == 0
+        e = field_errors(sim.macros(), ref, zeta_of(prob))
+        worst.append(max(e.values()) / eps)
+    assert max(worst) <= 10.0, worst
+    assert abs(worst[0] - worst[1]) <= 0.05 * worst[1], worst
