@@ -137,6 +137,33 @@ def test_reaction_order_limit(lib):
     assert st == -1 and "molecules" in msg
 
 
+def test_deviation_formats_need_a_valid_reference_state(lib):
+    """LBM_STORE_F16_DEV / _BF16_DEV store populations in 2 bytes and need ref_state
+    (density > 0, temperature > 0, mass fractions >= 0 summing to 1)."""
+    prob = W.config1()
+    sizes = {}
+    for st in (W.STORE_F64, W.STORE_F32, W.STORE_F16_DEV, W.STORE_BF16_DEV):
+        d, keep = lbm.make_desc(prob, st)
+        code, n, msg = _ws(lib, d)
+        assert code == 0, msg
+        sizes[st] = n
+    S, N = 4, 512
+    assert sizes[W.STORE_F32] - sizes[W.STORE_F16_DEV] >= 2 * S * 27 * N * 2
+    d, keep = lbm.make_desc(prob, W.STORE_F16_DEV)
+    d.ref_state = None
+    code, _, msg = _ws(lib, d)
+    assert code == -1 and "ref_state" in msg
+    for bad, needle in [([0.0, 1000.0, 0.3, 0.3, 0.4], "density"), ([1.0, -5.0, 0.3, 0.3, 0.4], "temperature"),
+                        ([1.0, 1000.0, 0.5, 0.3, 0.4], "sum"), ([1.0, 1000.0, -0.1, 0.7, 0.4], "Y[0]")]:
+        ref = np.array(bad, np.float64)
+        d.ref_state = ref.ctypes.data_as(C.c_void_p)
+        code, _, msg = _ws(lib, d)
+        assert code == -1 and needle in msg, (bad, msg)
+    d.storage = 4
+    code, _, msg = _ws(lib, d)
+    assert code == -1 and "storage" in msg
+
+
 def test_create_rejects_bad_workspace_without_device(lib):
     d, keep = _desc(W.config1())
     h = C.c_void_p()
