@@ -121,8 +121,11 @@ typedef struct {
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost
  * layer on open axes, temperature (FP64), a side channel of node fields for the
  * gradient stencils and the ghosts (2M + 7 words) and psi (3 words), the deferred
- * corrections (6 words), all in the storage precision, the constant tables and a
- * status word. */
+ * corrections (6 words per node of the padded lattice), all in the storage
+ * precision, the constant tables, a copy of the collision constants and a status
+ * word.  Fails with LBM_ERR_ARG when one padded plane of the lattice (its node count
+ * with the ghost layers) times 8 bytes for LBM_STORE_F64, 4 otherwise, reaches
+ * 2 GiB: the step kernel addresses a plane with 32-bit byte offsets. */
 lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 
 /* Validate the descriptor, copy it, and upload its tables into the caller's

@@ -24,7 +24,7 @@ thread_local std::string g_last_error;
 size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t status, tables, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, total;
+  size_t status, tables, consts, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, total;
   size_t corr_bytes;
 };
 
@@ -64,6 +64,7 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   };
   L.status = take(64);
   L.tables = take(sizeof(Tables));
+  L.consts = take(sizeof(CollideConsts));
   L.pop0 = take(S * Q * (size_t)g.NPAD * st);
   L.pop1 = take(S * Q * (size_t)g.NPAD * st);
   L.T = take(N * 8);
@@ -73,7 +74,7 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.side_rho = take(N * ct);
   L.side_u = take(3 * N * ct);
   L.psi = take(3 * N * ct);
-  L.corr_bytes = 6 * N * ct;   // deferred corrections
+  L.corr_bytes = 6 * (size_t)g.NPAD * ct;   // deferred corrections, padded planes
   L.corr = take(L.corr_bytes);
   L.total = off;
   return L;
@@ -158,6 +159,16 @@ bool validate(const lbm_desc *d, std::string *err) {
       ys += r[2 + a];
     }
     if (std::fabs(ys - 1.0) > 1e-9) return fail(err, "ref_state: mass fractions sum to %.17g, not 1", ys);
+  }
+  {
+    // the step kernel addresses one padded plane with 32-bit byte offsets
+    const double padded = (double)(d->nx + (d->bc[0] == LBM_BC_PERIODIC ? 0 : 2)) *
+                          (d->ny + (d->bc[2] == LBM_BC_PERIODIC ? 0 : 2)) *
+                          (d->nz + (d->bc[4] == LBM_BC_PERIODIC ? 0 : 2));
+    const double word = d->storage == LBM_STORE_F64 ? 8.0 : 4.0;   // largest element of a plane
+    if (padded * word > 2147483647.0)
+      return fail(err, "lattice has %.0f padded nodes; a plane of %.0f-byte values must stay below 2 GiB",
+                  padded, word);
   }
   return true;
 }
@@ -386,6 +397,7 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   b.side_u = ws + L.side_u;
   b.psi = ws + L.psi;
   b.corr = ws + L.corr;
+  b.kc = reinterpret_cast<const CollideConsts *>(ws + L.consts);
   Tables t;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
@@ -399,6 +411,7 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
     h->kc.invDpf[k] = t.invDpf[k];
   }
   e = hipMemcpy(ws + L.tables, &t, sizeof(Tables), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ws + L.consts, &h->kc, sizeof(CollideConsts), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     uint32_t zero[16] = {0};
     e = hipMemcpy(ws + L.status, zero, sizeof(zero), hipMemcpyHostToDevice);

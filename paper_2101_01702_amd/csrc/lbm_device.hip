@@ -162,16 +162,16 @@ struct Fmt<__bf16> {
 };
 
 // value of a stored population of set s along direction i
-template <typename ST>
-__device__ __forceinline__ double pop_val(ST raw, int s, int i, const CollideConsts &kc) {
+template <typename ST, typename K>
+__device__ __forceinline__ double pop_val(ST raw, int s, int i, const K &kc) {
   if constexpr (Fmt<ST>::dev)
     return double(fmaf(kc.sc[s], float(raw), kc.ref[s][i]));
   else
     return double(raw);
 }
 // stored form of the population value v of set s along direction i
-template <typename ST>
-__device__ __forceinline__ ST pop_enc(double v, int s, int i, const CollideConsts &kc) {
+template <typename ST, typename K>
+__device__ __forceinline__ ST pop_enc(double v, int s, int i, const K &kc) {
   if constexpr (Fmt<ST>::dev)
     return ST(float((v - double(kc.ref[s][i])) * double(kc.isc[s])));
   else
@@ -198,11 +198,12 @@ __device__ __forceinline__ int nb_coord(int x, int c, int n, bool periodic) {
   return s < 0 ? 0 : (s >= n ? n - 1 : s);
 }
 
+// deferred corrections, in padded planes whose ghost cells hold zero
 template <typename CT>
 struct Corr {
-  const CT *X;    // [3][N]
-  const CT *Cg;   // [3][N]
-  int64_t N;
+  const CT *X;    // [3][NPAD]
+  const CT *Cg;   // [3][NPAD]
+  int64_t NPAD;
 };
 
 // pulled value of the mixture f along c = (CX, cy, cz) with the deferred A_i.X term;
@@ -213,12 +214,12 @@ __device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src 
                                          int cz, int s, int i, const CollideConsts &kc) {
   double v = pop_val(ld(base, r.ps), s, i, kc);
   if (r.ns >= 0) {
-    const uint32_t ns = (uint32_t)r.ns;
+    const uint32_t ns = r.ps;   // the corrections live in padded planes
     if constexpr (CX != 0) {
       if (cy == 0 && cz == 0) v += double(CT(0.5 * CX * double(ld(cr.X, ns))));
     } else {
-      if (cy != 0 && cz == 0) v += double(CT(0.5 * cy * double(ld(cr.X + cr.N, ns))));
-      if (cy == 0 && cz != 0) v += double(CT(0.5 * cz * double(ld(cr.X + 2 * cr.N, ns))));
+      if (cy != 0 && cz == 0) v += double(CT(0.5 * cy * double(ld(cr.X + cr.NPAD, ns))));
+      if (cy == 0 && cz != 0) v += double(CT(0.5 * cz * double(ld(cr.X + 2 * cr.NPAD, ns))));
     }
   }
   return v;
@@ -231,11 +232,11 @@ __device__ __forceinline__ double pull_g(const ST *__restrict__ base, const Src 
   const double w3 = 3.0 * (w1(CX) * w1(cy) * w1(cz));
   double v = pop_val(ld(base, r.ps), s, i, kc);
   if (r.ns >= 0) {
-    const uint32_t ns = (uint32_t)r.ns;
+    const uint32_t ns = r.ps;   // the corrections live in padded planes
     double d = 0.0;
     if constexpr (CX != 0) d += CX * double(ld(cr.Cg, ns));
-    if (cy != 0) d += cy * double(ld(cr.Cg + cr.N, ns));
-    if (cz != 0) d += cz * double(ld(cr.Cg + 2 * cr.N, ns));
+    if (cy != 0) d += cy * double(ld(cr.Cg + cr.NPAD, ns));
+    if (cz != 0) d += cz * double(ld(cr.Cg + 2 * cr.NPAD, ns));
     v += double(CT(w3 * d));
   }
   return v;
@@ -251,11 +252,13 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // ---- thermodynamics (eqs. specHa, Umix; NASA-7) -------------------------------------
-__device__ __forceinline__ double h_RT(const double *a, double T, double invT) {
+template <typename P>
+__device__ __forceinline__ double h_RT(P a, double T, double invT) {
   return a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * (a[4] * 0.2)))) +
          a[5] * invT;
 }
-__device__ __forceinline__ double s_R(const double *a, double T, double lnT) {
+template <typename P>
+__device__ __forceinline__ double s_R(P a, double T, double lnT) {
   return a[0] * lnT + T * (a[1] + T * (a[2] * 0.5 + T * (a[3] * (1.0 / 3.0) + T * (a[4] * 0.25)))) +
          a[6];
 }
@@ -341,8 +344,8 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
 }
 
 // temperature from E - u^2/2 (eq. temperature) by Newton from T0; returns 1 when converged
-template <int M>
-__device__ __forceinline__ int node_temperature(const Tables &tb, const Macro<M> &m, double T0, double &T_out) {
+template <int M, typename TB>
+__device__ __forceinline__ int node_temperature(const TB &tb, const Macro<M> &m, double T0, double &T_out) {
   double ec[6], dc[5];
 #pragma unroll
   for (int k = 0; k < 6; ++k) ec[k] = 0.0;
@@ -429,252 +432,229 @@ struct CollCoef {
   F rcoef[M - 1];
 };
 
-// O7 for one direction, mixture f and energy g (eqs. f, g); A_i.X and the q^corr
-// part are added by the next pull
-template <int M, typename F, typename StFn>
-__device__ __forceinline__ void collide_fg(const CollideConsts &kc, const CollCoef<M, F> &cc, int cx, int cy,
-                                           int cz, double f, double gv, StFn &&store) {
-  const double om = kc.omega;
-  const double fcx = cx, fcy = cy, fcz = cz;
-  const double wi = w1(cx) * w1(cy) * w1(cz);
-  const double u0 = cc.u0, u1 = cc.u1, u2 = cc.u2;
-  const double feq = cc.rho * psi_c<double>(cx, u0, u0 * u0 + cc.zeta) * psi_c<double>(cy, u1, u1 * u1 + cc.zeta) *
-                     psi_c<double>(cz, u2, u2 * u2 + cc.zeta);
-  store(M - 1, (1.0 - om) * f + om * feq);
-  const double acc = cc.gA0 + fcx * cc.gA1[0] + fcy * cc.gA1[1] + fcz * cc.gA1[2] + fcx * fcx * cc.gA2[0] +
-                     fcy * fcy * cc.gA2[1] + fcz * fcz * cc.gA2[2] + fcx * fcy * cc.gA2[3] + fcx * fcz * cc.gA2[4] +
-                     fcy * fcz * cc.gA2[5];
-  store(M, (1.0 - om) * gv + wi * acc);
+// ---- lattice passes of the step kernel ------------------------------------------------
+// The passes over the 27 directions go row by row: row r = (cy+1) + 3 (cz+1) holds the
+// directions i = 3 r + cx + 1, cx = -1, 0, 1.  cy and cz are uniform and cx is a
+// compile-time constant, so that every factor that depends on (cy, cz) alone is formed
+// once per row.
+//
+// Each (set, direction) plane is read and written through a buffer resource (base and
+// size in scalar registers) with the lane's byte offset in one vector register: the
+// address arithmetic of a load or store is scalar.  An offset outside the plane reads
+// zero and drops a store instead of touching other memory.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ Rsrc plane_rsrc(const void *p, uint32_t bytes) {
+  // word 3 of an untyped buffer with a 32-bit data format (gfx9 family)
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(Rsrc r, uint32_t off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bst(Rsrc r, uint32_t off, T v) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+  else if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
+}
+// plane k of NPAD elements of type T starting at buf (a padded plane is below 2 GiB)
+template <typename T>
+__device__ __forceinline__ Rsrc plane(const void *buf, const Geom &g, int k) {
+  const uint32_t bytes = (uint32_t)g.NPAD * (uint32_t)sizeof(T);
+  return plane_rsrc(static_cast<const char *>(buf) + (uint64_t)k * bytes, bytes);
 }
 
-// O7 for one direction, the stored species a < M-1 (eq. finalNumericalEquations with
-// F_ai of eq. fStar); fa(a) returns the pulled population, store(a, v) writes it.
-// Phi_b(u) - Phi_b(u + du_b) is telescoped over the three axis factors, each factor
-// difference in closed form, so the difference keeps relative precision:
-// Psi_c(xi) - Psi_c(xi + d) = d (s_c (2 xi + d) + t_c), with s_0 = 1, t_0 = 0 and
-// s_c = -1/2, t_c = -c/2 for c = +-1 (eq. phis).  Axis factor of species b:
-// Psi_c(u_alpha, zeta_b) = A_c(u_alpha) + B_c zeta_b.  The inter-species term is
-// evaluated in F; the equilibria that carry the species mass in FP64.
-template <int M, typename F, typename FaFn, typename StFn>
-__device__ __forceinline__ void collide_species(const CollideConsts &kc, const CollCoef<M, F> &cc, int cx, int cy,
-                                                int cz, FaFn &&fa, StFn &&store) {
-  const double u0 = cc.u0, u1 = cc.u1, u2 = cc.u2;
-  // B_c is -1 or 1/2, so (B_c T) R_b equals B_c (R_b T) exactly
-  double BxT = (cx == 0 ? -1.0 : 0.5) * cc.T, ByT = (cy == 0 ? -1.0 : 0.5) * cc.T,
-         BzT = (cz == 0 ? -1.0 : 0.5) * cc.T;
-  double Ax = psi_c<double>(cx, u0, u0 * u0), Ay = psi_c<double>(cy, u1, u1 * u1),
-         Az = psi_c<double>(cz, u2, u2 * u2);
-  const F Axf = F(Ax), Ayf = F(Ay), Azf = F(Az), BxTf = F(BxT), ByTf = F(ByT), BzTf = F(BzT);
-  const F sx = cx == 0 ? F(1) : F(-0.5), sy = cy == 0 ? F(1) : F(-0.5), sz = cz == 0 ? F(1) : F(-0.5);
-  const F tx = F(-0.5) * F(cx), ty = F(-0.5) * F(cy), tz = F(-0.5) * F(cz);
-  const F x2 = F(2) * F(u0), y2 = F(2) * F(u1), z2 = F(2) * F(u2);
-  // F_a = sum_b invD_ab dd_b, accumulated over b in increasing order
-  F Fa[M - 1];
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
-#pragma unroll
-  for (int b = 0; b < M; ++b) {
-    F Rb;
-    if constexpr (sizeof(F) == 4) Rb = kc.Raf[b]; else Rb = F(kc.Ra[b]);
-    const F ex = Axf + BxTf * Rb, ey = Ayf + ByTf * Rb, ez = Azf + BzTf * Rb;
-    const F d0 = cc.dv[b][0], d1 = cc.dv[b][1], d2 = cc.dv[b][2];
-    const F dx = d0 * (sx * (x2 + d0) + tx), dy = d1 * (sy * (y2 + d1) + ty), dz = d2 * (sz * (z2 + d2) + tz);
-    const F rx = ex - dx, ry = ey - dy;
-    const F dd = cc.tbw[b] * (dx * ey * ez + rx * dy * ez + rx * ry * dz);
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a) {
-      if (a == b) continue;
-      const int lo = a < b ? a : b, hi = a < b ? b : a;
-      const int k = lo * M - lo * (lo + 1) / 2 + (hi - lo - 1);
-      F c;
-      if constexpr (sizeof(F) == 4) c = kc.invDpf[k]; else c = F(kc.invDp[k]);
-      Fa[a] += c * dd;
-    }
-  }
-  // the FP64 axis factors are recomputed below rather than kept from above
-  opaque(Ax);
-  opaque(Ay);
-  opaque(Az);
-  opaque(BxT);
-  opaque(ByT);
-  opaque(BzT);
-#pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    const double Ra = kc.Ra[a];
-    const double phe = (Ax + BxT * Ra) * (Ay + ByT * Ra) * (Az + BzT * Ra);
-    store(a, double(cc.omb[a]) * fa(a) + cc.ca[a] * phe + double(cc.rcoef[a] * Fa[a]));
-  }
-}
+// The constants of the collision, read through a constant-address-space pointer: loads
+// through it are scalar, and a pointer passed through opaque_uniform() in each row makes
+// them be loaded again there instead of being held in scalar registers over the passes.
+typedef const __attribute__((address_space(4))) CollideConsts KC4;
+typedef const __attribute__((address_space(4))) Tables TB4;
 
-// Source of the pull along direction i: padded index of the source cell, and whether
-// it is an interior node (then the deferred corrections at it apply) with its index.
-struct DirSrc {
-  uint32_t ps;
-  uint32_t nc;    // interior index of the source, 0 for a ghost source
-  bool inner;
+// A lane's node for the pulls: its padded index and coordinates.
+struct LaneSrc {
+  uint32_t self;
+  int x, y, z;
 };
 
-__device__ __forceinline__ DirSrc dir_src(const Geom &g, int x, int y, int z, int i) {
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-  const RowSrc row = row_src(g, y, z, cy, cz);
-  int sx = x - cx;
-  if (g.per[0]) sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
-  const bool outx = sx < 0 || sx >= g.nx;
-  DirSrc d;
-  d.ps = row.prow + (uint32_t)(sx + g.px);
-  d.inner = !(row.nrow < 0 || outx);
-  d.nc = d.inner ? (uint32_t)(row.nrow + sx) : 0u;
-  return d;
+// padded index of the source of direction (0, cy, cz), y - cy and z - cz wrapped on
+// periodic axes (an open axis has a ghost layer and never wraps)
+__device__ __forceinline__ uint32_t row_source(const Geom &g, const LaneSrc &l, int cy, int cz) {
+  const int32_t NXY = g.NX * g.NY;
+  uint32_t p = l.self - (uint32_t)(cy * g.NX + cz * NXY);
+  if (g.per[1] && cy != 0) p += (l.y == (cy > 0 ? 0 : g.ny - 1)) ? (uint32_t)(cy * g.ny * g.NX) : 0u;
+  if (g.per[2] && cz != 0) p += (l.z == (cz > 0 ? 0 : g.nz - 1)) ? (uint32_t)(cz * g.nz * NXY) : 0u;
+  return p;
+}
+// padded index of the source of direction (CX, cy, cz) from that of (0, cy, cz)
+template <int CX>
+__device__ __forceinline__ uint32_t dir_source(const Geom &g, const LaneSrc &l, uint32_t row) {
+  uint32_t p = row - (uint32_t)CX;
+  if constexpr (CX != 0)
+    if (g.per[0]) p += (l.x == (CX > 0 ? 0 : g.nx - 1)) ? (uint32_t)(CX * g.nx) : 0u;
+  return p;
 }
 
-// Values of f and g pulled along one direction, with the deferred corrections at the
-// source; all loads without branches, so that they are issued together (a ghost
-// source reads the corrections of node 0 and discards them).
+// f and g pulled along one direction, with the deferred corrections at the source.  The
+// corrections live in padded planes whose ghost cells hold zero, so a ghost source adds
+// nothing.  The loads carry no branch, so that they are all in flight together: X is
+// read from the plane of the direction's axis (any plane off the axis directions, where
+// it is multiplied by zero), and the y and z components of Cg are read in every row.
 template <typename ST>
 struct PulledFG {
   ST f, g;
-  typename Fmt<ST>::Side x, cg[3];
-  bool inner;
+  typename Fmt<ST>::Side x, c[3];
 };
 
-template <int M, typename ST>
-__device__ __forceinline__ void pull_fg(const Geom &g, const ST *__restrict__ src,
-                                        const typename Fmt<ST>::Side *__restrict__ corr,
-                                        int x, int y, int z, int i, PulledFG<ST> &p) {
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1;
-  const DirSrc d = dir_src(g, x, y, z, i);
-  const int64_t NPAD = g.NPAD, N = g.N;
-  p.inner = d.inner;
-  p.f = ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, d.ps);
-  p.g = ld(src + ((int64_t)M * Q + i) * NPAD, d.ps);
-  const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
-  p.x = ld(corr + axis * N, d.nc);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) p.cg[k] = ld(corr + (3 + k) * N, d.nc);
-}
-
-template <int M, typename ST, typename F>
-__device__ __forceinline__ void collide_pulled_fg(const CollideConsts &kc, const CollCoef<M, F> &cc, int i,
-                                                  const PulledFG<ST> &p, ST *__restrict__ dst, int64_t NPAD,
-                                                  uint32_t pself) {
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+template <int M, typename ST, int CX>
+__device__ __forceinline__ void pull_fg(const Geom &g, const void *src, const void *corr, int i, int cy, int cz,
+                                        uint32_t ps, PulledFG<ST> &p) {
   using Side = typename Fmt<ST>::Side;
-  // deferred A_i.X on the axis directions (eq. Ai), rounded to the side precision
-  const double xs = (cx * cx + cy * cy + cz * cz) == 1 ? 0.5 * double(cx + cy + cz) : 0.0;
-  const double xc = double(Side(xs * double(p.x)));
-  const double f = pop_val(p.f, M - 1, i, kc) + (p.inner ? xc : 0.0);
-  // deferred Fourier-correction flux 3 w_i c_i . Cg (eq. corrFourier)
-  const double w3 = 3.0 * (w1(cx) * w1(cy) * w1(cz));
-  const double d = double(cx) * double(p.cg[0]) + double(cy) * double(p.cg[1]) + double(cz) * double(p.cg[2]);
-  const double gc = double(Side(w3 * d));
-  const double gv = pop_val(p.g, M, i, kc) + (p.inner ? gc : 0.0);
-  collide_fg<M, F>(kc, cc, cx, cy, cz, f, gv, [&](int set, double v) {
-    st(dst + ((int64_t)set * Q + i) * NPAD, pself, pop_enc<ST>(v, set, i, kc));
-  });
+  const uint32_t po = ps * (uint32_t)sizeof(ST), co = ps * (uint32_t)sizeof(Side);
+  p.f = bld<ST>(plane<ST>(src, g, (M - 1) * Q + i), po);
+  p.g = bld<ST>(plane<ST>(src, g, M * Q + i), po);
+  const int xa = __builtin_amdgcn_readfirstlane(CX != 0 ? 0 : (cy != 0 ? 1 : 2));
+  p.x = bld<Side>(plane<Side>(corr, g, xa), co);
+  if constexpr (CX != 0)
+    p.c[0] = bld<Side>(plane<Side>(corr, g, 3), co);
+  else
+    p.c[0] = Side(0);
+  p.c[1] = bld<Side>(plane<Side>(corr, g, 4), co);
+  p.c[2] = bld<Side>(plane<Side>(corr, g, 5), co);
+}
+
+// values of f and g along (CX, cy, cz) with their deferred corrections: 1/2 c.X on the
+// axis directions (eq. Ai) and the Fourier-correction flux 3 w_i c_i.Cg (eq.
+// corrFourier), each rounded to the side precision and added in FP64, the same way in
+// every kernel that pulls
+template <int M, typename ST, int CX, typename K>
+__device__ __forceinline__ void fg_values(const PulledFG<ST> &p, int i, int cy, int cz, const K &kc, double &f,
+                                          double &gv) {
+  using Side = typename Fmt<ST>::Side;
+  const double xs = (CX * CX + cy * cy + cz * cz) == 1 ? 0.5 * double(CX + cy + cz) : 0.0;
+  f = pop_val(p.f, M - 1, i, kc) + double(Side(xs * double(p.x)));
+  const double w3 = 3.0 * (w1(CX) * w1(cy) * w1(cz));
+  const double d = double(CX) * double(p.c[0]) + double(cy) * double(p.c[1]) + double(cz) * double(p.c[2]);
+  gv = pop_val(p.g, M, i, kc) + double(Side(w3 * d));
 }
 
 template <int M, typename ST>
-struct PulledS {
+struct PulledAll {
+  PulledFG<ST> fg;
   ST fa[M - 1];
 };
 
-template <int M, typename ST>
-__device__ __forceinline__ void pull_species(const Geom &g, const ST *__restrict__ src, int x, int y, int z, int i,
-                                             PulledS<M, ST> &p) {
-  const DirSrc d = dir_src(g, x, y, z, i);
-  const int64_t NPAD = g.NPAD;
+template <int M, typename ST, int CX>
+__device__ __forceinline__ void pull_all(const Geom &g, const void *src, const void *corr, int i, int cy, int cz,
+                                         uint32_t ps, PulledAll<M, ST> &p) {
+  pull_fg<M, ST, CX>(g, src, corr, i, cy, cz, ps, p.fg);
+  const uint32_t po = ps * (uint32_t)sizeof(ST);
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) p.fa[a] = ld(src + ((int64_t)a * Q + i) * NPAD, d.ps);
+  for (int a = 0; a < M - 1; ++a) p.fa[a] = bld<ST>(plane<ST>(src, g, a * Q + i), po);
 }
 
-template <int M, typename F>
-__device__ __forceinline__ void opaque_species(CollCoef<M, F> &cc) {
-  opaque(cc.u0);
-  opaque(cc.u1);
-  opaque(cc.u2);
-  opaque(cc.T);
+// Row partial sums of one pulled quantity v over cx: P0 = sum v, P1 = sum cx v,
+// P2 = sum cx^2 v, built from the three directions in the order cx = -1, 0, 1.
+struct RowSum {
+  double m, z;   // v at cx = -1 and cx = 0
+};
+
+template <int M>
+struct RowMoments {
+  RowSum f, g, a[M - 1];
+};
+
+template <int M, typename ST, int CX, typename K>
+__device__ __forceinline__ void row_moments_dir(const PulledAll<M, ST> &p, int i, int cy, int cz, const K &kc,
+                                                RowMoments<M> &rm, double (&mo)[14], double (&sp)[M - 1][4]) {
+  double f, gv;
+  fg_values<M, ST, CX>(p.fg, i, cy, cz, kc, f, gv);
+  double fa[M - 1];
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
-    opaque(cc.tbw[a]);
+  for (int a = 0; a < M - 1; ++a) fa[a] = pop_val(p.fa[a], a, i, kc);
+  if constexpr (CX == -1) {
+    rm.f.m = f;
+    rm.g.m = gv;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) opaque(cc.dv[a][d]);
+    for (int a = 0; a < M - 1; ++a) rm.a[a].m = fa[a];
+  } else if constexpr (CX == 0) {
+    rm.f.z = f;
+    rm.g.z = gv;
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) rm.a[a].z = fa[a];
+  } else {
+    // the row is complete: add it to the moments (eqs. Pa, sumfDotc, g0momTotalEnergy)
+    const double dy = cy, dz = cz;
+    const double f2 = rm.f.m + f, f1 = f - rm.f.m, f0 = f2 + rm.f.z;
+    mo[0] += f0;
+    mo[1] += f1;
+    mo[2] += dy * f0;
+    mo[3] += dz * f0;
+    mo[4] += f2;
+    mo[5] += (dy * dy) * f0;
+    mo[6] += (dz * dz) * f0;
+    mo[7] += dy * f1;
+    mo[8] += dz * f1;
+    mo[9] += (dy * dz) * f0;
+    const double g1 = gv - rm.g.m, g0 = (rm.g.m + gv) + rm.g.z;
+    mo[10] += g0;
+    mo[11] += g1;
+    mo[12] += dy * g0;
+    mo[13] += dz * g0;
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) {
+      const double s1 = fa[a] - rm.a[a].m, s0 = (rm.a[a].m + fa[a]) + rm.a[a].z;
+      sp[a][0] += s0;
+      sp[a][1] += s1;
+      sp[a][2] += dy * s0;
+      sp[a][3] += dz * s0;
+    }
   }
 }
 
-template <int M, typename ST, typename F>
-__device__ __forceinline__ void collide_pulled_species(const CollideConsts &kc, const CollCoef<M, F> &cc, int i,
-                                                       const PulledS<M, ST> &p, ST *__restrict__ dst, int64_t NPAD,
-                                                       uint32_t pself) {
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-  collide_species<M, F>(
-      kc, cc, cx, cy, cz, [&](int a) { return pop_val(p.fa[a], a, i, kc); },
-      [&](int a, double v) { st(dst + ((int64_t)a * Q + i) * NPAD, pself, pop_enc<ST>(v, a, i, kc)); });
-}
-
-// ---- step, part 1: the node-local kernel ----------------------------------------------
-// Values of all stored sets pulled along one direction, with the deferred corrections
-// at the source (branch-free, so that the loads are issued together).
+// O1: moments of all sets over the 27 directions.  The loads run two directions ahead
+// of the sums: at the start of row r, directions (r, -1) and (r, 0) are in flight.
 template <int M, typename ST>
-struct PulledAll {
-  ST f, g, fa[M - 1];
-  typename Fmt<ST>::Side x, cg[3];
-  bool inner;
-};
-
-template <int M, typename ST>
-__device__ __forceinline__ void pull_all(const Geom &g, const ST *__restrict__ src,
-                                         const typename Fmt<ST>::Side *__restrict__ corr,
-                                         int x, int y, int z, int i, PulledAll<M, ST> &p) {
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1;
-  const DirSrc d = dir_src(g, x, y, z, i);
-  const int64_t NPAD = g.NPAD, N = g.N;
-  p.inner = d.inner;
-  p.f = ld(src + ((int64_t)(M - 1) * Q + i) * NPAD, d.ps);
-  p.g = ld(src + ((int64_t)M * Q + i) * NPAD, d.ps);
+__device__ __forceinline__ void moments_pass(const Geom &g, const void *src, const void *corr, const LaneSrc &l,
+                                             KC4 *kp, double (&mo)[14], double (&sp)[M - 1][4]) {
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) p.fa[a] = ld(src + ((int64_t)a * Q + i) * NPAD, d.ps);
-  const int axis = cx != 0 ? 0 : (cy != 0 ? 1 : 2);
-  p.x = ld(corr + axis * N, d.nc);
+  for (int k = 0; k < 14; ++k) mo[k] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) p.cg[k] = ld(corr + (3 + k) * N, d.nc);
-}
-
-// O1 (eqs. Pa, sumfDotc, g0momTotalEnergy): add direction i to the moments
-template <int M, typename ST>
-__device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, const CollideConsts &kc,
-                                            double (&mo)[14], double (&sp)[M - 1][4]) {
-  using Side = typename Fmt<ST>::Side;
-  const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-  const double xs = (cx * cx + cy * cy + cz * cz) == 1 ? 0.5 * double(cx + cy + cz) : 0.0;
-  const double xc = double(Side(xs * double(p.x)));
-  const double f = pop_val(p.f, M - 1, i, kc) + (p.inner ? xc : 0.0);
-  const double w3 = 3.0 * (w1(cx) * w1(cy) * w1(cz));
-  const double d = double(cx) * double(p.cg[0]) + double(cy) * double(p.cg[1]) + double(cz) * double(p.cg[2]);
-  const double gc = double(Side(w3 * d));
-  const double gv = pop_val(p.g, M, i, kc) + (p.inner ? gc : 0.0);
-  const double fx = cx, fy = cy, fz = cz;
-  // rho, j (3), P (xx yy zz xy xz yz), rho E, q (3)
-  mo[0] += f;
-  mo[1] += fx * f;
-  mo[2] += fy * f;
-  mo[3] += fz * f;
-  mo[4] += (fx * fx) * f;
-  mo[5] += (fy * fy) * f;
-  mo[6] += (fz * fz) * f;
-  mo[7] += (fx * fy) * f;
-  mo[8] += (fx * fz) * f;
-  mo[9] += (fy * fz) * f;
-  mo[10] += gv;
-  mo[11] += fx * gv;
-  mo[12] += fy * gv;
-  mo[13] += fz * gv;
+  for (int a = 0; a < M - 1; ++a)
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    const double fa = pop_val(p.fa[a], a, i, kc);
-    sp[a][0] += fa;
-    sp[a][1] += fx * fa;
-    sp[a][2] += fy * fa;
-    sp[a][3] += fz * fa;
+    for (int k = 0; k < 4; ++k) sp[a][k] = 0.0;
+  PulledAll<M, ST> pa, pb, pc;
+  RowMoments<M> rm;
+  {
+    const uint32_t s0 = row_source(g, l, -1, -1);
+    pull_all<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, s0), pa);
+    pull_all<M, ST, 0>(g, src, corr, 1, -1, -1, dir_source<0>(g, l, s0), pb);
+  }
+#pragma unroll 1
+  for (int r = 0; r < 9; ++r) {
+    const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
+    KC4 *k = kp;
+    opaque_uniform(k);
+    // the next row (the last row reloads its own: no branch, so that the wait counts
+    // stay exact)
+    const int rn = r < 8 ? r + 1 : 8;
+    const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
+    const uint32_t s0 = row_source(g, l, cy, cz), s1 = row_source(g, l, ny, nz);
+    pull_all<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
+    row_moments_dir<M, ST, -1>(pa, 3 * r, cy, cz, *k, rm, mo, sp);
+    pull_all<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, s1), pa);
+    row_moments_dir<M, ST, 0>(pb, 3 * r + 1, cy, cz, *k, rm, mo, sp);
+    pull_all<M, ST, 0>(g, src, corr, 3 * rn + 1, ny, nz, dir_source<0>(g, l, s1), pb);
+    row_moments_dir<M, ST, 1>(pc, 3 * r + 2, cy, cz, *k, rm, mo, sp);
   }
 }
 
@@ -684,39 +664,24 @@ __device__ __forceinline__ void add_moments(int i, const PulledAll<M, ST> &p, co
 // store happens before the side channel at the end, so that the constant tables are
 // read with scalar loads throughout.
 template <int M, typename ST>
-__device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, const CollideConsts &kc,
-                                           const IslStash &sh, int64_t n, int x, int y, int z, int cur,
-                                           CollCoef<M, FT<ST>> &cc) {
+__device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 *kp, const IslStash &sh,
+                                           int64_t n, const LaneSrc &l, int cur, CollCoef<M, FT<ST>> &cc) {
   using SW = IslWords<M>;
   using F = FT<ST>;
   using Side = typename Fmt<ST>::Side;
-  const Tables &tb = *b.tab;
-  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
-  const Side *__restrict__ corr = static_cast<const Side *>(b.corr);
+  // the constant tables through the constant address space: their loads are scalar
+  // wherever they stand, also after stores and opaque() barriers
+  TB4 &tb = *(TB4 *)b.tab;
+  const void *src = b.pop[cur];
+  const void *corr = b.corr;
   const int64_t N = g.N;
   const double T0 = b.T[n];
-  (void)N;
 
-  // O1: moments; the loads of direction i+1 are in flight while direction i is summed
+  // O1: moments
   Macro<M> m;
   {
     double mo[14], sp[M - 1][4];
-#pragma unroll
-    for (int k = 0; k < 14; ++k) mo[k] = 0.0;
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) sp[a][k] = 0.0;
-    PulledAll<M, ST> pa, pb;
-    pull_all<M, ST>(g, src, corr, x, y, z, 0, pa);
-#pragma unroll 1
-    for (int i = 0; i < Q - 1; i += 2) {
-      pull_all<M, ST>(g, src, corr, x, y, z, i + 1, pb);
-      add_moments<M, ST>(i, pa, kc, mo, sp);
-      pull_all<M, ST>(g, src, corr, x, y, z, i + 2, pa);
-      add_moments<M, ST>(i + 1, pb, kc, mo, sp);
-    }
-    add_moments<M, ST>(Q - 1, pa, kc, mo, sp);
+    moments_pass<M, ST>(g, src, corr, l, kp, mo, sp);
     m.rho = mo[0];
     const double inv_rho = 1.0 / mo[0];
     m.u[0] = mo[1] * inv_rho;
@@ -986,68 +951,186 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, cons
   }
 }
 
-// O7 + O8 for f and g over the 27 directions: the loads of direction i+1 are in flight
-// while direction i is collided; unrolled twice so that the two sets of pulled values
-// alternate in registers.
-template <int M, typename ST, typename F>
-__device__ __forceinline__ void fg_pass(const Geom &g, const ST *__restrict__ src, ST *__restrict__ dst,
-                                        const typename Fmt<ST>::Side *__restrict__ corr, const CollideConsts &kc,
-                                        const CollCoef<M, F> &cc, int x, int y, int z, uint32_t pself) {
-  const int64_t NPAD = g.NPAD;
-  PulledFG<ST> pa, pb;
-  pull_fg<M, ST>(g, src, corr, x, y, z, 0, pa);
-#pragma unroll 1
-  for (int i = 0; i < Q - 1; i += 2) {
-    pull_fg<M, ST>(g, src, corr, x, y, z, i + 1, pb);
-    collide_pulled_fg<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
-    pull_fg<M, ST>(g, src, corr, x, y, z, i + 2, pa);
-    collide_pulled_fg<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
-  }
-  collide_pulled_fg<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
+// O7 + O8 for f and g of one direction (eqs. f, g) from the factors of its row:
+// f^eq = (rho Psi_y Psi_z) Psi_x, and g' = (1 - omega) g + w_i [A0 + A1.c + A2 : cc]
+// with the (cy, cz) part of the bracket summed once per row.  A_i.X and the q^corr part
+// are added by the next pull.
+struct RowFG {
+  double rf;       // rho Psi_cy(u_y) Psi_cz(u_z)
+  double R0, R1;   // bracket = R0 + cx R1 + cx^2 A2_xx
+  double wyz;      // w1(cy) w1(cz)
+};
+
+template <int M, typename F>
+__device__ __forceinline__ RowFG fg_row(const CollCoef<M, F> &cc, int cy, int cz) {
+  RowFG rw;
+  const double u1 = cc.u1, u2 = cc.u2;
+  rw.rf = cc.rho * psi_c<double>(cy, u1, u1 * u1 + cc.zeta) * psi_c<double>(cz, u2, u2 * u2 + cc.zeta);
+  const double dy = cy, dz = cz;
+  rw.R0 = cc.gA0 + dy * cc.gA1[1] + dz * cc.gA1[2] + (dy * dy) * cc.gA2[1] + (dz * dz) * cc.gA2[2] +
+          (dy * dz) * cc.gA2[5];
+  rw.R1 = cc.gA1[0] + dy * cc.gA2[3] + dz * cc.gA2[4];
+  rw.wyz = w1(cy) * w1(cz);
+  return rw;
 }
 
-// O7 + O8 for the stored species, pipelined like fg_pass
-template <int M, typename ST, typename F>
-__device__ __forceinline__ void species_pass(const Geom &g, const ST *__restrict__ src, ST *__restrict__ dst,
-                                             const CollideConsts &kc, CollCoef<M, F> &cc, int x, int y, int z,
-                                             uint32_t pself) {
-  const int64_t NPAD = g.NPAD;
-  PulledS<M, ST> pa, pb;
-  pull_species<M, ST>(g, src, x, y, z, 0, pa);
-#pragma unroll 1
-  for (int i = 0; i < Q - 1; i += 2) {
-    pull_species<M, ST>(g, src, x, y, z, i + 1, pb);
-    opaque_species<M, F>(cc);
-    collide_pulled_species<M, ST, F>(kc, cc, i, pa, dst, NPAD, pself);
-    pull_species<M, ST>(g, src, x, y, z, i + 2, pa);
-    opaque_species<M, F>(cc);
-    collide_pulled_species<M, ST, F>(kc, cc, i + 1, pb, dst, NPAD, pself);
-  }
-  collide_pulled_species<M, ST, F>(kc, cc, Q - 1, pa, dst, NPAD, pself);
+template <int M, typename ST, typename F, int CX, typename K>
+__device__ __forceinline__ void collide_fg_dir(const Geom &g, void *dst, const CollCoef<M, F> &cc, const RowFG &rw,
+                                               const PulledFG<ST> &p, int i, int cy, int cz, const K &kc,
+                                               uint32_t so) {
+  double f, gv;
+  fg_values<M, ST, CX>(p, i, cy, cz, kc, f, gv);
+  const double om = kc.omega;
+  const double u0 = cc.u0;
+  const double feq = rw.rf * psi_c<double>(CX, u0, u0 * u0 + cc.zeta);
+  bst<ST>(plane<ST>(dst, g, (M - 1) * Q + i), so, pop_enc<ST>((1.0 - om) * f + om * feq, M - 1, i, kc));
+  const double acc = CX == 0 ? rw.R0 : rw.R0 + double(CX) * rw.R1 + cc.gA2[0];
+  bst<ST>(plane<ST>(dst, g, M * Q + i), so, pop_enc<ST>((1.0 - om) * gv + (w1(CX) * rw.wyz) * acc, M, i, kc));
 }
 
-// Fused step: the node-local part, then the collide passes from the coefficients in
-// registers.  The populations are read twice, the second time mostly from cache, and
-// no record goes through memory.
+// O7 + O8 for the stored species a < M-1 (eq. finalNumericalEquations with F_ai of eq.
+// fStar).  Phi_b(u) - Phi_b(u + du_b) is telescoped over the three axis factors, each
+// factor difference in closed form so that the difference keeps its relative precision:
+// Psi_c(xi) - Psi_c(xi + d) = d (s_c d + s_c 2 xi + t_c), with s_0 = 1, t_0 = 0 and
+// s_c = -1/2, t_c = -c/2 for c = +-1 (eq. phis).  With e = Psi_c(u_alpha, zeta_b) =
+// A_c(u_alpha) + B_c zeta_b per axis, d the factor differences and r = e - d,
+//   Phi_b(u) - Phi_b(u + du_b) = d_x (e_y e_z) + r_x (d_y e_z + r_y d_z),
+// whose two brackets depend on (cy, cz) only.  The inter-species term is evaluated in
+// F; the equilibria that carry the species mass in FP64.
+template <int M, typename F>
+struct RowSpecies {
+  F Y1[M], Y2[M];       // rho_b zeta_b e_y e_z and rho_b zeta_b (d_y e_z + r_y d_z)
+  double pyz[M - 1];    // c_a (A_y + B_y zeta_a)(A_z + B_z zeta_a)
+};
+
+template <typename F, typename K>
+__device__ __forceinline__ F gas_const(const K &kc, int b) {
+  if constexpr (sizeof(F) == 4) return kc.Raf[b]; else return F(kc.Ra[b]);
+}
+template <int M, typename F, typename K>
+__device__ __forceinline__ F inv_diff(const K &kc, int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  const int k = lo * M - lo * (lo + 1) / 2 + (hi - lo - 1);
+  if constexpr (sizeof(F) == 4) return kc.invDpf[k]; else return F(kc.invDp[k]);
+}
+
+template <int M, typename F, typename K>
+__device__ __forceinline__ void species_row(const CollCoef<M, F> &cc, double T, int cy, int cz, const K &kc,
+                                            RowSpecies<M, F> &rs) {
+  const double u1 = cc.u1, u2 = cc.u2;
+  // B_c is -1 or 1/2, so (B_c T) R_b equals B_c (R_b T) exactly
+  const double Ay = psi_c<double>(cy, u1, u1 * u1), Az = psi_c<double>(cz, u2, u2 * u2);
+  const double ByT = (cy == 0 ? -1.0 : 0.5) * T, BzT = (cz == 0 ? -1.0 : 0.5) * T;
+  const F Ayf = F(Ay), Azf = F(Az), ByTf = F(ByT), BzTf = F(BzT);
+  const F sy = cy == 0 ? F(1) : F(-0.5), sz = cz == 0 ? F(1) : F(-0.5);
+  const F ky = sy * (F(2) * F(u1)) + F(-0.5) * F(cy), kz = sz * (F(2) * F(u2)) + F(-0.5) * F(cz);
+#pragma unroll
+  for (int b = 0; b < M; ++b) {
+    const F Rb = gas_const<F>(kc, b);
+    const F ey = Ayf + ByTf * Rb, ez = Azf + BzTf * Rb;
+    const F d1 = cc.dv[b][1], d2 = cc.dv[b][2];
+    const F dy = d1 * (sy * d1 + ky), dz = d2 * (sz * d2 + kz);
+    const F ry = ey - dy;
+    rs.Y1[b] = cc.tbw[b] * (ey * ez);
+    rs.Y2[b] = cc.tbw[b] * (dy * ez + ry * dz);
+  }
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    const double Ra = kc.Ra[a];
+    rs.pyz[a] = cc.ca[a] * ((Ay + ByT * Ra) * (Az + BzT * Ra));
+  }
+}
+
+template <int M, typename ST, typename F, int CX, typename K>
+__device__ __forceinline__ void collide_species_dir(const Geom &g, void *dst, const CollCoef<M, F> &cc,
+                                                    double u0, double T, const RowSpecies<M, F> &rs,
+                                                    const ST (&fa)[M - 1], int i, const K &kc, uint32_t so) {
+  const double Ax = psi_c<double>(CX, u0, u0 * u0);
+  const double BxT = (CX == 0 ? -1.0 : 0.5) * T;
+  const F Axf = F(Ax), BxTf = F(BxT);
+  constexpr F sx = CX == 0 ? F(1) : F(-0.5);
+  const F kx = sx * (F(2) * F(u0)) + F(-0.5 * CX);
+  // F_a = sum_b (1/D_ab) dd_b, accumulated over b in increasing order
+  F Fa[M - 1];
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) Fa[a] = F(0);
+#pragma unroll
+  for (int b = 0; b < M; ++b) {
+    const F ex = Axf + BxTf * gas_const<F>(kc, b);
+    const F d0 = cc.dv[b][0];
+    const F dx = d0 * (sx * d0 + kx);
+    const F rx = ex - dx;
+    const F dd = dx * rs.Y1[b] + rx * rs.Y2[b];
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a)
+      if (a != b) Fa[a] += inv_diff<M, F>(kc, a, b) * dd;
+  }
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    const double ex = Ax + BxT * kc.Ra[a];
+    const double v = double(cc.omb[a]) * pop_val(fa[a], a, i, kc) + rs.pyz[a] * ex + double(cc.rcoef[a] * Fa[a]);
+    bst<ST>(plane<ST>(dst, g, a * Q + i), so, pop_enc<ST>(v, a, i, kc));
+  }
+}
+
+// O7 + O8 over the 27 directions: f, g and the stored species of one direction from
+// the factors of its row, with the loads of the next direction in flight while the
+// current one is collided
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void collide_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
+                                             const CollCoef<M, F> &cc, const LaneSrc &l) {
+  const uint32_t so = l.self * (uint32_t)sizeof(ST);
+  PulledAll<M, ST> pa, pb, pc;
+  pull_all<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
+#pragma unroll 1
+  for (int r = 0; r < 9; ++r) {
+    const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
+    KC4 *k = kp;
+    opaque_uniform(k);
+    double u0 = cc.u0, T = cc.T;
+    opaque(u0);
+    opaque(T);
+    const uint32_t s0 = row_source(g, l, cy, cz);
+    const RowFG rw = fg_row<M, F>(cc, cy, cz);
+    RowSpecies<M, F> rs;
+    species_row<M, F>(cc, T, cy, cz, *k, rs);
+    pull_all<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
+    collide_fg_dir<M, ST, F, -1>(g, dst, cc, rw, pa.fg, 3 * r, cy, cz, *k, so);
+    collide_species_dir<M, ST, F, -1>(g, dst, cc, u0, T, rs, pa.fa, 3 * r, *k, so);
+    pull_all<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
+    collide_fg_dir<M, ST, F, 0>(g, dst, cc, rw, pb.fg, 3 * r + 1, cy, cz, *k, so);
+    collide_species_dir<M, ST, F, 0>(g, dst, cc, u0, T, rs, pb.fa, 3 * r + 1, *k, so);
+    {
+      // first direction of the next row (the last row reloads its own: no branch, so
+      // that the wait counts stay exact)
+      const int rn = r < 8 ? r + 1 : 8;
+      const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
+      pull_all<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
+    }
+    collide_fg_dir<M, ST, F, 1>(g, dst, cc, rw, pc.fg, 3 * r + 2, cy, cz, *k, so);
+    collide_species_dir<M, ST, F, 1>(g, dst, cc, u0, T, rs, pc.fa, 3 * r + 2, *k, so);
+  }
+}
+
+// Fused step: the node-local part, then the collide pass from the coefficients in
+// registers.  The populations are read twice, and no record goes through memory.
 template <int M, typename ST>
-__global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, CollideConsts kc, int cur) {
+__global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cur) {
   using F = FT<ST>;
   __shared__ double words[IslWords<M>::WORDS * ISL_BLOCK];
   const IslStash sh{(lds_double *)&words[threadIdx.x]};
   const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
-  const int x = (int)(n % g.nx);
-  const int y = (int)((n / g.nx) % g.ny);
-  const int z = (int)(n / ((int64_t)g.nx * g.ny));
+  LaneSrc l;
+  l.x = (int)(n % g.nx);
+  l.y = (int)((n / g.nx) % g.ny);
+  l.z = (int)(n / ((int64_t)g.nx * g.ny));
+  l.self = ((uint32_t)(l.z + g.pz) * (uint32_t)g.NY + (uint32_t)(l.y + g.py)) * (uint32_t)g.NX +
+           (uint32_t)(l.x + g.px);
+  KC4 *kp = (KC4 *)b.kc;
   CollCoef<M, F> cc;
-  node_local<M, ST>(g, b, kc, sh, n, x, y, z, cur, cc);
-  const ST *__restrict__ src = static_cast<const ST *>(b.pop[cur]);
-  ST *__restrict__ dst = static_cast<ST *>(b.pop[cur ^ 1]);
-  const typename Fmt<ST>::Side *__restrict__ corr = static_cast<const typename Fmt<ST>::Side *>(b.corr);
-  const uint32_t pself = ((uint32_t)(z + g.pz) * (uint32_t)g.NY + (uint32_t)(y + g.py)) * (uint32_t)g.NX +
-                         (uint32_t)(x + g.px);
-  fg_pass<M, ST, F>(g, src, dst, corr, kc, cc, x, y, z, pself);
-  species_pass<M, ST, F>(g, src, dst, kc, cc, x, y, z, pself);
+  node_local<M, ST>(g, b, kp, sh, n, l, cur, cc);
+  collide_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
 }
 
 // ---- psi_alpha = (1/omega - 1/2) d_alpha phi_alpha (isotropic gradient) ------------
@@ -1120,11 +1203,14 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
       if constexpr (cz != 0) C[2] += (cz * w) * hy;
     }
   });
+  // padded planes: the ghost cells keep the zero they are cleared to at init
   CT *corr = static_cast<CT *>(b.corr);
+  const int64_t NPAD = g.NPAD;
+  const int64_t pn = ((int64_t)(z + g.pz) * g.NY + (y + g.py)) * g.NX + (x + g.px);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    corr[d * N + n] = CT(X[d]);
-    corr[(3 + d) * N + n] = CT(C[d]);
+    corr[d * NPAD + pn] = CT(X[d]);
+    corr[(3 + d) * NPAD + pn] = CT(C[d]);
   }
 }
 
@@ -1287,7 +1373,7 @@ __global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, CollideConsts
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const int64_t N = g.N;
   using Side = typename Fmt<ST>::Side;
-  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * N, N};
+  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * g.NPAD, g.NPAD};
   Macro<M> m;
   node_moments<M, ST>(g, static_cast<const ST *>(b.pop[cur]), cr, kc, x, y, z, m);
   const Tables &tb = *b.tab;
@@ -1318,10 +1404,10 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, CollideConsts
   const int64_t n = nodes[k];
   if (n < 0 || n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
-  const int64_t N = g.N, NPAD = g.NPAD;
+  const int64_t NPAD = g.NPAD;
   using Side = typename Fmt<ST>::Side;
   const ST *pop = static_cast<const ST *>(b.pop[cur]);
-  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * N, N};
+  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * g.NPAD, g.NPAD};
   const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
   const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
   const AxisSrc az = axis_src(z, g.nz, g.per[2]);
@@ -1374,7 +1460,8 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 template <int M, typename ST, typename RT>
 struct RunStep {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
-    hipLaunchKernelGGL((k_step<M, ST>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b, kc, cur);
+    (void)kc;   // k_step reads the device copy of the constants (Buffers::kc)
+    hipLaunchKernelGGL((k_step<M, ST>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b, cur);
     return hipGetLastError();
   }
 };

@@ -40,9 +40,10 @@ struct Tables {
   double omega, omega1;
 };
 
-// Constants of the step passed as kernel arguments: they are read with scalar loads
-// from the argument segment, which stays valid after a kernel's first store to
-// global memory.
+// Constants of the collision.  The init, ghost and output kernels take them as a kernel
+// argument; the step kernel reads a copy in the workspace through a constant-address
+// pointer.  Both are read with scalar loads, which stay valid after a kernel's first
+// store to global memory.
 struct CollideConsts {
   double omega;
   double Ra[MAXM];                       // lattice gas constants kappa R_U / m_a
@@ -76,7 +77,8 @@ struct Buffers {
   void *side_rho;             // [N]   density (ghost equilibria)
   void *side_u;               // [3][N] velocity (ghost equilibria)
   void *psi;                  // [3][N]
-  void *corr;                 // [6][N]: X (3), then the energy-flux correction (3)
+  void *corr;                 // [6][NPAD]: X (3), then the energy-flux correction (3); zero in ghost cells
+  const CollideConsts *kc;    // device copy of the collision constants
 };
 
 // launchers (lbm_device.hip)

@@ -164,6 +164,20 @@ def test_deviation_formats_need_a_valid_reference_state(lib):
     assert code == -1 and "storage" in msg
 
 
+def test_plane_offsets_stay_32_bit(lib):
+    """One padded plane times the element size must stay below 2 GiB (8 bytes for FP64
+    storage, 4 otherwise): 700^3 periodic fits in FP32 and not in FP64."""
+    for storage, ok in ((W.STORE_F32, True), (W.STORE_F64, False)):
+        d, keep = lbm.make_desc(W.config1(), storage)
+        d.nx = d.ny = d.nz = 700
+        code, n, msg = _ws(lib, d)
+        if ok:
+            assert code == 0, msg
+            assert n > 2 * 4 * 27 * 700 ** 3 * 4
+        else:
+            assert code == -1 and "2 GiB" in msg, msg
+
+
 def test_create_rejects_bad_workspace_without_device(lib):
     d, keep = _desc(W.config1())
     h = C.c_void_p()
