@@ -621,8 +621,8 @@ __device__ __forceinline__ void row_moments_dir(const PulledAll<M, ST> &p, int i
   }
 }
 
-// O1: moments of all sets over the 27 directions.  The loads run two directions ahead
-// of the sums: at the start of row r, directions (r, -1) and (r, 0) are in flight.
+// O1: moments of all sets over the 27 directions; the loads of the next direction are in
+// flight while the current one is summed
 template <int M, typename ST>
 __device__ __forceinline__ void moments_pass(const Geom &g, const void *src, const void *corr, const LaneSrc &l,
                                              KC4 *kp, double (&mo)[14], double (&sp)[M - 1][4]) {
@@ -634,26 +634,22 @@ __device__ __forceinline__ void moments_pass(const Geom &g, const void *src, con
     for (int k = 0; k < 4; ++k) sp[a][k] = 0.0;
   PulledAll<M, ST> pa, pb, pc;
   RowMoments<M> rm;
-  {
-    const uint32_t s0 = row_source(g, l, -1, -1);
-    pull_all<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, s0), pa);
-    pull_all<M, ST, 0>(g, src, corr, 1, -1, -1, dir_source<0>(g, l, s0), pb);
-  }
+  pull_all<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
 #pragma unroll 1
   for (int r = 0; r < 9; ++r) {
     const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
     KC4 *k = kp;
     opaque_uniform(k);
-    // the next row (the last row reloads its own: no branch, so that the wait counts
-    // stay exact)
-    const int rn = r < 8 ? r + 1 : 8;
-    const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
-    const uint32_t s0 = row_source(g, l, cy, cz), s1 = row_source(g, l, ny, nz);
-    pull_all<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
+    const uint32_t s0 = row_source(g, l, cy, cz);
+    pull_all<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
     row_moments_dir<M, ST, -1>(pa, 3 * r, cy, cz, *k, rm, mo, sp);
-    pull_all<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, s1), pa);
+    pull_all<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
     row_moments_dir<M, ST, 0>(pb, 3 * r + 1, cy, cz, *k, rm, mo, sp);
-    pull_all<M, ST, 0>(g, src, corr, 3 * rn + 1, ny, nz, dir_source<0>(g, l, s1), pb);
+    {
+      const int rn = r < 8 ? r + 1 : 8;
+      const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
+      pull_all<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
+    }
     row_moments_dir<M, ST, 1>(pc, 3 * r + 2, cy, cz, *k, rm, mo, sp);
   }
 }
@@ -997,10 +993,17 @@ __device__ __forceinline__ void collide_fg_dir(const Geom &g, void *dst, const C
 //   Phi_b(u) - Phi_b(u + du_b) = d_x (e_y e_z) + r_x (d_y e_z + r_y d_z),
 // whose two brackets depend on (cy, cz) only.  The inter-species term is evaluated in
 // F; the equilibria that carry the species mass in FP64.
+// The FP64 (y, z) factor of the species equilibria is kept per row when F is FP32;
+// with an FP64 F term it is formed per direction from the row's axis factors, which
+// holds fewer registers.
+template <typename F>
+constexpr bool kRowEquilibrium = sizeof(F) == 4;
+
 template <int M, typename F>
 struct RowSpecies {
   F Y1[M], Y2[M];       // rho_b zeta_b e_y e_z and rho_b zeta_b (d_y e_z + r_y d_z)
-  double pyz[M - 1];    // c_a (A_y + B_y zeta_a)(A_z + B_z zeta_a)
+  double pyz[kRowEquilibrium<F> ? M - 1 : 1];   // c_a (A_y + B_y zeta_a)(A_z + B_z zeta_a)
+  double Ay, Az, ByT, BzT;                        // axis factors, without kRowEquilibrium
 };
 
 template <typename F, typename K>
@@ -1034,10 +1037,17 @@ __device__ __forceinline__ void species_row(const CollCoef<M, F> &cc, double T, 
     rs.Y1[b] = cc.tbw[b] * (ey * ez);
     rs.Y2[b] = cc.tbw[b] * (dy * ez + ry * dz);
   }
+  if constexpr (kRowEquilibrium<F>) {
 #pragma unroll
-  for (int a = 0; a < M - 1; ++a) {
-    const double Ra = kc.Ra[a];
-    rs.pyz[a] = cc.ca[a] * ((Ay + ByT * Ra) * (Az + BzT * Ra));
+    for (int a = 0; a < M - 1; ++a) {
+      const double Ra = kc.Ra[a];
+      rs.pyz[a] = cc.ca[a] * ((Ay + ByT * Ra) * (Az + BzT * Ra));
+    }
+  } else {
+    rs.Ay = Ay;
+    rs.Az = Az;
+    rs.ByT = ByT;
+    rs.BzT = BzT;
   }
 }
 
@@ -1067,9 +1077,81 @@ __device__ __forceinline__ void collide_species_dir(const Geom &g, void *dst, co
   }
 #pragma unroll
   for (int a = 0; a < M - 1; ++a) {
-    const double ex = Ax + BxT * kc.Ra[a];
-    const double v = double(cc.omb[a]) * pop_val(fa[a], a, i, kc) + rs.pyz[a] * ex + double(cc.rcoef[a] * Fa[a]);
+    const double Ra = kc.Ra[a];
+    const double ex = Ax + BxT * Ra;
+    double eq;
+    if constexpr (kRowEquilibrium<F>)
+      eq = rs.pyz[a] * ex;
+    else
+      eq = cc.ca[a] * (((rs.Ay + rs.ByT * Ra) * (rs.Az + rs.BzT * Ra)) * ex);
+    const double v = double(cc.omb[a]) * pop_val(fa[a], a, i, kc) + eq + double(cc.rcoef[a] * Fa[a]);
     bst<ST>(plane<ST>(dst, g, a * Q + i), so, pop_enc<ST>(v, a, i, kc));
+  }
+}
+
+// O7 + O8 for f and g alone over the 27 directions (the two-pass form of the
+// collision, for formats whose one-pass form holds too many registers)
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void fg_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
+                                        const CollCoef<M, F> &cc, const LaneSrc &l) {
+  const uint32_t so = l.self * (uint32_t)sizeof(ST);
+  PulledFG<ST> pa, pb, pc;
+  pull_fg<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
+#pragma unroll 1
+  for (int r = 0; r < 9; ++r) {
+    const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
+    KC4 *k = kp;
+    opaque_uniform(k);
+    const uint32_t s0 = row_source(g, l, cy, cz);
+    const RowFG rw = fg_row<M, F>(cc, cy, cz);
+    pull_fg<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
+    collide_fg_dir<M, ST, F, -1>(g, dst, cc, rw, pa, 3 * r, cy, cz, *k, so);
+    pull_fg<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
+    collide_fg_dir<M, ST, F, 0>(g, dst, cc, rw, pb, 3 * r + 1, cy, cz, *k, so);
+    {
+      const int rn = r < 8 ? r + 1 : 8;
+      const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
+      pull_fg<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
+    }
+    collide_fg_dir<M, ST, F, 1>(g, dst, cc, rw, pc, 3 * r + 2, cy, cz, *k, so);
+  }
+}
+
+template <int M, typename ST>
+__device__ __forceinline__ void pull_species(const Geom &g, const void *src, int i, uint32_t ps, ST (&fa)[M - 1]) {
+  const uint32_t po = ps * (uint32_t)sizeof(ST);
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) fa[a] = bld<ST>(plane<ST>(src, g, a * Q + i), po);
+}
+
+// O7 + O8 for the stored species alone, pipelined like fg_pass
+template <int M, typename ST, typename F>
+__device__ __forceinline__ void species_pass(const Geom &g, const void *src, void *dst, KC4 *kp,
+                                             const CollCoef<M, F> &cc, const LaneSrc &l) {
+  const uint32_t so = l.self * (uint32_t)sizeof(ST);
+  ST pa[M - 1], pb[M - 1], pc[M - 1];
+  pull_species<M, ST>(g, src, 0, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
+#pragma unroll 1
+  for (int r = 0; r < 9; ++r) {
+    const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
+    KC4 *k = kp;
+    opaque_uniform(k);
+    double u0 = cc.u0, T = cc.T;
+    opaque(u0);
+    opaque(T);
+    const uint32_t s0 = row_source(g, l, cy, cz);
+    RowSpecies<M, F> rs;
+    species_row<M, F>(cc, T, cy, cz, *k, rs);
+    pull_species<M, ST>(g, src, 3 * r + 1, dir_source<0>(g, l, s0), pb);
+    collide_species_dir<M, ST, F, -1>(g, dst, cc, u0, T, rs, pa, 3 * r, *k, so);
+    pull_species<M, ST>(g, src, 3 * r + 2, dir_source<1>(g, l, s0), pc);
+    collide_species_dir<M, ST, F, 0>(g, dst, cc, u0, T, rs, pb, 3 * r + 1, *k, so);
+    {
+      const int rn = r < 8 ? r + 1 : 8;
+      const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
+      pull_species<M, ST>(g, src, 3 * rn, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
+    }
+    collide_species_dir<M, ST, F, 1>(g, dst, cc, u0, T, rs, pc, 3 * r + 2, *k, so);
   }
 }
 
@@ -1113,7 +1195,9 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
 }
 
 // Fused step: the node-local part, then the collide pass from the coefficients in
-// registers.  The populations are read twice, and no record goes through memory.
+// registers (FP32 storage; the other formats collide f and g, then the species, in
+// two passes that each hold fewer registers).  The populations are read twice, and no
+// record goes through memory.
 template <int M, typename ST>
 __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cur) {
   using F = FT<ST>;
@@ -1130,7 +1214,12 @@ __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cu
   KC4 *kp = (KC4 *)b.kc;
   CollCoef<M, F> cc;
   node_local<M, ST>(g, b, kp, sh, n, l, cur, cc);
-  collide_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
+  if constexpr (sizeof(ST) == 4 && sizeof(F) == 4) {
+    collide_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
+  } else {
+    fg_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
+    species_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], kp, cc, l);
+  }
 }
 
 // ---- psi_alpha = (1/omega - 1/2) d_alpha phi_alpha (isotropic gradient) ------------
