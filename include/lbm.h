@@ -165,6 +165,19 @@ lbm_status lbm_macros(lbm_handle h, double *d_rho, double *d_u, double *d_T, dou
 lbm_status lbm_populations(lbm_handle h, const int64_t *d_nodes, int64_t n_nodes, double *d_out,
                            double *d_T_out, void *stream);
 
+/* Diagnostics of the current state (Sec. 5.2), as lbm_macros reports it:
+ *   d_hrr[N]     heat release rate -sum_a H_a rho_dot_a at every node, in lattice
+ *                units (H_a the species enthalpy R_a T h_a(T), rho_dot_a the production
+ *                rate by mass action per step, the same as the collision's source);
+ *   d_totals[LBM_DIAG_TOTALS]  sums over the lattice: [0] heat release rate, [1] the
+ *                number of nodes with T >= T_iso (the burnt volume), [2] mass sum rho,
+ *                [3] total energy sum rho E.
+ * Either output may be NULL.  Device FP64 buffers owned by the caller; the sums are
+ * formed in a fixed order (the same value on every call for the same state).  Uses
+ * the diagnostics section of the workspace: concurrent calls on one handle race. */
+#define LBM_DIAG_TOTALS 4
+lbm_status lbm_diagnostics(lbm_handle h, double T_iso, double *d_hrr, double *d_totals, void *stream);
+
 /* Discrete adjoint of one step.  Not provided by this build: returns
  * LBM_ERR_UNSUPPORTED. */
 lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, double *d_grad_params,

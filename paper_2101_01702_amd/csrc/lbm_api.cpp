@@ -24,7 +24,7 @@ thread_local std::string g_last_error;
 size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t status, tables, consts, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, total;
+  size_t status, tables, consts, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, diag, total;
   size_t corr_bytes;
 };
 
@@ -76,6 +76,7 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.psi = take(3 * N * ct);
   L.corr_bytes = 6 * (size_t)g.NPAD * ct;   // deferred corrections, padded planes
   L.corr = take(L.corr_bytes);
+  L.diag = take((size_t)LBM_DIAG_TOTALS * ((N + 127) / 128) * 8);   // diagnostics partial sums
   L.total = off;
   return L;
 }
@@ -398,6 +399,7 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   b.psi = ws + L.psi;
   b.corr = ws + L.corr;
   b.kc = reinterpret_cast<const CollideConsts *>(ws + L.consts);
+  b.diag = reinterpret_cast<double *>(ws + L.diag);
   Tables t;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
@@ -513,6 +515,16 @@ lbm_status lbm_populations(lbm_handle h, const int64_t *d_nodes, int64_t n_nodes
   hipError_t e = launch_export(h->g, h->b, h->kc, h->d.storage, h->cur, d_nodes, n_nodes, d_out, d_T_out,
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(h, e, "populations");
+  return LBM_OK;
+}
+
+lbm_status lbm_diagnostics(lbm_handle h, double T_iso, double *d_hrr, double *d_totals, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!std::isfinite(T_iso)) return arg_fail(h, "T_iso must be finite");
+  if (!d_hrr && !d_totals) return LBM_OK;
+  hipError_t e = launch_diag(h->g, h->b, h->kc, h->d.storage, h->cur, T_iso, d_hrr, d_totals,
+                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "diagnostics");
   return LBM_OK;
 }
 

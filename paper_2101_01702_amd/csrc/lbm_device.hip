@@ -1304,55 +1304,87 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
 }
 
 // ---- equilibria of one state (init and ghosts) --------------------------------------
-template <int M, typename ST>
-__device__ __forceinline__ void write_equilibria(const Tables &tb, const CollideConsts &kc,
-                                                 ST *__restrict__ dst, int64_t NPAD, const int64_t (&pidx)[27],
-                                                 double rho, const double *u, double T, const double *Y) {
-  double zeta_a[M], zeta = 0.0, H = 0.0, U = 0.0;
+// The moments of the equilibria of one state (eqs. feq, gieq): the species temperature
+// factors, and the Grad coefficients of g^eq.
+template <int M>
+struct EqState {
+  double rho, u[3], su[3], zeta, zeta_a[M], Y[M];
+  double A0, qeq[3], Rd[3], Ro[3];   // Rd: 4.5 R_dd - 1.5 rho E; Ro: 9 R_xy, R_xz, R_yz
+};
+
+template <int M, typename TB>
+__device__ __forceinline__ void eq_state(const TB &tb, double rho, const double *u, double T, const double *Y,
+                                         EqState<M> &e) {
+  double zeta = 0.0, H = 0.0, U = 0.0;
   const double invT = 1.0 / T;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    zeta_a[a] = tb.Ra[a] * T;
-    zeta += Y[a] * zeta_a[a];
+    e.zeta_a[a] = tb.Ra[a] * T;
+    e.Y[a] = Y[a];
+    zeta += Y[a] * e.zeta_a[a];
     const double h = h_RT(tb.nasa[a], T, invT);
-    H += Y[a] * zeta_a[a] * h;
-    U += Y[a] * zeta_a[a] * (h - 1.0);
+    H += Y[a] * e.zeta_a[a] * h;
+    U += Y[a] * e.zeta_a[a] * (h - 1.0);
   }
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const double rhoE = rho * (U + 0.5 * usq);
   const double h2 = H + 0.5 * usq, P = rho * zeta;
-  double qeq[3], Req[6];
+  double Req[6];
   const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
-  for (int d = 0; d < 3; ++d) qeq[d] = h2 * rho * u[d];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) e.qeq[d] = h2 * rho * u[d];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const double Peq = (k < 3 ? rho * zeta : 0.0) + rho * u[ia[k]] * u[ib[k]];
     Req[k] = h2 * Peq + P * u[ia[k]] * u[ib[k]];
   }
-  const double trR = Req[0] + Req[1] + Req[2];
-  const double A0 = 2.5 * rhoE - 1.5 * trR;
-  double su[3];
-  for (int d = 0; d < 3; ++d) su[d] = u[d] * u[d];
+  e.A0 = 2.5 * rhoE - 1.5 * (Req[0] + Req[1] + Req[2]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    e.Rd[d] = 4.5 * Req[d] - 1.5 * rhoE;
+    e.Ro[d] = Req[3 + d];
+  }
+  e.rho = rho;
+  e.zeta = zeta;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    e.u[d] = u[d];
+    e.su[d] = u[d] * u[d];
+  }
+}
+
+// the equilibria of all sets along direction i = (cx, cy, cz), stored at padded index p
+template <int M, typename ST, typename K>
+__device__ __forceinline__ void write_eq_dir(const EqState<M> &e, const K &kc, ST *__restrict__ dst, int64_t NPAD,
+                                             int i, int cx, int cy, int cz, int64_t p) {
+  const double fe = e.rho * psi_c<double>(cx, e.u[0], e.su[0] + e.zeta) *
+                    psi_c<double>(cy, e.u[1], e.su[1] + e.zeta) * psi_c<double>(cz, e.u[2], e.su[2] + e.zeta);
+  dst[(int64_t)((M - 1) * Q + i) * NPAD + p] = pop_enc<ST>(fe, M - 1, i, kc);
+  const double fx = cx, fy = cy, fz = cz;
+  double acc = e.A0 + 3.0 * (fx * e.qeq[0] + fy * e.qeq[1] + fz * e.qeq[2]);
+  acc += fx * fx * e.Rd[0] + fy * fy * e.Rd[1] + fz * fz * e.Rd[2];
+  acc += 9.0 * (fx * fy * e.Ro[0] + fx * fz * e.Ro[1] + fy * fz * e.Ro[2]);
+  dst[(int64_t)(M * Q + i) * NPAD + p] = pop_enc<ST>(w1(cx) * w1(cy) * w1(cz) * acc, M, i, kc);
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) {
+    const double z = e.zeta_a[a];
+    const double fa = e.rho * e.Y[a] * psi_c<double>(cx, e.u[0], e.su[0] + z) *
+                      psi_c<double>(cy, e.u[1], e.su[1] + z) * psi_c<double>(cz, e.u[2], e.su[2] + z);
+    dst[(int64_t)(a * Q + i) * NPAD + p] = pop_enc<ST>(fa, a, i, kc);
+  }
+}
+
+template <int M, typename ST>
+__device__ __forceinline__ void write_equilibria(const Tables &tb, const CollideConsts &kc,
+                                                 ST *__restrict__ dst, int64_t NPAD, const int64_t (&pidx)[27],
+                                                 double rho, const double *u, double T, const double *Y) {
+  EqState<M> e;
+  eq_state<M>(tb, rho, u, T, Y, e);
   static_for<27>([&](auto Ic) {
     constexpr int I = decltype(Ic)::value;
-    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     const int64_t p = pidx[I];
     if (p < 0) return;
-    const double fe = rho * psi_c<double>(cx, u[0], su[0] + zeta) * psi_c<double>(cy, u[1], su[1] + zeta) *
-                      psi_c<double>(cz, u[2], su[2] + zeta);
-    dst[(int64_t)((M - 1) * Q + I) * NPAD + p] = pop_enc<ST>(fe, M - 1, I, kc);
-    double acc = A0 + 3.0 * (cx * qeq[0] + cy * qeq[1] + cz * qeq[2]);
-    acc += cx * cx * (4.5 * Req[0] - 1.5 * rhoE) + cy * cy * (4.5 * Req[1] - 1.5 * rhoE) +
-           cz * cz * (4.5 * Req[2] - 1.5 * rhoE);
-    acc += 9.0 * (cx * cy * Req[3] + cx * cz * Req[4] + cy * cz * Req[5]);
-    dst[(int64_t)(M * Q + I) * NPAD + p] = pop_enc<ST>(wgt(I) * acc, M, I, kc);
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a) {
-      const double z = zeta_a[a];
-      const double fa = rho * Y[a] * psi_c<double>(cx, u[0], su[0] + z) * psi_c<double>(cy, u[1], su[1] + z) *
-                        psi_c<double>(cz, u[2], su[2] + z);
-      dst[(int64_t)(a * Q + I) * NPAD + p] = pop_enc<ST>(fa, a, I, kc);
-    }
+    write_eq_dir<M, ST>(e, kc, dst, NPAD, I, cx_of(I), cy_of(I), cz_of(I), p);
   });
 }
 
@@ -1436,9 +1468,13 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts 
 #pragma unroll
   for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
   const int64_t p = ((int64_t)(gz + g.pz) * g.NY + (gy + g.py)) * g.NX + (gx + g.px);
-  // only the directions along which an interior node pulls from this ghost cell
-  int64_t pidx[27];
-#pragma unroll
+  EqState<M> e;
+  eq_state<M>(*b.tab, double(srho[na]), u, b.T[na], Y, e);
+  // only the directions along which an interior node pulls from this ghost cell (a
+  // face cell serves 9, an edge cell 3, a corner cell 1); a runtime loop keeps the
+  // kernel small
+  ST *dst = static_cast<ST *>(b.pop[cur ^ 1]);
+#pragma unroll 1
   for (int i = 0; i < 27; ++i) {
     const int c[3] = {cx_of(i), cy_of(i), cz_of(i)};
     bool need = true;
@@ -1447,10 +1483,8 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts 
       const int t = gc[d] + c[d];
       need = need && (g.per[d] || (t >= 0 && t < nn[d]));
     }
-    pidx[i] = need ? p : -1;
+    if (need) write_eq_dir<M, ST>(e, kc, dst, g.NPAD, i, c[0], c[1], c[2], p);
   }
-  write_equilibria<M, ST>(*b.tab, kc, static_cast<ST *>(b.pop[cur ^ 1]), g.NPAD, pidx, double(srho[na]), u,
-                          b.T[na], Y);
 }
 
 // macroscopic fields of the current state (no state change)
@@ -1519,6 +1553,109 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, CollideConsts
   if (T_out) T_out[k] = b.T[n];
 }
 
+// ---- diagnostics (Sec. 5.2) -----------------------------------------------------------
+// Production rates rho_dot_a of one node by mass action (Sec. 4): forward rate
+// k_f = A T^b exp(-T_a / T) in log form, reverse rate k_f / K_c with K_c from the NASA-7
+// Gibbs function at p0, concentrations rho_a rho_ref / m_a.
+template <int M, typename TB>
+__device__ __forceinline__ void node_rates(const TB &tb, const double *rs, double T, double *rdot) {
+  const double invT = 1.0 / T, lnT = log(T);
+  double c[M], gib[M], wd[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    c[a] = rs[a] * tb.conc_scale[a];
+    gib[a] = h_RT(tb.nasa[a], T, invT) - s_R(tb.nasa[a], T, lnT);
+    wd[a] = 0.0;
+  }
+  const double ln_c0 = tb.ln_c0_const - lnT;
+  for (int k = 0; k < tb.R; ++k) {
+    const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
+    double fwd = exp(lnkf);
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+      for (int r = 0; r < tb.nu_r[k][a]; ++r) fwd *= c[a];
+    double rev = 0.0;
+    if (tb.rev[k]) {
+      double dG = 0.0;
+#pragma unroll
+      for (int a = 0; a < M; ++a) dG += tb.dnu_a[k][a] * gib[a];
+      rev = exp(lnkf + dG - tb.dnu[k] * ln_c0);
+#pragma unroll
+      for (int a = 0; a < M; ++a)
+        for (int r = 0; r < tb.nu_p[k][a]; ++r) rev *= c[a];
+    }
+    const double q = fwd - rev;
+#pragma unroll
+    for (int a = 0; a < M; ++a) wd[a] += tb.dnu_a[k][a] * q;
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) rdot[a] = tb.rdot_scale[a] * wd[a];
+}
+
+// Heat release rate -sum_a H_a rho_dot_a (Sec. 5.2) at every node of the current state,
+// and per-workgroup partial sums of LBM_DIAG_TOTALS quantities, added up in a fixed
+// order by k_diag_sum: heat release, cells with T >= T_iso, mass, total energy.
+constexpr int DIAG_BLOCK = 128;
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(DIAG_BLOCK) void k_diag(Geom g, Buffers b, CollideConsts kc, int cur, double T_iso,
+                                                    double *hrr) {
+  __shared__ double red[LBM_DIAG_TOTALS][DIAG_BLOCK];
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[LBM_DIAG_TOTALS] = {0.0, 0.0, 0.0, 0.0};
+  if (n < g.N) {
+    const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+    using Side = typename Fmt<ST>::Side;
+    const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * g.NPAD,
+                        g.NPAD};
+    Macro<M> m;
+    node_moments<M, ST>(g, static_cast<const ST *>(b.pop[cur]), cr, kc, x, y, z, m);
+    const Tables &tb = *b.tab;
+    double T;
+    node_temperature<M>(tb, m, b.T[n], T);
+    double rdot[M];
+    node_rates<M>(tb, m.rs, T, rdot);
+    const double invT = 1.0 / T;
+    double h = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) h -= tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT) * rdot[a];
+    if (hrr) hrr[n] = h;
+    v[0] = h;
+    v[1] = T >= T_iso ? 1.0 : 0.0;
+    v[2] = m.rho;
+    v[3] = m.rhoE;
+  }
+#pragma unroll
+  for (int k = 0; k < LBM_DIAG_TOTALS; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = DIAG_BLOCK / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < LBM_DIAG_TOTALS; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < LBM_DIAG_TOTALS; ++k) b.diag[(int64_t)k * gridDim.x + blockIdx.x] = red[k][0];
+}
+
+// total k of the partial sums: one workgroup per total, a fixed strided order and a
+// fixed tree, so that the result does not depend on scheduling
+constexpr int DIAG_SUM_BLOCK = 256;
+__global__ __launch_bounds__(DIAG_SUM_BLOCK) void k_diag_sum(const double *part, int64_t nparts,
+                                                              double *totals) {
+  __shared__ double red[DIAG_SUM_BLOCK];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < nparts; j += DIAG_SUM_BLOCK) acc += part[(int64_t)k * nparts + j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = DIAG_SUM_BLOCK / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) totals[k] = red[0];
+}
+
 __global__ void k_zero(uint32_t *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -1584,6 +1721,21 @@ struct RunGhost {
   }
 };
 template <int M, typename ST, typename RT>
+struct RunDiag {
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double T_iso,
+                        double *hrr, double *totals, hipStream_t st) {
+    const unsigned nb = blocks_for(g.N, DIAG_BLOCK);
+    hipLaunchKernelGGL((k_diag<M, ST, RT>), dim3(nb), dim3(DIAG_BLOCK), 0, st, g, b, kc, cur, T_iso, hrr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && totals) {
+      hipLaunchKernelGGL(k_diag_sum, dim3(LBM_DIAG_TOTALS), dim3(DIAG_SUM_BLOCK), 0, st, b.diag, (int64_t)nb,
+                         totals);
+      e = hipGetLastError();
+    }
+    return e;
+  }
+};
+template <int M, typename ST, typename RT>
 struct RunMacros {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double *rho,
                         double *u, double *T, double *P, double *Y, hipStream_t st) {
@@ -1632,6 +1784,11 @@ hipError_t launch_init(const Geom &g, const Buffers &b, const CollideConsts &kc,
 hipError_t launch_ghost(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
                         hipStream_t st) {
   return dispatch<RunGhost>(g.M, store, g, b, kc, cur, st);
+}
+
+hipError_t launch_diag(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
+                       double *hrr, double *totals, hipStream_t st) {
+  return dispatch<RunDiag>(g.M, store, g, b, kc, cur, T_iso, hrr, totals, st);
 }
 
 hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,

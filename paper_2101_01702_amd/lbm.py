@@ -52,8 +52,9 @@ class LbmError(RuntimeError):
 _lib = None
 
 EXPORTS = ("lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_step",
-           "lbm_step_timed", "lbm_macros", "lbm_populations", "lbm_adjoint_step", "lbm_status_sync",
-           "lbm_last_error")
+           "lbm_step_timed", "lbm_macros", "lbm_populations", "lbm_diagnostics", "lbm_adjoint_step",
+           "lbm_status_sync", "lbm_last_error")
+DIAG_TOTALS = 4   # heat release rate, nodes with T >= T_iso, mass, total energy
 
 
 def load(path: Optional[str] = None):
@@ -74,6 +75,7 @@ def load(path: Optional[str] = None):
     lib.lbm_step_timed.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_float)]
     lib.lbm_macros.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.lbm_populations.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
+    lib.lbm_diagnostics.argtypes = [vp, C.c_double, vp, vp, vp]
     lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp]
     lib.lbm_status_sync.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     lib.lbm_last_error.argtypes = [vp]
@@ -228,6 +230,19 @@ class Solver:
             t.cuda.synchronize(self.device)
             out = {k: v.cpu().numpy() for k, v in out.items()}
         return out
+
+    def diagnostics(self, T_iso: float, to_numpy: bool = True):
+        """Heat release rate field [N] and the sums (heat release, nodes with
+        T >= T_iso, mass, total energy) of the current state (``lbm_diagnostics``)."""
+        t = self.torch
+        hrr = t.empty(self.N, dtype=t.float64, device=self.device)
+        tot = t.empty(DIAG_TOTALS, dtype=t.float64, device=self.device)
+        self._check(self.lib.lbm_diagnostics(self.h, C.c_double(T_iso), C.c_void_p(hrr.data_ptr()),
+                                             C.c_void_p(tot.data_ptr()), self._stream()), self.h)
+        if to_numpy:
+            t.cuda.synchronize(self.device)
+            return hrr.cpu().numpy(), tot.cpu().numpy()
+        return hrr, tot
 
     def populations(self, nodes: Sequence[int], to_numpy: bool = True):
         """Pre-collision populations [S, 27, k] and stored temperatures at node ids."""
