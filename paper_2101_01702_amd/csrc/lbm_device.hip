@@ -1254,22 +1254,52 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
 }
 
 // ---- X_alpha = -d_alpha psi_alpha; Cg = sum_a w_a grad Y_a ---------------------------
+// One workgroup per tile of CT_X x CT_Y x CT_Z nodes.  psi (3 fields) and Y_a (M fields)
+// of the tile and its one-cell halo are staged in LDS with loads along x, and each node
+// then sums its 26 neighbours from LDS.  A halo cell holds the neighbour the gradient
+// stencil takes: wrapped on periodic axes, clamped on open ones (zero gradient).
+constexpr int CT_X = 32, CT_Y = 4, CT_Z = 2, CT_THREADS = CT_X * CT_Y * CT_Z;
+constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_CELLS = CH_X * CH_Y * CH_Z;
+
+__device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
+  if (periodic) {
+    v %= n;
+    return v < 0 ? v + n : v;
+  }
+  return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+inline int64_t corr_tiles(const Geom &g) {
+  return (int64_t)((g.nx + CT_X - 1) / CT_X) * ((g.ny + CT_Y - 1) / CT_Y) * ((g.nz + CT_Z - 1) / CT_Z);
+}
+
 template <int M, typename RT, typename CT>
-__global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
-  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
-  if (n >= g.N) return;
-  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+__global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
+  __shared__ RT sh[(M + 3) * CH_CELLS];   // field f of halo cell c at f * CH_CELLS + c
+  const int tiles_x = (g.nx + CT_X - 1) / CT_X, tiles_y = (g.ny + CT_Y - 1) / CT_Y;
+  const int64_t t = xcd_tile();
+  const int x0 = (int)(t % tiles_x) * CT_X, y0 = (int)((t / tiles_x) % tiles_y) * CT_Y,
+            z0 = (int)(t / ((int64_t)tiles_x * tiles_y)) * CT_Z;
   const RT *psi = static_cast<const RT *>(b.psi);
   const RT *Yf = static_cast<const RT *>(b.side_Y);
   const RT *wf = static_cast<const RT *>(b.side_w);
   const int64_t N = g.N;
-  int xs[3], ys[3], zs[3];
+  for (int c = threadIdx.x; c < CH_CELLS; c += CT_THREADS) {
+    const int hx = c % CH_X, hy = (c / CH_X) % CH_Y, hz = c / (CH_X * CH_Y);
+    const int gx = halo_coord(x0 + hx - 1, g.nx, g.per[0]), gy = halo_coord(y0 + hy - 1, g.ny, g.per[1]),
+              gz = halo_coord(z0 + hz - 1, g.nz, g.per[2]);
+    const int64_t nn = ((int64_t)gz * g.ny + gy) * g.nx + gx;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    xs[k] = nb_coord(x, k - 1, g.nx, g.per[0]);
-    ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
-    zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
+    for (int f = 0; f < 3; ++f) sh[f * CH_CELLS + c] = psi[f * N + nn];
+#pragma unroll
+    for (int a = 0; a < M; ++a) sh[(3 + a) * CH_CELLS + c] = Yf[a * N + nn];
   }
+  __syncthreads();
+  const int lx = threadIdx.x % CT_X, ly = (threadIdx.x / CT_X) % CT_Y, lz = threadIdx.x / (CT_X * CT_Y);
+  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+  if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+  const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
+  const int c0 = ((lz + 1) * CH_Y + (ly + 1)) * CH_X + (lx + 1);
   // side fields in RT, sums in FP64
   double wa[M];
 #pragma unroll
@@ -1279,14 +1309,14 @@ __global__ __launch_bounds__(256) void k_corr(Geom g, Buffers b) {
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     if constexpr (I != 13) {
-      const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
+      const int nc = c0 + (cz * CH_Y + cy) * CH_X + cx;
       constexpr double w = 3.0 * wgt(I);
-      if constexpr (cx != 0) X[0] -= (cx * w) * double(psi[0 * N + nn]);
-      if constexpr (cy != 0) X[1] -= (cy * w) * double(psi[1 * N + nn]);
-      if constexpr (cz != 0) X[2] -= (cz * w) * double(psi[2 * N + nn]);
+      if constexpr (cx != 0) X[0] -= (cx * w) * double(sh[0 * CH_CELLS + nc]);
+      if constexpr (cy != 0) X[1] -= (cy * w) * double(sh[1 * CH_CELLS + nc]);
+      if constexpr (cz != 0) X[2] -= (cz * w) * double(sh[2 * CH_CELLS + nc]);
       double hy = 0.0;
 #pragma unroll
-      for (int a = 0; a < M; ++a) hy += wa[a] * double(Yf[a * N + nn]);
+      for (int a = 0; a < M; ++a) hy += wa[a] * double(sh[(3 + a) * CH_CELLS + nc]);
       if constexpr (cx != 0) C[0] += (cx * w) * hy;
       if constexpr (cy != 0) C[1] += (cy * w) * hy;
       if constexpr (cz != 0) C[2] += (cz * w) * hy;
@@ -1694,7 +1724,7 @@ struct RunStep {
 template <int M, typename ST, typename RT>
 struct RunCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
-    hipLaunchKernelGGL((k_corr<M, RT, RT>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    hipLaunchKernelGGL((k_corr<M, RT, RT>), dim3((unsigned)corr_tiles(g)), dim3(CT_THREADS), 0, st, g, b);
     return hipGetLastError();
   }
 };
