@@ -39,10 +39,12 @@ Geom make_geom(const lbm_desc &d) {
     pad[a] = g.per[a] ? 0 : 1;
   }
   for (int k = 0; k < 6; ++k) g.bc[k] = d.bc[k];
-  g.px = pad[0]; g.py = pad[1]; g.pz = pad[2];
-  g.NX = n[0] + 2 * pad[0]; g.NY = n[1] + 2 * pad[1]; g.NZ = n[2] + 2 * pad[2];
+  g.px = 0; g.py = pad[1]; g.pz = pad[2];
+  g.NX = n[0]; g.NY = n[1] + 2 * pad[1]; g.NZ = n[2] + 2 * pad[2];
+  g.xg = pad[0];
   g.N = (int64_t)d.nx * d.ny * d.nz;
-  g.NPAD = (int64_t)g.NX * g.NY * g.NZ;
+  g.XG = (int64_t)g.NX * g.NY * g.NZ;
+  g.NPAD = g.XG + (g.xg ? 2LL * g.NY * g.NZ : 0);
   return g;
 }
 

@@ -74,12 +74,19 @@ __device__ __forceinline__ AxisSrc axis_src(int x, int n, bool periodic) {
   return a;
 }
 
+// index in a plane of cell x (-1..nx) of padded row prow: in the row, or one of the x
+// ghost cells after the rows
+__device__ __forceinline__ uint32_t cell_index(const Geom &g, int x, uint32_t prow) {
+  if (x < 0) return (uint32_t)g.XG + prow;
+  if (x >= g.nx) return (uint32_t)(g.XG + (int64_t)g.NY * g.NZ) + prow;
+  return prow * (uint32_t)g.NX + (uint32_t)x;
+}
+
 __device__ __forceinline__ Src make_src(const Geom &g, const AxisSrc &ax, const AxisSrc &ay,
                                         const AxisSrc &az, int kx, int ky, int kz) {
   Src r;
-  const uint32_t sx = (uint32_t)(ax.s[kx] + g.px), sy = (uint32_t)(ay.s[ky] + g.py),
-                 sz = (uint32_t)(az.s[kz] + g.pz);
-  r.ps = (sz * (uint32_t)g.NY + sy) * (uint32_t)g.NX + sx;
+  const uint32_t sy = (uint32_t)(ay.s[ky] + g.py), sz = (uint32_t)(az.s[kz] + g.pz);
+  r.ps = cell_index(g, ax.s[kx], sz * (uint32_t)g.NY + sy);
   const bool out = ax.out[kx] || ay.out[ky] || az.out[kz];
   r.ns = out ? -1 : (az.s[kz] * g.ny + ay.s[ky]) * g.nx + ax.s[kx];
   return r;
@@ -88,7 +95,7 @@ __device__ __forceinline__ Src make_src(const Geom &g, const AxisSrc &ax, const 
 // source of the pull for a uniform (cy, cz) and a compile-time x index: the y and z
 // coordinates are wrapped or left in the ghost layer without table lookups
 struct RowSrc {
-  uint32_t prow;   // padded row index (z, y) times NX
+  uint32_t prow;   // padded row index (z + pz) NY + (y + py)
   int32_t nrow;    // interior row index times nx, or -1 when (y, z) is in the ghost layer
 };
 
@@ -98,14 +105,14 @@ __device__ __forceinline__ RowSrc row_src(const Geom &g, int y, int z, int cy, i
   if (g.per[2]) sz = sz < 0 ? sz + g.nz : (sz >= g.nz ? sz - g.nz : sz);
   const bool out = sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz;
   RowSrc r;
-  r.prow = ((uint32_t)(sz + g.pz) * (uint32_t)g.NY + (uint32_t)(sy + g.py)) * (uint32_t)g.NX;
+  r.prow = (uint32_t)(sz + g.pz) * (uint32_t)g.NY + (uint32_t)(sy + g.py);
   r.nrow = out ? -1 : (sz * g.ny + sy) * g.nx;
   return r;
 }
 
 __device__ __forceinline__ Src src_from_row(const Geom &g, const RowSrc &row, const AxisSrc &ax, int kx) {
   Src r;
-  r.ps = row.prow + (uint32_t)(ax.s[kx] + g.px);
+  r.ps = cell_index(g, ax.s[kx], row.prow);
   r.ns = (row.nrow < 0 || ax.out[kx]) ? -1 : row.nrow + ax.s[kx];
   return r;
 }
@@ -480,27 +487,36 @@ __device__ __forceinline__ Rsrc plane(const void *buf, const Geom &g, int k) {
 typedef const __attribute__((address_space(4))) CollideConsts KC4;
 typedef const __attribute__((address_space(4))) Tables TB4;
 
-// A lane's node for the pulls: its padded index and coordinates.
+// A lane's node for the pulls: its coordinates.
 struct LaneSrc {
-  uint32_t self;
   int x, y, z;
 };
 
-// padded index of the source of direction (0, cy, cz), y - cy and z - cz wrapped on
-// periodic axes (an open axis has a ghost layer and never wraps)
-__device__ __forceinline__ uint32_t row_source(const Geom &g, const LaneSrc &l, int cy, int cz) {
-  const int32_t NXY = g.NX * g.NY;
-  uint32_t p = l.self - (uint32_t)(cy * g.NX + cz * NXY);
-  if (g.per[1] && cy != 0) p += (l.y == (cy > 0 ? 0 : g.ny - 1)) ? (uint32_t)(cy * g.ny * g.NX) : 0u;
-  if (g.per[2] && cz != 0) p += (l.z == (cz > 0 ? 0 : g.nz - 1)) ? (uint32_t)(cz * g.nz * NXY) : 0u;
-  return p;
+// source row of the directions (*, cy, cz), y - cy and z - cz wrapped on periodic axes
+// (an open axis has a ghost layer and never wraps): the padded row and the index of
+// its cell x (24-bit products: a plane has far fewer than 2^24 rows and cells per row)
+struct RowPos {
+  uint32_t row, p0;
+};
+__device__ __forceinline__ RowPos row_source(const Geom &g, const LaneSrc &l, int cy, int cz) {
+  int sy = l.y - cy, sz = l.z - cz;
+  if (g.per[1] && cy != 0) sy += (l.y == (cy > 0 ? 0 : g.ny - 1)) ? cy * g.ny : 0;
+  if (g.per[2] && cz != 0) sz += (l.z == (cz > 0 ? 0 : g.nz - 1)) ? cz * g.nz : 0;
+  RowPos r;
+  r.row = __umul24((uint32_t)(sz + g.pz), (uint32_t)g.NY) + (uint32_t)(sy + g.py);
+  r.p0 = __umul24(r.row, (uint32_t)g.NX) + (uint32_t)l.x;
+  return r;
 }
-// padded index of the source of direction (CX, cy, cz) from that of (0, cy, cz)
+// index of the source of direction (CX, cy, cz) in its row: x - CX, wrapped on a
+// periodic x axis, or one of the x ghost cells after the rows on an open one
 template <int CX>
-__device__ __forceinline__ uint32_t dir_source(const Geom &g, const LaneSrc &l, uint32_t row) {
-  uint32_t p = row - (uint32_t)CX;
-  if constexpr (CX != 0)
-    if (g.per[0]) p += (l.x == (CX > 0 ? 0 : g.nx - 1)) ? (uint32_t)(CX * g.nx) : 0u;
+__device__ __forceinline__ uint32_t dir_source(const Geom &g, const LaneSrc &l, const RowPos &r) {
+  uint32_t p = r.p0 - (uint32_t)CX;
+  if constexpr (CX != 0) {
+    const bool edge = l.x == (CX > 0 ? 0 : g.nx - 1);
+    if (g.per[0]) p += edge ? (uint32_t)(CX * g.nx) : 0u;
+    if (g.xg) p = edge ? (uint32_t)g.XG + (CX > 0 ? 0u : (uint32_t)(g.NY * g.NZ)) + r.row : p;
+  }
   return p;
 }
 
@@ -640,7 +656,7 @@ __device__ __forceinline__ void moments_pass(const Geom &g, const void *src, con
     const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
     KC4 *k = kp;
     opaque_uniform(k);
-    const uint32_t s0 = row_source(g, l, cy, cz);
+    const RowPos s0 = row_source(g, l, cy, cz);
     pull_all<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
     row_moments_dir<M, ST, -1>(pa, 3 * r, cy, cz, *k, rm, mo, sp);
     pull_all<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
@@ -1094,7 +1110,7 @@ __device__ __forceinline__ void collide_species_dir(const Geom &g, void *dst, co
 template <int M, typename ST, typename F>
 __device__ __forceinline__ void fg_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
                                         const CollCoef<M, F> &cc, const LaneSrc &l) {
-  const uint32_t so = l.self * (uint32_t)sizeof(ST);
+  const uint32_t so = row_source(g, l, 0, 0).p0 * (uint32_t)sizeof(ST);
   PulledFG<ST> pa, pb, pc;
   pull_fg<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
 #pragma unroll 1
@@ -1102,7 +1118,7 @@ __device__ __forceinline__ void fg_pass(const Geom &g, const void *src, void *ds
     const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
     KC4 *k = kp;
     opaque_uniform(k);
-    const uint32_t s0 = row_source(g, l, cy, cz);
+    const RowPos s0 = row_source(g, l, cy, cz);
     const RowFG rw = fg_row<M, F>(cc, cy, cz);
     pull_fg<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
     collide_fg_dir<M, ST, F, -1>(g, dst, cc, rw, pa, 3 * r, cy, cz, *k, so);
@@ -1128,7 +1144,7 @@ __device__ __forceinline__ void pull_species(const Geom &g, const void *src, int
 template <int M, typename ST, typename F>
 __device__ __forceinline__ void species_pass(const Geom &g, const void *src, void *dst, KC4 *kp,
                                              const CollCoef<M, F> &cc, const LaneSrc &l) {
-  const uint32_t so = l.self * (uint32_t)sizeof(ST);
+  const uint32_t so = row_source(g, l, 0, 0).p0 * (uint32_t)sizeof(ST);
   ST pa[M - 1], pb[M - 1], pc[M - 1];
   pull_species<M, ST>(g, src, 0, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
 #pragma unroll 1
@@ -1139,7 +1155,7 @@ __device__ __forceinline__ void species_pass(const Geom &g, const void *src, voi
     double u0 = cc.u0, T = cc.T;
     opaque(u0);
     opaque(T);
-    const uint32_t s0 = row_source(g, l, cy, cz);
+    const RowPos s0 = row_source(g, l, cy, cz);
     RowSpecies<M, F> rs;
     species_row<M, F>(cc, T, cy, cz, *k, rs);
     pull_species<M, ST>(g, src, 3 * r + 1, dir_source<0>(g, l, s0), pb);
@@ -1161,7 +1177,7 @@ __device__ __forceinline__ void species_pass(const Geom &g, const void *src, voi
 template <int M, typename ST, typename F>
 __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
                                              const CollCoef<M, F> &cc, const LaneSrc &l) {
-  const uint32_t so = l.self * (uint32_t)sizeof(ST);
+  const uint32_t so = row_source(g, l, 0, 0).p0 * (uint32_t)sizeof(ST);
   PulledAll<M, ST> pa, pb, pc;
   pull_all<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
 #pragma unroll 1
@@ -1172,7 +1188,7 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
     double u0 = cc.u0, T = cc.T;
     opaque(u0);
     opaque(T);
-    const uint32_t s0 = row_source(g, l, cy, cz);
+    const RowPos s0 = row_source(g, l, cy, cz);
     const RowFG rw = fg_row<M, F>(cc, cy, cz);
     RowSpecies<M, F> rs;
     species_row<M, F>(cc, T, cy, cz, *k, rs);
@@ -1209,8 +1225,7 @@ __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cu
   l.x = (int)(n % g.nx);
   l.y = (int)((n / g.nx) % g.ny);
   l.z = (int)(n / ((int64_t)g.nx * g.ny));
-  l.self = ((uint32_t)(l.z + g.pz) * (uint32_t)g.NY + (uint32_t)(l.y + g.py)) * (uint32_t)g.NX +
-           (uint32_t)(l.x + g.px);
+
   KC4 *kp = (KC4 *)b.kc;
   CollCoef<M, F> cc;
   node_local<M, ST>(g, b, kp, sh, n, l, cur, cc);
@@ -1254,11 +1269,12 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
 }
 
 // ---- X_alpha = -d_alpha psi_alpha; Cg = sum_a w_a grad Y_a ---------------------------
-// One workgroup per tile of CT_X x CT_Y x CT_Z nodes.  psi (3 fields) and Y_a (M fields)
+// One workgroup per tile of CT_X x CT_Y x CT_Z nodes (32 x 4 x 4 measured fastest of
+// 16x4x4, 32x4x2, 32x4x4 and 64x2x2).  psi (3 fields) and Y_a (M fields)
 // of the tile and its one-cell halo are staged in LDS with loads along x, and each node
 // then sums its 26 neighbours from LDS.  A halo cell holds the neighbour the gradient
 // stencil takes: wrapped on periodic axes, clamped on open ones (zero gradient).
-constexpr int CT_X = 32, CT_Y = 4, CT_Z = 2, CT_THREADS = CT_X * CT_Y * CT_Z;
+constexpr int CT_X = 32, CT_Y = 4, CT_Z = 4, CT_THREADS = CT_X * CT_Y * CT_Z;
 constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_CELLS = CH_X * CH_Y * CH_Z;
 
 __device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
@@ -1325,7 +1341,7 @@ __global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
   // padded planes: the ghost cells keep the zero they are cleared to at init
   CT *corr = static_cast<CT *>(b.corr);
   const int64_t NPAD = g.NPAD;
-  const int64_t pn = ((int64_t)(z + g.pz) * g.NY + (y + g.py)) * g.NX + (x + g.px);
+  const int64_t pn = ((int64_t)(z + g.pz) * g.NY + (y + g.py)) * g.NX + x;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     corr[d * NPAD + pn] = CT(X[d]);
@@ -1497,7 +1513,7 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts 
   double Y[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
-  const int64_t p = ((int64_t)(gz + g.pz) * g.NY + (gy + g.py)) * g.NX + (gx + g.px);
+  const int64_t p = cell_index(g, gx, (uint32_t)(gz + g.pz) * (uint32_t)g.NY + (uint32_t)(gy + g.py));
   EqState<M> e;
   eq_state<M>(*b.tab, double(srho[na]), u, b.T[na], Y, e);
   // only the directions along which an interior node pulls from this ghost cell (a
@@ -1740,7 +1756,7 @@ struct RunInit {
 template <int M, typename ST, typename RT>
 struct RunGhost {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
-    const int64_t sx = g.px ? 2LL * g.NY * g.NZ : 0;
+    const int64_t sx = g.xg ? 2LL * g.NY * g.NZ : 0;
     const int64_t sy = g.py ? 2LL * g.nx * g.NZ : 0;
     const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
     const int64_t tot = sx + sy + sz;

@@ -55,14 +55,22 @@ struct CollideConsts {
   float sc[MAXM + 1], isc[MAXM + 1];
 };
 
+// A plane of one (set, direction) holds the rows (z, y) of the lattice padded with a
+// ghost layer on open y and z axes, x fastest (NX = nx), and after them, on an open x
+// axis, the x ghost cells: one per padded row for x = -1, then one per padded row for
+// x = nx.  Row r = (z + pz) NY + (y + py); cell x of row r at r NX + x; the x ghost
+// cells at XG + r and XG + NY NZ + r.
 struct Geom {
   int32_t M;                  // species
   int32_t nx, ny, nz;
-  int32_t px, py, pz;         // ghost padding per axis (1 on open axes)
-  int32_t NX, NY, NZ;         // padded sizes
+  int32_t px, py, pz;         // ghost padding inside the rows (px = 0; 1 on open y, z)
+  int32_t NX, NY, NZ;         // row length nx and padded row counts
   int32_t per[3];             // periodic axis flags
   int32_t bc[6];
-  int64_t N, NPAD;
+  int32_t xg;                 // 1 when the x axis is open: x ghost cells after the rows
+  int32_t pad_;
+  int64_t N, NPAD;            // interior nodes, cells of one plane
+  int64_t XG;                 // first x ghost cell, NX NY NZ
 };
 
 // Device pointers into the workspace.
