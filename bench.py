@@ -99,6 +99,31 @@ def error_vs_f64(lbm, W, storage, steps=100):
     return {"max_rel": max(errs.values()), "fields": errs, "steps": steps, "lattice": "32^3 crop"}
 
 
+def error_vs_f64_full(lbm, W, storage, n, steps):
+    """The same field error at full size: the benchmarked storage against FP64 storage
+    on the n^3 flame after `steps` steps (both runs on the GPU)."""
+    import numpy as np
+    import torch
+    out = {}
+    for st in (W.STORE_F64, storage):
+        prob = W.sphere3d(n=n, storage=st)
+        s = lbm.Solver(prob, storage=st).init()
+        del prob.rho, prob.u, prob.T, prob.Y
+        s.step(steps)
+        out[st] = s.macros()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    a, b = out[storage], out[W.STORE_F64]
+    zeta_floor = math.sqrt(0.003)   # sqrt of the unburnt lattice RT, as in error_vs_f64
+    errs = {k: float(np.abs(a[k] - b[k]).max() / np.abs(b[k]).max()) for k in ("rho", "T", "P")}
+    errs["u"] = float(max(np.abs(a["u"][d] - b["u"][d]).max() / max(np.abs(b["u"][d]).max(), zeta_floor)
+                          for d in range(3)))
+    errs["Y"] = float(max(np.abs(a["Y"][k] - b["Y"][k]).max() / max(np.abs(b["Y"][k]).max(), 1e-12)
+                          for k in range(b["Y"].shape[0])))
+    return {"max_rel": max(errs.values()), "fields": errs, "steps": steps, "lattice": f"{n}^3"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +135,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--copy-only", action="store_true", help="run only the copy kernel (counter calibration)")
+    ap.add_argument("--full-error-steps", type=int, default=0,
+                    help="also measure the field error against FP64 storage at full size after this many steps")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -191,6 +218,8 @@ def main():
     }
     if not args.no_error_check:
         out["error_vs_f64"] = error_vs_f64(lbm, W, storage)
+    if args.full_error_steps > 0 and storage != W.STORE_F64:
+        out["error_vs_f64_full"] = error_vs_f64_full(lbm, W, storage, args.n, args.full_error_steps)
     out["copy_ceiling_GBps"] = round(copy_ceiling_gbs(torch, dev), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

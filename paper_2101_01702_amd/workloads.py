@@ -399,12 +399,14 @@ def flame1d(nx: int = 4096, seed: int = FLAME_SEED, phi: float = 1.0, T_u: float
 def sphere3d(n: int = 256, seed: int = FLAME_SEED, phi: float = 0.8, T_u: float = 300.0,
              T_ig: float = 1500.0, radius: float = 12.0, zeta_ref: float = 0.003,
              omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 3e-10,
-             diff_range=(0.02, 0.08), edge: float = 2.0, storage: int = STORE_F32,
+             diff_range=(0.02, 0.08), edge: float = 8.0, storage: int = STORE_F32,
              shape: Optional[Tuple[int, int, int]] = None,
              mech: Optional[Mechanism] = None) -> Problem:
     """3D expanding spherical flame: n^3 lattice, all faces open, quiescent premixture
     at T_u and equivalence ratio phi, ignition sphere at T_ig of the given radius
-    centred with a seeded sub-cell offset, tanh edge of ``edge`` cells."""
+    centred with a seeded sub-cell offset, tanh edge of ``edge`` cells.  With a 2-cell
+    edge the run goes non-finite within 100 steps (FP64); with 8 cells it stays finite
+    and positive over the 500 steps checked."""
     rng = np.random.default_rng(seed + 2000)
     mech = mech or h2air_mechanism(seed)
     nx, ny, nz = shape or (n, n, n)
