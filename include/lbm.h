@@ -49,7 +49,11 @@ typedef enum {
 enum {
   LBM_BC_PERIODIC = 0, /* both faces of an axis must be periodic together        */
   LBM_BC_OPEN_EQ = 1,  /* ghost = equilibrium at the adjacent node's rho_a, u, T  */
-  LBM_BC_OPEN_EQ_U0 = 2 /* same with ghost velocity 0                            */
+  LBM_BC_OPEN_EQ_U0 = 2, /* same with ghost velocity 0                           */
+  LBM_BC_SYMMETRY = 3   /* mirror plane half a cell beyond the boundary nodes (Sec. 5.2):
+                           a ghost holds the mirrored population of the mirrored node, with
+                           mirrored deferred corrections; beyond a symmetry and an open face,
+                           the equilibrium of the mirrored direction                        */
 };
 
 /* population storage; the node-local work (temperature inversion, thermo,

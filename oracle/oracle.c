@@ -265,29 +265,45 @@ static void node_coords(const orc_sim *s, int64_t n, int *x, int *y, int *z) {
 }
 static int dim(const orc_sim *s, int a) { return a == 0 ? s->p.nx : (a == 1 ? s->p.ny : s->p.nz); }
 
-/* neighbour for gradients: periodic wrap, or the boundary node outside an open face */
-static int64_t grad_neighbour(const orc_sim *s, int64_t n, int i) {
+/* neighbour for gradients: periodic wrap, or the boundary node outside an open face
+ * (zero gradient), or its mirror image outside a symmetry face.  *mirror gets a bit
+ * per axis whose symmetry face the neighbour lies beyond. */
+static int64_t grad_neighbour(const orc_sim *s, int64_t n, int i, int *mirror) {
   int xyz[3];
   node_coords(s, n, &xyz[0], &xyz[1], &xyz[2]);
+  *mirror = 0;
   for (int a = 0; a < 3; ++a) {
     const int L = dim(s, a);
     int v = xyz[a] + CI(i, a);
     if (s->p.bc[2 * a] == ORC_BC_PERIODIC) {
       v = ((v % L) + L) % L;
-    } else {
-      if (v < 0) v = 0;
-      if (v >= L) v = L - 1;
+    } else if (v < 0) {
+      if (s->p.bc[2 * a] == ORC_BC_SYMMETRY) *mirror |= 1 << a;
+      v = -1 - v;
+    } else if (v >= L) {
+      if (s->p.bc[2 * a + 1] == ORC_BC_SYMMETRY) *mirror |= 1 << a;
+      v = 2 * L - 1 - v;
     }
     xyz[a] = v;
   }
   return node_index(s, xyz[0], xyz[1], xyz[2]);
 }
 
-/* isotropic lattice gradient of a nodal field, component alpha */
-static double iso_grad(const orc_sim *s, const double *field, int64_t n, int alpha) {
+/* isotropic lattice gradient, component alpha, of a nodal field that is a scalar
+ * (vec_axis < 0) or the vec_axis component of a vector: that component changes sign
+ * in the mirror image beyond a symmetry face normal to its axis */
+static double iso_grad_v(const orc_sim *s, const double *field, int64_t n, int alpha, int vec_axis) {
   double acc = 0.0;
-  for (int i = 0; i < Q; ++i) acc += weight(i) * CI(i, alpha) * field[grad_neighbour(s, n, i)];
+  for (int i = 0; i < Q; ++i) {
+    int mirror;
+    double v = field[grad_neighbour(s, n, i, &mirror)];
+    if (vec_axis >= 0 && (mirror >> vec_axis & 1)) v = -v;
+    acc += weight(i) * CI(i, alpha) * v;
+  }
   return acc / THETA;
+}
+static double iso_grad(const orc_sim *s, const double *field, int64_t n, int alpha) {
+  return iso_grad_v(s, field, n, alpha, -1);
 }
 
 /* ---- O1-O5: local part of the step at one node ---------------------------------------- */
@@ -460,36 +476,58 @@ static double ghost_value(const orc_sim *s, int set, int i, const node_t *d, int
   return grad_form(i, rhoE, qeq, Req);
 }
 
+/* direction i with the components along the axes in mask reversed */
+static int mirror_dir(int i, int mask) {
+  int c[3] = {CX(i), CY(i), CZ(i)};
+  for (int a = 0; a < 3; ++a)
+    if (mask >> a & 1) c[a] = -c[a];
+  return (c[0] + 1) + 3 * (c[1] + 1) + 9 * (c[2] + 1);
+}
+
+/* O8: pull streaming.  A source beyond an open face is the equilibrium at the boundary
+ * node (Sec. 5.1).  Beyond a symmetry face the source is the mirror image: the
+ * population of the mirrored direction at the mirrored node, post-collision with its
+ * corrections; beyond a symmetry and an open face, the equilibrium of the mirrored
+ * direction at the mirrored boundary node. */
 static void stream_node(orc_sim *s, int64_t n) {
   const int S = s->S;
   const int64_t N = s->N;
   int xyz[3];
   node_coords(s, n, &xyz[0], &xyz[1], &xyz[2]);
   for (int i = 0; i < Q; ++i) {
-    int src[3], outside = 0, zero_u = 0;
+    int src[3], open_out = 0, zero_u = 0, mirror = 0;
     for (int a = 0; a < 3; ++a) {
       const int L = dim(s, a);
       int v = xyz[a] - CI(i, a);
       if (s->p.bc[2 * a] == ORC_BC_PERIODIC) {
         v = ((v % L) + L) % L;
       } else if (v < 0) {
-        outside = 1;
-        if (s->p.bc[2 * a] == ORC_BC_OPEN_U0) zero_u = 1;
-        v = 0;
+        if (s->p.bc[2 * a] == ORC_BC_SYMMETRY) {
+          mirror |= 1 << a;
+        } else {
+          open_out = 1;
+          if (s->p.bc[2 * a] == ORC_BC_OPEN_U0) zero_u = 1;
+        }
+        v = -1 - v;
       } else if (v >= L) {
-        outside = 1;
-        if (s->p.bc[2 * a + 1] == ORC_BC_OPEN_U0) zero_u = 1;
-        v = L - 1;
+        if (s->p.bc[2 * a + 1] == ORC_BC_SYMMETRY) {
+          mirror |= 1 << a;
+        } else {
+          open_out = 1;
+          if (s->p.bc[2 * a + 1] == ORC_BC_OPEN_U0) zero_u = 1;
+        }
+        v = 2 * L - 1 - v;
       }
       src[a] = v;
     }
     const int64_t m = node_index(s, src[0], src[1], src[2]);
+    const int im = mirror_dir(i, mirror);
     for (int set = 0; set < S; ++set) {
       double v;
-      if (!outside)
-        v = s->post[((int64_t)set * Q + i) * N + m];
+      if (open_out)
+        v = ghost_value(s, set, im, &s->nd[m], zero_u);
       else
-        v = ghost_value(s, set, i, &s->nd[m], zero_u);
+        v = s->post[((int64_t)set * Q + im) * N + m];
       s->pop[((int64_t)set * Q + i) * N + n] = v;
     }
   }
@@ -582,17 +620,18 @@ static void nonlocal_fields(orc_sim *s, int nthreads) {
   const int64_t N = s->N;
   double *fld = s->scratch;
   (void)nthreads;
-  /* psi_alpha = (1/omega - 1/2) d_alpha phi_alpha ; X_alpha = -d_alpha psi_alpha (eq. Xalpha) */
+  /* psi_alpha = (1/omega - 1/2) d_alpha phi_alpha ; X_alpha = -d_alpha psi_alpha (eq. Xalpha).
+   * phi_alpha is odd under a mirror normal to alpha (it is odd in u_alpha), psi_alpha even */
   for (int a = 0; a < 3; ++a) {
     for (int64_t n = 0; n < N; ++n) fld[n] = s->nd[n].phi[a];
 #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (int64_t n = 0; n < N; ++n)
-      s->nd[n].psi[a] = (1.0 / s->p.omega - 0.5) * iso_grad(s, fld, n, a);
+      s->nd[n].psi[a] = (1.0 / s->p.omega - 0.5) * iso_grad_v(s, fld, n, a, a);
   }
   for (int a = 0; a < 3; ++a) {
     for (int64_t n = 0; n < N; ++n) fld[n] = s->nd[n].psi[a];
 #pragma omp parallel for schedule(static) num_threads(nthreads)
-    for (int64_t n = 0; n < N; ++n) s->nd[n].X[a] = -iso_grad(s, fld, n, a);
+    for (int64_t n = 0; n < N; ++n) s->nd[n].X[a] = -iso_grad(s, fld, n, a);   /* psi is even under mirrors */
   }
   /* gradients of the mass fractions (eq. corrFourier) */
   for (int sp = 0; sp < M; ++sp) {

@@ -25,7 +25,7 @@
 #define ORC_MAXM 16
 #define ORC_MAXR 64
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_OPEN = 1, ORC_BC_OPEN_U0 = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OPEN = 1, ORC_BC_OPEN_U0 = 2, ORC_BC_SYMMETRY = 3 };
 enum { ORC_ANOM_NONFINITE = 1u, ORC_ANOM_NEWTON = 2u, ORC_ANOM_NEG_DENSITY = 4u };
 
 typedef struct {

@@ -101,7 +101,7 @@ bool validate(const lbm_desc *d, std::string *err) {
   for (int a = 0; a < 3; ++a) {
     for (int s = 0; s < 2; ++s) {
       const int b = d->bc[2 * a + s];
-      if (b != LBM_BC_PERIODIC && b != LBM_BC_OPEN_EQ && b != LBM_BC_OPEN_EQ_U0)
+      if (b != LBM_BC_PERIODIC && b != LBM_BC_OPEN_EQ && b != LBM_BC_OPEN_EQ_U0 && b != LBM_BC_SYMMETRY)
         return fail(err, "bc[%d] = %d is not a boundary type", 2 * a + s, b);
     }
     if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))

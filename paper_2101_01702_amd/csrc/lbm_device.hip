@@ -220,8 +220,8 @@ template <int CX, typename ST, typename CT>
 __device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src &r, const Corr<CT> &cr, int cy,
                                          int cz, int s, int i, const CollideConsts &kc) {
   double v = pop_val(ld(base, r.ps), s, i, kc);
-  if (r.ns >= 0) {
-    const uint32_t ns = r.ps;   // the corrections live in padded planes
+  {
+    const uint32_t ns = r.ps;   // padded planes: zero at open ghosts, mirrored at symmetry ghosts
     if constexpr (CX != 0) {
       if (cy == 0 && cz == 0) v += double(CT(0.5 * CX * double(ld(cr.X, ns))));
     } else {
@@ -238,8 +238,8 @@ __device__ __forceinline__ double pull_g(const ST *__restrict__ base, const Src 
                                          int cz, int s, int i, const CollideConsts &kc) {
   const double w3 = 3.0 * (w1(CX) * w1(cy) * w1(cz));
   double v = pop_val(ld(base, r.ps), s, i, kc);
-  if (r.ns >= 0) {
-    const uint32_t ns = r.ps;   // the corrections live in padded planes
+  {
+    const uint32_t ns = r.ps;   // padded planes: zero at open ghosts, mirrored at symmetry ghosts
     double d = 0.0;
     if constexpr (CX != 0) d += CX * double(ld(cr.Cg, ns));
     if (cy != 0) d += cy * double(ld(cr.Cg + cr.NPAD, ns));
@@ -1253,15 +1253,25 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
     ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
     zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
   }
+  // phi_alpha is odd in u_alpha: its mirror image beyond a symmetry face normal to
+  // alpha has the opposite sign
+  double sg[3][3];
+  const int xyz[3] = {x, y, z}, nn3[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    sg[a][0] = (xyz[a] == 0 && g.bc[2 * a] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+    sg[a][1] = 1.0;
+    sg[a][2] = (xyz[a] == nn3[a] - 1 && g.bc[2 * a + 1] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+  }
   double acc[3] = {0, 0, 0};
   static_for<27>([&](auto Ic) {
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
     constexpr double w = 3.0 * wgt(I);
-    if constexpr (cx != 0) acc[0] += (cx * w) * double(phi[0 * N + nn]);
-    if constexpr (cy != 0) acc[1] += (cy * w) * double(phi[1 * N + nn]);
-    if constexpr (cz != 0) acc[2] += (cz * w) * double(phi[2 * N + nn]);
+    if constexpr (cx != 0) acc[0] += (cx * w) * (sg[0][cx + 1] * double(phi[0 * N + nn]));
+    if constexpr (cy != 0) acc[1] += (cy * w) * (sg[1][cy + 1] * double(phi[1 * N + nn]));
+    if constexpr (cz != 0) acc[2] += (cz * w) * (sg[2][cz + 1] * double(phi[2 * N + nn]));
   });
   RT *psi = static_cast<RT *>(b.psi);
 #pragma unroll
@@ -1458,78 +1468,153 @@ __global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, CollideConsts k
   b.T[n] = T[n];
 }
 
-// ghost layer of open faces: equilibria at the adjacent boundary node (Sec. 5.1)
-template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts kc, int cur, int64_t nx_slab,
-                                               int64_t ny_slab,
-                                               int64_t nz_slab) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int gx, gy, gz;
-  if (t < nx_slab) {          // x = -1 or nx, all padded y, z
+// ghost cell t of the slabs beyond the non-periodic faces: x slabs (all padded y, z),
+// then y slabs (interior x, padded z), then z slabs (interior x, y)
+__device__ __forceinline__ bool ghost_cell(const Geom &g, int64_t t, int64_t nx_slab, int64_t ny_slab,
+                                           int64_t nz_slab, int (&gc)[3]) {
+  if (t < nx_slab) {          // x = -1 or nx
     const int64_t per = (int64_t)g.NY * g.NZ;
-    gx = (t < per) ? -1 : g.nx;
+    gc[0] = (t < per) ? -1 : g.nx;
     const int64_t r = t % per;
-    gy = (int)(r % g.NY) - g.py;
-    gz = (int)(r / g.NY) - g.pz;
-  } else if ((t -= nx_slab) < ny_slab) {   // y = -1 or ny, interior x, padded z
-    const int64_t per = (int64_t)g.nx * g.NZ;
-    gy = (t < per) ? -1 : g.ny;
-    const int64_t r = t % per;
-    gx = (int)(r % g.nx);
-    gz = (int)(r / g.nx) - g.pz;
-  } else if ((t -= ny_slab) < nz_slab) {   // z = -1 or nz, interior x, y
-    const int64_t per = (int64_t)g.nx * g.ny;
-    gz = (t < per) ? -1 : g.nz;
-    const int64_t r = t % per;
-    gx = (int)(r % g.nx);
-    gy = (int)(r / g.nx);
-  } else {
-    return;
+    gc[1] = (int)(r % g.NY) - g.py;
+    gc[2] = (int)(r / g.NY) - g.pz;
+    return true;
   }
-  bool zero_u = false;
-  const int gc[3] = {gx, gy, gz};
-  const int nn[3] = {g.nx, g.ny, g.nz};
+  if ((t -= nx_slab) < ny_slab) {   // y = -1 or ny
+    const int64_t per = (int64_t)g.nx * g.NZ;
+    gc[1] = (t < per) ? -1 : g.ny;
+    const int64_t r = t % per;
+    gc[0] = (int)(r % g.nx);
+    gc[2] = (int)(r / g.nx) - g.pz;
+    return true;
+  }
+  if ((t -= ny_slab) < nz_slab) {   // z = -1 or nz
+    const int64_t per = (int64_t)g.nx * g.ny;
+    gc[2] = (t < per) ? -1 : g.nz;
+    const int64_t r = t % per;
+    gc[0] = (int)(r % g.nx);
+    gc[1] = (int)(r / g.nx);
+    return true;
+  }
+  return false;
+}
+
+// The boundary node a ghost cell stands for: the ghost reflected back across every face
+// it lies beyond (for the one-cell layer, the nearest node).  mirror gets a bit per
+// crossed symmetry face, open is set when an open face is crossed, zero_u when a
+// zero-velocity face is.
+struct GhostSrc {
   int a3[3];
+  int mirror;
+  bool open, zero_u;
+};
+__device__ __forceinline__ GhostSrc ghost_src(const Geom &g, const int (&gc)[3]) {
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  GhostSrc r;
+  r.mirror = 0;
+  r.open = r.zero_u = false;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     int v = gc[d];
-    if (v < 0) {
-      zero_u |= (g.bc[2 * d] == LBM_BC_OPEN_EQ_U0);
-      v = 0;
-    } else if (v >= nn[d]) {
-      zero_u |= (g.bc[2 * d + 1] == LBM_BC_OPEN_EQ_U0);
-      v = nn[d] - 1;
+    if (v < 0 || v >= nn[d]) {
+      const int bc = g.bc[2 * d + (v < 0 ? 0 : 1)];
+      if (bc == LBM_BC_SYMMETRY) {
+        r.mirror |= 1 << d;
+      } else {
+        r.open = true;
+        r.zero_u |= (bc == LBM_BC_OPEN_EQ_U0);
+      }
+      v = v < 0 ? -1 - v : 2 * nn[d] - 1 - v;
     }
-    a3[d] = v;
+    r.a3[d] = v;
   }
+  return r;
+}
+
+// Ghost layer of the non-periodic faces, after the collision.  Beyond an open face the
+// ghost is the equilibrium at the adjacent boundary node (Sec. 5.1); beyond symmetry
+// faces only, it is the mirror image: the post-collision population of the mirrored
+// direction at the mirrored node (the quarter-domain flame of Sec. 5.2); beyond a
+// symmetry and an open face, the equilibrium of the mirrored direction.
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts kc, int cur, int64_t nx_slab,
+                                               int64_t ny_slab, int64_t nz_slab) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int gc[3];
+  if (!ghost_cell(g, t, nx_slab, ny_slab, nz_slab, gc)) return;
+  const GhostSrc gs = ghost_src(g, gc);
+  const int nn[3] = {g.nx, g.ny, g.nz};
   const int64_t N = g.N;
-  const int64_t na = ((int64_t)a3[2] * g.ny + a3[1]) * g.nx + a3[0];
-  const RT *srho = static_cast<const RT *>(b.side_rho);
-  const RT *su = static_cast<const RT *>(b.side_u);
-  const RT *sY = static_cast<const RT *>(b.side_Y);
-  double u[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) u[d] = zero_u ? 0.0 : double(su[d * N + na]);
-  double Y[M];
-#pragma unroll
-  for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
-  const int64_t p = cell_index(g, gx, (uint32_t)(gz + g.pz) * (uint32_t)g.NY + (uint32_t)(gy + g.py));
+  const int64_t na = ((int64_t)gs.a3[2] * g.ny + gs.a3[1]) * g.nx + gs.a3[0];
+  const int64_t p = cell_index(g, gc[0], (uint32_t)(gc[2] + g.pz) * (uint32_t)g.NY + (uint32_t)(gc[1] + g.py));
+  ST *dst = static_cast<ST *>(b.pop[cur ^ 1]);
   EqState<M> e;
-  eq_state<M>(*b.tab, double(srho[na]), u, b.T[na], Y, e);
+  if (gs.open) {
+    const RT *srho = static_cast<const RT *>(b.side_rho);
+    const RT *su = static_cast<const RT *>(b.side_u);
+    const RT *sY = static_cast<const RT *>(b.side_Y);
+    double u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = gs.zero_u ? 0.0 : double(su[d * N + na]);
+    double Y[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
+    eq_state<M>(*b.tab, double(srho[na]), u, b.T[na], Y, e);
+  }
+  const int64_t pa = cell_index(g, gs.a3[0], (uint32_t)(gs.a3[2] + g.pz) * (uint32_t)g.NY +
+                                                 (uint32_t)(gs.a3[1] + g.py));
   // only the directions along which an interior node pulls from this ghost cell (a
   // face cell serves 9, an edge cell 3, a corner cell 1); a runtime loop keeps the
   // kernel small
-  ST *dst = static_cast<ST *>(b.pop[cur ^ 1]);
 #pragma unroll 1
   for (int i = 0; i < 27; ++i) {
     const int c[3] = {cx_of(i), cy_of(i), cz_of(i)};
     bool need = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int t = gc[d] + c[d];
-      need = need && (g.per[d] || (t >= 0 && t < nn[d]));
+      const int t2 = gc[d] + c[d];
+      need = need && (g.per[d] || (t2 >= 0 && t2 < nn[d]));
     }
-    if (need) write_eq_dir<M, ST>(e, kc, dst, g.NPAD, i, c[0], c[1], c[2], p);
+    if (!need) continue;
+    int cm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cm[d] = (gs.mirror >> d & 1) ? -c[d] : c[d];
+    if (gs.open) {
+      write_eq_dir<M, ST>(e, kc, dst, g.NPAD, i, cm[0], cm[1], cm[2], p);
+    } else {
+      // the rest equilibria of the 16-bit formats are mirror-symmetric, so the stored
+      // form copies as it is
+      const int im = (cm[0] + 1) + 3 * (cm[1] + 1) + 9 * (cm[2] + 1);
+#pragma unroll
+      for (int s2 = 0; s2 <= M; ++s2)
+        dst[((int64_t)s2 * Q + i) * g.NPAD + p] = dst[((int64_t)s2 * Q + im) * g.NPAD + pa];
+    }
+  }
+}
+
+// Deferred corrections of the ghost cells beyond symmetry faces only: the mirror image of
+// those at the mirrored node, X and Cg with their components normal to the crossed
+// faces reversed (both are odd under such a mirror).  After k_corr; other ghost cells
+// keep zero.
+template <typename CT>
+__global__ __launch_bounds__(128) void k_ghost_corr(Geom g, Buffers b, int64_t nx_slab, int64_t ny_slab,
+                                                    int64_t nz_slab) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int gc[3];
+  if (!ghost_cell(g, t, nx_slab, ny_slab, nz_slab, gc)) return;
+  const GhostSrc gs = ghost_src(g, gc);
+  if (gs.open || gs.mirror == 0) return;
+  const int64_t p = cell_index(g, gc[0], (uint32_t)(gc[2] + g.pz) * (uint32_t)g.NY + (uint32_t)(gc[1] + g.py));
+  const int64_t pa = cell_index(g, gs.a3[0], (uint32_t)(gs.a3[2] + g.pz) * (uint32_t)g.NY +
+                                                 (uint32_t)(gs.a3[1] + g.py));
+  CT *corr = static_cast<CT *>(b.corr);
+  const int64_t NPAD = g.NPAD;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool flip = gs.mirror >> d & 1;
+    const CT x = corr[d * NPAD + pa], c = corr[(3 + d) * NPAD + pa];
+    corr[d * NPAD + p] = flip ? CT(-x) : x;
+    corr[(3 + d) * NPAD + p] = flip ? CT(-c) : c;
   }
 }
 
@@ -1781,6 +1866,24 @@ struct RunDiag {
     return e;
   }
 };
+inline bool any_symmetry(const Geom &g) {
+  for (int k = 0; k < 6; ++k)
+    if (g.bc[k] == LBM_BC_SYMMETRY) return true;
+  return false;
+}
+template <int M, typename ST, typename RT>
+struct RunGhostCorr {
+  static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
+    if (!any_symmetry(g)) return hipSuccess;
+    const int64_t sx = g.xg ? 2LL * g.NY * g.NZ : 0;
+    const int64_t sy = g.py ? 2LL * g.nx * g.NZ : 0;
+    const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
+    const int64_t tot = sx + sy + sz;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ghost_corr<RT>), dim3(blocks_for(tot, 128)), dim3(128), 0, st, g, b, sx, sy, sz);
+    return hipGetLastError();
+  }
+};
 template <int M, typename ST, typename RT>
 struct RunMacros {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double *rho,
@@ -1819,7 +1922,9 @@ hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st
 }
 
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st) {
-  return dispatch<RunCorr>(g.M, store, g, b, st);
+  hipError_t e = dispatch<RunCorr>(g.M, store, g, b, st);
+  if (e == hipSuccess) e = dispatch<RunGhostCorr>(g.M, store, g, b, st);
+  return e;
 }
 
 hipError_t launch_init(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, const double *rho,

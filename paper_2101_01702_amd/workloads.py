@@ -33,6 +33,7 @@ T_REF = 298.15             # K, standard-state temperature of the thermo data
 BC_PERIODIC = 0
 BC_OPEN = 1                # zero-gradient, equilibrium ghost at the adjacent node
 BC_OPEN_U0 = 2             # same, ghost velocity set to zero
+BC_SYMMETRY = 3            # mirror plane half a cell outside the boundary nodes
 
 STORE_F64 = 0
 STORE_F32 = 1
