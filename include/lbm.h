@@ -102,6 +102,16 @@ enum {
  *   ref_state       [2 + M] host array (rho in lattice units, T in K, Y[M] mass
  *                   fractions summing to 1) of the reference state at rest of the
  *                   deviation formats; may be NULL for LBM_STORE_F64 / _F32
+ *   n_segments      0 or 1: one lattice.  >= 2: a batch of independent lattices of
+ *                   the same ny x nz cross-section and transport, mechanism and
+ *                   units, side by side along x (e.g. quasi-1D flames of different
+ *                   lengths, Sec. 5.1).  Segment s takes segment_lengths[s] >= 1
+ *                   consecutive x; the lengths sum to nx, the x faces must not be
+ *                   periodic, and every segment has bc[0] at its first x and bc[1]
+ *                   after its last.  Nodes of different segments never exchange
+ *                   populations or stencil values.  Node indices, fields and
+ *                   populations keep the one-lattice layout of nx x ny x nz.
+ *   segment_lengths [n_segments] host array, read when n_segments >= 2
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -120,6 +130,9 @@ typedef struct {
   int32_t storage;
   int32_t reserved;
   const double *ref_state;
+  int32_t n_segments;
+  int32_t reserved2;
+  const int32_t *segment_lengths;
 } lbm_desc;
 
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost
@@ -127,8 +140,9 @@ typedef struct {
  * gradient stencils and the ghosts (2M + 7 words) and psi (3 words), the deferred
  * corrections (6 words per node of the padded lattice), all in the storage
  * precision, the constant tables, a copy of the collision constants and a status
- * word.  Fails with LBM_ERR_ARG when one padded plane of the lattice (its node count
- * with the ghost layers) times 8 bytes for LBM_STORE_F64, 4 otherwise, reaches
+ * word (and, for a batch of segments, the segment table, 4 (nx + n_segments + 1)
+ * bytes; the x ghost layer is then two cells per segment and row).  Fails with
+ * LBM_ERR_ARG when one padded plane of the lattice (its node count with the ghost layers) times 8 bytes for LBM_STORE_F64, 4 otherwise, reaches
  * 2 GiB: the step kernel addresses a plane with 32-bit byte offsets. */
 lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 

@@ -24,7 +24,8 @@ thread_local std::string g_last_error;
 size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t status, tables, consts, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, diag, total;
+  size_t status, tables, consts, segs, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, diag,
+      total;
   size_t corr_bytes;
 };
 
@@ -42,9 +43,10 @@ Geom make_geom(const lbm_desc &d) {
   g.px = 0; g.py = pad[1]; g.pz = pad[2];
   g.NX = n[0]; g.NY = n[1] + 2 * pad[1]; g.NZ = n[2] + 2 * pad[2];
   g.xg = pad[0];
+  g.nseg = d.n_segments > 1 ? d.n_segments : 1;
   g.N = (int64_t)d.nx * d.ny * d.nz;
   g.XG = (int64_t)g.NX * g.NY * g.NZ;
-  g.NPAD = g.XG + (g.xg ? 2LL * g.NY * g.NZ : 0);
+  g.NPAD = g.XG + (g.xg ? 2LL * g.nseg * g.NY * g.NZ : 0);
   return g;
 }
 
@@ -67,6 +69,7 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.status = take(64);
   L.tables = take(sizeof(Tables));
   L.consts = take(sizeof(CollideConsts));
+  L.segs = take(g.nseg > 1 ? ((size_t)d.nx + g.nseg + 1) * 4 : 0);   // x -> segment, segment offsets
   L.pop0 = take(S * Q * (size_t)g.NPAD * st);
   L.pop1 = take(S * Q * (size_t)g.NPAD * st);
   L.T = take(N * 8);
@@ -163,9 +166,22 @@ bool validate(const lbm_desc *d, std::string *err) {
     }
     if (std::fabs(ys - 1.0) > 1e-9) return fail(err, "ref_state: mass fractions sum to %.17g, not 1", ys);
   }
+  if (d->n_segments < 0) return fail(err, "n_segments = %d must be >= 0", d->n_segments);
+  if (d->n_segments > 1) {
+    if (d->bc[0] == LBM_BC_PERIODIC) return fail(err, "segments along x need non-periodic x faces");
+    if (d->n_segments > d->nx) return fail(err, "n_segments = %d exceeds nx = %d", d->n_segments, d->nx);
+    if (!d->segment_lengths) return fail(err, "segment_lengths must not be NULL when n_segments > 1");
+    int64_t sum = 0;
+    for (int s = 0; s < d->n_segments; ++s) {
+      if (d->segment_lengths[s] < 1) return fail(err, "segment_lengths[%d] = %d must be >= 1", s, d->segment_lengths[s]);
+      sum += d->segment_lengths[s];
+    }
+    if (sum != d->nx) return fail(err, "segment lengths sum to %lld, not nx = %d", (long long)sum, d->nx);
+  }
   {
     // the step kernel addresses one padded plane with 32-bit byte offsets
-    const double padded = (double)(d->nx + (d->bc[0] == LBM_BC_PERIODIC ? 0 : 2)) *
+    const double xghost = d->bc[0] == LBM_BC_PERIODIC ? 0.0 : 2.0 * (d->n_segments > 1 ? d->n_segments : 1);
+    const double padded = (d->nx + xghost) *
                           (d->ny + (d->bc[2] == LBM_BC_PERIODIC ? 0 : 2)) *
                           (d->nz + (d->bc[4] == LBM_BC_PERIODIC ? 0 : 2));
     const double word = d->storage == LBM_STORE_F64 ? 8.0 : 4.0;   // largest element of a plane
@@ -296,6 +312,7 @@ struct lbm_ctx {
   std::vector<double> arrh;
   std::vector<uint8_t> rev;
   std::vector<double> ref_state;
+  std::vector<int32_t> seg_len;
   Geom g{};
   Layout L{};
   Buffers b{};
@@ -370,6 +387,12 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
     h->ref_state.assign(desc->ref_state, desc->ref_state + 2 + M);
     h->d.ref_state = h->ref_state.data();
   }
+  if (desc->n_segments > 1) {
+    h->seg_len.assign(desc->segment_lengths, desc->segment_lengths + desc->n_segments);
+    h->d.segment_lengths = h->seg_len.data();
+  } else {
+    h->d.segment_lengths = nullptr;
+  }
   h->g = make_geom(h->d);
   h->L = make_layout(h->d, h->g);
   if (bytes < h->L.total) {
@@ -402,6 +425,10 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   b.corr = ws + L.corr;
   b.kc = reinterpret_cast<const CollideConsts *>(ws + L.consts);
   b.diag = reinterpret_cast<double *>(ws + L.diag);
+  if (h->g.nseg > 1) {
+    h->g.x_seg = reinterpret_cast<const int32_t *>(ws + L.segs);
+    h->g.seg_off = h->g.x_seg + h->d.nx;
+  }
   Tables t;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
@@ -416,6 +443,16 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   }
   e = hipMemcpy(ws + L.tables, &t, sizeof(Tables), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ws + L.consts, &h->kc, sizeof(CollideConsts), hipMemcpyHostToDevice);
+  if (e == hipSuccess && h->g.nseg > 1) {
+    std::vector<int32_t> segs((size_t)h->d.nx + h->g.nseg + 1);
+    int32_t x = 0;
+    for (int s = 0; s < h->g.nseg; ++s) {
+      segs[(size_t)h->d.nx + s] = x;
+      for (int k = 0; k < h->seg_len[s]; ++k) segs[x++] = s;
+    }
+    segs[(size_t)h->d.nx + h->g.nseg] = x;
+    e = hipMemcpy(ws + L.segs, segs.data(), segs.size() * 4, hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) {
     uint32_t zero[16] = {0};
     e = hipMemcpy(ws + L.status, zero, sizeof(zero), hipMemcpyHostToDevice);

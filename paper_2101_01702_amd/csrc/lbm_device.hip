@@ -74,12 +74,39 @@ __device__ __forceinline__ AxisSrc axis_src(int x, int n, bool periodic) {
   return a;
 }
 
-// index in a plane of cell x (-1..nx) of padded row prow: in the row, or one of the x
-// ghost cells after the rows
+// first and last x of the segment that holds x, and the segment's index
+struct XSeg {
+  int x0, x1, s;
+};
+__device__ __forceinline__ XSeg x_segment(const Geom &g, int x) {
+  if (g.nseg <= 1) return XSeg{0, g.nx - 1, 0};
+  const int s = g.x_seg[x];
+  return XSeg{g.seg_off[s], g.seg_off[s + 1] - 1, s};
+}
+
+// x ghost cells are coded as x = -1 - q, q = 2 s (before segment s) or 2 s + 1 (after it)
+__device__ __forceinline__ int x_ghost_code(int s, int side) { return -1 - (2 * s + side); }
+
+// index in a plane of cell x of padded row prow: in the row, or, for a coded x ghost
+// cell, one of the x ghost cells after the rows
 __device__ __forceinline__ uint32_t cell_index(const Geom &g, int x, uint32_t prow) {
-  if (x < 0) return (uint32_t)g.XG + prow;
-  if (x >= g.nx) return (uint32_t)(g.XG + (int64_t)g.NY * g.NZ) + prow;
+  if (x < 0) return (uint32_t)(g.XG + (int64_t)(-1 - x) * g.NY * g.NZ) + prow;
   return prow * (uint32_t)g.NX + (uint32_t)x;
+}
+
+// x sources x - c for c = -1, 0, +1: wrapped on a periodic axis; on an open one a
+// source beyond the end of the lane's segment is that end's coded x ghost cell
+__device__ __forceinline__ AxisSrc axis_src_x(const Geom &g, int x) {
+  AxisSrc a;
+  if (g.per[0]) return axis_src(x, g.nx, true);
+  const XSeg sg = x_segment(g, x);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int v = x - (k - 1);
+    a.out[k] = v < sg.x0 || v > sg.x1;
+    a.s[k] = v < sg.x0 ? x_ghost_code(sg.s, 0) : (v > sg.x1 ? x_ghost_code(sg.s, 1) : v);
+  }
+  return a;
 }
 
 __device__ __forceinline__ Src make_src(const Geom &g, const AxisSrc &ax, const AxisSrc &ay,
@@ -284,7 +311,7 @@ __device__ __forceinline__ void node_moments(const Geom &g, const ST *__restrict
                                              const Corr<typename Fmt<ST>::Side> &cr, const CollideConsts &kc,
                                              int x, int y, int z, Macro<M> &m) {
   using Side = typename Fmt<ST>::Side;
-  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ax = axis_src_x(g, x);
   const int64_t NPAD = g.NPAD;
   double rho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
   double rE = 0, qx = 0, qy = 0, qz = 0;
@@ -487,10 +514,24 @@ __device__ __forceinline__ Rsrc plane(const void *buf, const Geom &g, int k) {
 typedef const __attribute__((address_space(4))) CollideConsts KC4;
 typedef const __attribute__((address_space(4))) Tables TB4;
 
-// A lane's node for the pulls: its coordinates.
+// A lane's node for the pulls: its coordinates, whether it is the first (lo) or last
+// (hi) x of its segment, and the first x ghost cell of its segment (XG + 2 s NY NZ).
 struct LaneSrc {
   int x, y, z;
+  bool lo, hi;
+  uint32_t xq;
 };
+__device__ __forceinline__ LaneSrc lane_src(const Geom &g, int64_t n) {
+  LaneSrc l;
+  l.x = (int)(n % g.nx);
+  l.y = (int)((n / g.nx) % g.ny);
+  l.z = (int)(n / ((int64_t)g.nx * g.ny));
+  const XSeg sg = x_segment(g, l.x);
+  l.lo = l.x == sg.x0;
+  l.hi = l.x == sg.x1;
+  l.xq = (uint32_t)(g.XG + 2LL * sg.s * g.NY * g.NZ);
+  return l;
+}
 
 // source row of the directions (*, cy, cz), y - cy and z - cz wrapped on periodic axes
 // (an open axis has a ghost layer and never wraps): the padded row and the index of
@@ -508,14 +549,14 @@ __device__ __forceinline__ RowPos row_source(const Geom &g, const LaneSrc &l, in
   return r;
 }
 // index of the source of direction (CX, cy, cz) in its row: x - CX, wrapped on a
-// periodic x axis, or one of the x ghost cells after the rows on an open one
+// periodic x axis, or the x ghost cell of the segment's end on an open one
 template <int CX>
 __device__ __forceinline__ uint32_t dir_source(const Geom &g, const LaneSrc &l, const RowPos &r) {
   uint32_t p = r.p0 - (uint32_t)CX;
   if constexpr (CX != 0) {
-    const bool edge = l.x == (CX > 0 ? 0 : g.nx - 1);
+    const bool edge = CX > 0 ? l.lo : l.hi;
     if (g.per[0]) p += edge ? (uint32_t)(CX * g.nx) : 0u;
-    if (g.xg) p = edge ? (uint32_t)g.XG + (CX > 0 ? 0u : (uint32_t)(g.NY * g.NZ)) + r.row : p;
+    if (g.xg) p = edge ? l.xq + (CX > 0 ? 0u : (uint32_t)(g.NY * g.NZ)) + r.row : p;
   }
   return p;
 }
@@ -1221,10 +1262,7 @@ __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cu
   const IslStash sh{(lds_double *)&words[threadIdx.x]};
   const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
-  LaneSrc l;
-  l.x = (int)(n % g.nx);
-  l.y = (int)((n / g.nx) % g.ny);
-  l.z = (int)(n / ((int64_t)g.nx * g.ny));
+  const LaneSrc l = lane_src(g, n);
 
   KC4 *kp = (KC4 *)b.kc;
   CollCoef<M, F> cc;
@@ -1246,22 +1284,24 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
   const RT *phi = static_cast<const RT *>(b.side_phi);
   const int64_t N = g.N;
   const double coef = 1.0 / b.tab->omega - 0.5;
+  // x neighbours within the node's segment (the whole axis when it is periodic)
+  const XSeg xsg = x_segment(g, x);
   int xs[3], ys[3], zs[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    xs[k] = nb_coord(x, k - 1, g.nx, g.per[0]);
+    xs[k] = g.per[0] ? nb_coord(x, k - 1, g.nx, true) : min(max(x + k - 1, xsg.x0), xsg.x1);
     ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
     zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
   }
   // phi_alpha is odd in u_alpha: its mirror image beyond a symmetry face normal to
   // alpha has the opposite sign
   double sg[3][3];
-  const int xyz[3] = {x, y, z}, nn3[3] = {g.nx, g.ny, g.nz};
+  const int xyz[3] = {x, y, z}, lo3[3] = {xsg.x0, 0, 0}, hi3[3] = {xsg.x1, g.ny - 1, g.nz - 1};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    sg[a][0] = (xyz[a] == 0 && g.bc[2 * a] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+    sg[a][0] = (xyz[a] == lo3[a] && g.bc[2 * a] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
     sg[a][1] = 1.0;
-    sg[a][2] = (xyz[a] == nn3[a] - 1 && g.bc[2 * a + 1] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+    sg[a][2] = (xyz[a] == hi3[a] && g.bc[2 * a + 1] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
   }
   double acc[3] = {0, 0, 0};
   static_for<27>([&](auto Ic) {
@@ -1326,6 +1366,10 @@ __global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
   if (x >= g.nx || y >= g.ny || z >= g.nz) return;
   const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
   const int c0 = ((lz + 1) * CH_Y + (ly + 1)) * CH_X + (lx + 1);
+  // x neighbours stay within the node's segment: at its ends the stencil takes the node
+  // itself (the halo cell beyond the lattice's ends holds the same value)
+  const XSeg xsg = x_segment(g, x);
+  const int dxm = (!g.per[0] && x == xsg.x0) ? 0 : -1, dxp = (!g.per[0] && x == xsg.x1) ? 0 : 1;
   // side fields in RT, sums in FP64
   double wa[M];
 #pragma unroll
@@ -1335,7 +1379,7 @@ __global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     if constexpr (I != 13) {
-      const int nc = c0 + (cz * CH_Y + cy) * CH_X + cx;
+      const int nc = c0 + (cz * CH_Y + cy) * CH_X + (cx < 0 ? dxm : (cx > 0 ? dxp : 0));
       constexpr double w = 3.0 * wgt(I);
       if constexpr (cx != 0) X[0] -= (cx * w) * double(sh[0 * CH_CELLS + nc]);
       if constexpr (cy != 0) X[1] -= (cy * w) * double(sh[1 * CH_CELLS + nc]);
@@ -1451,7 +1495,7 @@ __global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, CollideConsts k
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
-  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ax = axis_src_x(g, x);
   const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
   const AxisSrc az = axis_src(z, g.nz, g.per[2]);
   int64_t pidx[27];
@@ -1468,54 +1512,71 @@ __global__ __launch_bounds__(128) void k_init(Geom g, Buffers b, CollideConsts k
   b.T[n] = T[n];
 }
 
-// ghost cell t of the slabs beyond the non-periodic faces: x slabs (all padded y, z),
-// then y slabs (interior x, padded z), then z slabs (interior x, y)
+// Ghost cell t of the slabs beyond the non-periodic faces: the x ghost cells (two per
+// segment and padded row, in their order after the rows), then the y slabs (interior
+// x, padded z), then the z slabs (interior x, y).  gc holds its coordinates, x relative
+// to the first x (x0) of its segment of length len; for the y and z slabs the segment
+// is the whole row.  p is its index in a plane.
+struct GhostCell {
+  int gc[3];
+  int x0, len;
+  uint32_t p;
+};
 __device__ __forceinline__ bool ghost_cell(const Geom &g, int64_t t, int64_t nx_slab, int64_t ny_slab,
-                                           int64_t nz_slab, int (&gc)[3]) {
-  if (t < nx_slab) {          // x = -1 or nx
+                                           int64_t nz_slab, GhostCell &c) {
+  c.x0 = 0;
+  c.len = g.nx;
+  if (t < nx_slab) {          // before or after a segment: x ghost cell XG + t
     const int64_t per = (int64_t)g.NY * g.NZ;
-    gc[0] = (t < per) ? -1 : g.nx;
+    const int q = (int)(t / per);
     const int64_t r = t % per;
-    gc[1] = (int)(r % g.NY) - g.py;
-    gc[2] = (int)(r / g.NY) - g.pz;
+    if (g.nseg > 1) {
+      c.x0 = g.seg_off[q >> 1];
+      c.len = g.seg_off[(q >> 1) + 1] - c.x0;
+    }
+    c.gc[0] = (q & 1) ? c.len : -1;
+    c.gc[1] = (int)(r % g.NY) - g.py;
+    c.gc[2] = (int)(r / g.NY) - g.pz;
+    c.p = (uint32_t)(g.XG + t);
     return true;
   }
   if ((t -= nx_slab) < ny_slab) {   // y = -1 or ny
     const int64_t per = (int64_t)g.nx * g.NZ;
-    gc[1] = (t < per) ? -1 : g.ny;
+    c.gc[1] = (t < per) ? -1 : g.ny;
     const int64_t r = t % per;
-    gc[0] = (int)(r % g.nx);
-    gc[2] = (int)(r / g.nx) - g.pz;
-    return true;
-  }
-  if ((t -= ny_slab) < nz_slab) {   // z = -1 or nz
+    c.gc[0] = (int)(r % g.nx);
+    c.gc[2] = (int)(r / g.nx) - g.pz;
+  } else if ((t -= ny_slab) < nz_slab) {   // z = -1 or nz
     const int64_t per = (int64_t)g.nx * g.ny;
-    gc[2] = (t < per) ? -1 : g.nz;
+    c.gc[2] = (t < per) ? -1 : g.nz;
     const int64_t r = t % per;
-    gc[0] = (int)(r % g.nx);
-    gc[1] = (int)(r / g.nx);
-    return true;
+    c.gc[0] = (int)(r % g.nx);
+    c.gc[1] = (int)(r / g.nx);
+  } else {
+    return false;
   }
-  return false;
+  c.p = cell_index(g, c.gc[0], (uint32_t)(c.gc[2] + g.pz) * (uint32_t)g.NY + (uint32_t)(c.gc[1] + g.py));
+  return true;
 }
 
 // The boundary node a ghost cell stands for: the ghost reflected back across every face
-// it lies beyond (for the one-cell layer, the nearest node).  mirror gets a bit per
-// crossed symmetry face, open is set when an open face is crossed, zero_u when a
-// zero-velocity face is.
+// it lies beyond (for the one-cell layer, the nearest node), and its index pa in a
+// plane.  mirror gets a bit per crossed symmetry face, open is set when an open face is
+// crossed, zero_u when a zero-velocity face is.
 struct GhostSrc {
-  int a3[3];
+  int a3[3];        // lattice coordinates (x global)
+  uint32_t pa;
   int mirror;
   bool open, zero_u;
 };
-__device__ __forceinline__ GhostSrc ghost_src(const Geom &g, const int (&gc)[3]) {
-  const int nn[3] = {g.nx, g.ny, g.nz};
+__device__ __forceinline__ GhostSrc ghost_src(const Geom &g, const GhostCell &c) {
+  const int nn[3] = {c.len, g.ny, g.nz};
   GhostSrc r;
   r.mirror = 0;
   r.open = r.zero_u = false;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    int v = gc[d];
+    int v = c.gc[d];
     if (v < 0 || v >= nn[d]) {
       const int bc = g.bc[2 * d + (v < 0 ? 0 : 1)];
       if (bc == LBM_BC_SYMMETRY) {
@@ -1528,6 +1589,8 @@ __device__ __forceinline__ GhostSrc ghost_src(const Geom &g, const int (&gc)[3])
     }
     r.a3[d] = v;
   }
+  r.a3[0] += c.x0;
+  r.pa = cell_index(g, r.a3[0], (uint32_t)(r.a3[2] + g.pz) * (uint32_t)g.NY + (uint32_t)(r.a3[1] + g.py));
   return r;
 }
 
@@ -1540,13 +1603,13 @@ template <int M, typename ST, typename RT>
 __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts kc, int cur, int64_t nx_slab,
                                                int64_t ny_slab, int64_t nz_slab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int gc[3];
-  if (!ghost_cell(g, t, nx_slab, ny_slab, nz_slab, gc)) return;
-  const GhostSrc gs = ghost_src(g, gc);
-  const int nn[3] = {g.nx, g.ny, g.nz};
+  GhostCell c;
+  if (!ghost_cell(g, t, nx_slab, ny_slab, nz_slab, c)) return;
+  const GhostSrc gs = ghost_src(g, c);
+  const int nn[3] = {c.len, g.ny, g.nz};
   const int64_t N = g.N;
   const int64_t na = ((int64_t)gs.a3[2] * g.ny + gs.a3[1]) * g.nx + gs.a3[0];
-  const int64_t p = cell_index(g, gc[0], (uint32_t)(gc[2] + g.pz) * (uint32_t)g.NY + (uint32_t)(gc[1] + g.py));
+  const int64_t p = c.p, pa = gs.pa;
   ST *dst = static_cast<ST *>(b.pop[cur ^ 1]);
   EqState<M> e;
   if (gs.open) {
@@ -1561,24 +1624,22 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts 
     for (int a = 0; a < M; ++a) Y[a] = double(sY[a * N + na]);
     eq_state<M>(*b.tab, double(srho[na]), u, b.T[na], Y, e);
   }
-  const int64_t pa = cell_index(g, gs.a3[0], (uint32_t)(gs.a3[2] + g.pz) * (uint32_t)g.NY +
-                                                 (uint32_t)(gs.a3[1] + g.py));
-  // only the directions along which an interior node pulls from this ghost cell (a
-  // face cell serves 9, an edge cell 3, a corner cell 1); a runtime loop keeps the
-  // kernel small
+  // only the directions along which a node of the lattice (of the segment, for x) pulls
+  // from this ghost cell (a face cell serves 9, an edge cell 3, a corner cell 1); a
+  // runtime loop keeps the kernel small
 #pragma unroll 1
   for (int i = 0; i < 27; ++i) {
-    const int c[3] = {cx_of(i), cy_of(i), cz_of(i)};
+    const int cv[3] = {cx_of(i), cy_of(i), cz_of(i)};
     bool need = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int t2 = gc[d] + c[d];
+      const int t2 = c.gc[d] + cv[d];
       need = need && (g.per[d] || (t2 >= 0 && t2 < nn[d]));
     }
     if (!need) continue;
     int cm[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) cm[d] = (gs.mirror >> d & 1) ? -c[d] : c[d];
+    for (int d = 0; d < 3; ++d) cm[d] = (gs.mirror >> d & 1) ? -cv[d] : cv[d];
     if (gs.open) {
       write_eq_dir<M, ST>(e, kc, dst, g.NPAD, i, cm[0], cm[1], cm[2], p);
     } else {
@@ -1600,13 +1661,11 @@ template <typename CT>
 __global__ __launch_bounds__(128) void k_ghost_corr(Geom g, Buffers b, int64_t nx_slab, int64_t ny_slab,
                                                     int64_t nz_slab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int gc[3];
-  if (!ghost_cell(g, t, nx_slab, ny_slab, nz_slab, gc)) return;
-  const GhostSrc gs = ghost_src(g, gc);
+  GhostCell gcl;
+  if (!ghost_cell(g, t, nx_slab, ny_slab, nz_slab, gcl)) return;
+  const GhostSrc gs = ghost_src(g, gcl);
   if (gs.open || gs.mirror == 0) return;
-  const int64_t p = cell_index(g, gc[0], (uint32_t)(gc[2] + g.pz) * (uint32_t)g.NY + (uint32_t)(gc[1] + g.py));
-  const int64_t pa = cell_index(g, gs.a3[0], (uint32_t)(gs.a3[2] + g.pz) * (uint32_t)g.NY +
-                                                 (uint32_t)(gs.a3[1] + g.py));
+  const int64_t p = gcl.p, pa = gs.pa;
   CT *corr = static_cast<CT *>(b.corr);
   const int64_t NPAD = g.NPAD;
 #pragma unroll
@@ -1662,7 +1721,7 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, CollideConsts
   using Side = typename Fmt<ST>::Side;
   const ST *pop = static_cast<const ST *>(b.pop[cur]);
   const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * g.NPAD, g.NPAD};
-  const AxisSrc ax = axis_src(x, g.nx, g.per[0]);
+  const AxisSrc ax = axis_src_x(g, x);
   const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
   const AxisSrc az = axis_src(z, g.nz, g.per[2]);
   for (int kyz = 0; kyz < 9; ++kyz) {
@@ -1841,7 +1900,7 @@ struct RunInit {
 template <int M, typename ST, typename RT>
 struct RunGhost {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
-    const int64_t sx = g.xg ? 2LL * g.NY * g.NZ : 0;
+    const int64_t sx = g.xg ? 2LL * g.nseg * g.NY * g.NZ : 0;
     const int64_t sy = g.py ? 2LL * g.nx * g.NZ : 0;
     const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
     const int64_t tot = sx + sy + sz;
@@ -1875,7 +1934,7 @@ template <int M, typename ST, typename RT>
 struct RunGhostCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
     if (!any_symmetry(g)) return hipSuccess;
-    const int64_t sx = g.xg ? 2LL * g.NY * g.NZ : 0;
+    const int64_t sx = g.xg ? 2LL * g.nseg * g.NY * g.NZ : 0;
     const int64_t sy = g.py ? 2LL * g.nx * g.NZ : 0;
     const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
     const int64_t tot = sx + sy + sz;

@@ -57,9 +57,11 @@ struct CollideConsts {
 
 // A plane of one (set, direction) holds the rows (z, y) of the lattice padded with a
 // ghost layer on open y and z axes, x fastest (NX = nx), and after them, on an open x
-// axis, the x ghost cells: one per padded row for x = -1, then one per padded row for
-// x = nx.  Row r = (z + pz) NY + (y + py); cell x of row r at r NX + x; the x ghost
-// cells at XG + r and XG + NY NZ + r.
+// axis, the x ghost cells.  Row r = (z + pz) NY + (y + py); cell x of row r at r NX + x.
+// The x axis may be split into nseg independent segments (a batch of lattices of the
+// same cross-section side by side, each with the x faces' boundary conditions at both
+// of its ends); segment s has the x ghost cells XG + 2 s NY NZ + r before its first x
+// and XG + (2 s + 1) NY NZ + r after its last.  One segment: XG + r and XG + NY NZ + r.
 struct Geom {
   int32_t M;                  // species
   int32_t nx, ny, nz;
@@ -68,9 +70,11 @@ struct Geom {
   int32_t per[3];             // periodic axis flags
   int32_t bc[6];
   int32_t xg;                 // 1 when the x axis is open: x ghost cells after the rows
-  int32_t pad_;
+  int32_t nseg;               // independent segments along x (1: one lattice)
   int64_t N, NPAD;            // interior nodes, cells of one plane
   int64_t XG;                 // first x ghost cell, NX NY NZ
+  const int32_t *x_seg;       // [nx] segment of each x (nseg > 1)
+  const int32_t *seg_off;     // [nseg + 1] first x of each segment, then nx (nseg > 1)
 };
 
 // Device pointers into the workspace.

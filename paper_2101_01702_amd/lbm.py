@@ -40,6 +40,7 @@ class LbmDesc(C.Structure):
         ("omega", C.c_double), ("omega1", C.c_double),
         ("kappa", C.c_double), ("dt_phys", C.c_double), ("rho_ref", C.c_double), ("p0", C.c_double),
         ("storage", C.c_int32), ("reserved", C.c_int32), ("ref_state", C.c_void_p),
+        ("n_segments", C.c_int32), ("reserved2", C.c_int32), ("segment_lengths", _ip),
     ]
 
 
@@ -115,6 +116,11 @@ def make_desc(prob, storage: Optional[int] = None):
     d.omega, d.omega1 = prob.omega, prob.omega1
     d.kappa, d.dt_phys, d.rho_ref, d.p0 = prob.kappa, prob.dt_phys, prob.rho_ref, prob.p0
     d.storage = prob.storage if storage is None else storage
+    segs = getattr(prob, "segments", None)
+    if segs is not None and len(segs) > 1:
+        keep["segments"] = np.ascontiguousarray(segs, np.int32)
+        d.n_segments = len(segs)
+        d.segment_lengths = keep["segments"].ctypes.data_as(_ip)
     if d.storage in (STORE_F16_DEV, STORE_BF16_DEV):
         ref = prob.ref_state
         if ref is None:

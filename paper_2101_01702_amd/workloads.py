@@ -89,6 +89,8 @@ class Problem:
     storage: int = STORE_F64
     # quiescent reference state of the 16-bit deviation formats: [rho, T, Y_0..Y_M-1]
     ref_state: Optional[np.ndarray] = None
+    # lengths along x of independent lattices side by side (a batch); None: one lattice
+    segments: Optional[Tuple[int, ...]] = None
 
     @property
     def N(self) -> int:
@@ -395,6 +397,85 @@ def flame1d(nx: int = 4096, seed: int = FLAME_SEED, phi: float = 1.0, T_u: float
     return Problem(f"flame1d_{nx}", nx, 1, 1, (BC_OPEN_U0, BC_OPEN, 0, 0, 0, 0), mech, D, omega,
                    omega1_from_prandtl(omega, prandtl), kappa, dt_phys, rho_ref, P_ATM,
                    rho, u, T, Y, steps=steps, storage=storage, ref_state=ref)
+
+
+def flame_batch(n_flames: int = 256, seed: int = FLAME_SEED, len_range=(512, 8192), phi_range=(0.5, 3.0),
+                T_u: float = 300.0, T_hot: float = 2000.0, hot_cells: int = 64, zeta_ref: float = 0.003,
+                omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 3e-10,
+                diff_range=(0.02, 0.08), edge: float = 8.0, storage: int = STORE_F32,
+                lengths: Optional[Sequence[int]] = None, phis: Optional[Sequence[float]] = None,
+                mech: Optional[Mechanism] = None) -> Problem:
+    """Batch of independent quasi-1D premixed flames side by side along x, each set up
+    as ``flame1d`` (zero-velocity open end at its -x end, open end at +x, hot slab of
+    ``hot_cells`` cells with a tanh edge at its +x end).  Lengths are drawn uniformly
+    from the integers in ``len_range`` and equivalence ratios uniformly from
+    ``phi_range`` (seeded), unless given.  All flames share the mechanism, the
+    diffusivities and the lattice units; kappa and rho_ref come from the
+    stoichiometric premixture at T_u, so a flame at another equivalence ratio has its
+    own unburnt lattice R T (zeta_ref scaled by the mean molar mass ratio)."""
+    rng = np.random.default_rng(seed + 3000)
+    mech = mech or h2air_mechanism(seed)
+    M = mech.M
+    if lengths is None:
+        lengths = rng.integers(len_range[0], len_range[1] + 1, size=n_flames)
+    if phis is None:
+        phis = rng.uniform(phi_range[0], phi_range[1], size=len(lengths))
+    lengths = [int(v) for v in lengths]
+    if len(phis) != len(lengths) or min(lengths) < 1:
+        raise ValueError("one equivalence ratio per flame and lengths >= 1 are needed")
+    m_st = float(mean_molar_mass(premixed_h2air_X(mech, 1.0), mech.molar_mass))
+    kappa, rho_ref = lattice_scales(zeta_ref, T_u, m_st, P_ATM)
+    rho_l, T_l, Y_l = [], [], []
+    for nx, phi in zip(lengths, phis):
+        X_u = premixed_h2air_X(mech, float(phi))
+        x = np.arange(nx, dtype=np.float64)
+        hot = tanh_profile(x - (nx - hot_cells - 0.5), edge)
+        T = T_u + (T_hot - T_u) * hot
+        X = np.repeat(X_u[:, None], nx, axis=1)
+        Y_l.append(mole_to_mass(X, mech.molar_mass))
+        m = mean_molar_mass(X, mech.molar_mass)
+        rho_l.append(lattice_density(np.full(nx, P_ATM), T, m, rho_ref))
+        T_l.append(T)
+    N = int(sum(lengths))
+    D = _default_transport(M, np.random.default_rng(seed + 1000), *diff_range)
+    Y_st = mole_to_mass(premixed_h2air_X(mech, 1.0), mech.molar_mass)
+    ref = np.concatenate([[lattice_density(P_ATM, T_u, m_st, rho_ref), T_u], Y_st])
+    prob = Problem(f"flame_batch_{len(lengths)}x{N}", N, 1, 1, (BC_OPEN_U0, BC_OPEN, 0, 0, 0, 0), mech, D,
+                   omega, omega1_from_prandtl(omega, prandtl), kappa, dt_phys, rho_ref, P_ATM,
+                   np.concatenate(rho_l), np.zeros((3, N)), np.concatenate(T_l), np.concatenate(Y_l, axis=1),
+                   storage=storage, ref_state=ref, segments=tuple(lengths))
+    prob.phis = np.asarray(phis, np.float64)
+    return prob
+
+
+def split_batch(prob: Problem) -> List[Problem]:
+    """The lattices of a batch (``Problem.segments``) as separate problems, in order:
+    the x ranges of the batch lattice, each with the full cross-section."""
+    if prob.segments is None:
+        return [prob]
+    shp = (prob.nz, prob.ny, prob.nx)
+
+    def cut(a, sl):
+        lead = a.shape[:-1]
+        return np.ascontiguousarray(a.reshape(lead + shp)[..., sl]).reshape(lead + (-1,))
+
+    out, x0 = [], 0
+    for k, nx in enumerate(prob.segments):
+        sl = slice(x0, x0 + nx)
+        out.append(dataclasses.replace(prob, name=f"{prob.name}[{k}]", nx=nx, rho=cut(prob.rho, sl),
+                                       u=cut(prob.u, sl), T=cut(prob.T, sl), Y=cut(prob.Y, sl),
+                                       segments=None))
+        x0 += nx
+    return out
+
+
+def batch_nodes(prob: Problem, k: int) -> np.ndarray:
+    """Node indices (of the whole batch lattice) of segment k, in that segment's own
+    node order."""
+    x0 = int(sum(prob.segments[:k]))
+    nx = prob.segments[k]
+    z, y, x = np.meshgrid(np.arange(prob.nz), np.arange(prob.ny), np.arange(x0, x0 + nx), indexing="ij")
+    return (x + prob.nx * (y + prob.ny * z)).reshape(-1)
 
 
 def sphere3d(n: int = 256, seed: int = FLAME_SEED, phi: float = 0.8, T_u: float = 300.0,

@@ -196,3 +196,51 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lbm_status_sync(None, None, None) == -1
     assert lib.lbm_diagnostics(None, 1000.0, None, None, None) == -1
     assert lib.lbm_adjoint_step(None, None, None, None, None) == -2
+
+
+def test_segment_descriptors(lib):
+    """A batch of lattices along x: lengths >= 1 summing to nx, non-periodic x faces;
+    two x ghost cells per segment and row, plus the segment table."""
+    prob = W.flame_batch(lengths=[7, 1, 12], phis=[1.0, 1.0, 1.0], hot_cells=4, storage=W.STORE_F64)
+    d, keep = lbm.make_desc(prob)
+    assert d.n_segments == 3
+    code, n3, msg = _ws(lib, d)
+    assert code == 0, msg
+    one = W.flame_batch(lengths=[20], phis=[1.0], hot_cells=4, storage=W.STORE_F64)
+    d1, k1 = lbm.make_desc(one)
+    assert d1.n_segments == 0
+    code, n1, msg = _ws(lib, d1)
+    assert code == 0, msg
+    S = prob.M + 1
+    assert n3 - n1 >= 2 * S * 27 * 4 * 8            # 2 x 2 more ghost cells per plane, two copies
+    for lens, needle in (([7, 1, 11], "sum"), ([7, 0, 13], "segment_lengths[1]")):
+        arr = np.array(lens, np.int32)
+        d.segment_lengths = arr.ctypes.data_as(C.POINTER(C.c_int32))
+        code, _, msg = _ws(lib, d)
+        assert code == -1 and needle in msg, msg
+    d.segment_lengths = None
+    code, _, msg = _ws(lib, d)
+    assert code == -1 and "NULL" in msg
+    d, keep = lbm.make_desc(prob)
+    d.n_segments = -2
+    code, _, msg = _ws(lib, d)
+    assert code == -1 and "n_segments" in msg
+    d, keep = lbm.make_desc(prob)
+    d.bc = (C.c_int32 * 6)(0, 0, 0, 0, 0, 0)
+    code, _, msg = _ws(lib, d)
+    assert code == -1 and "periodic" in msg
+    d, keep = lbm.make_desc(prob)
+    d.n_segments = 21
+    code, _, msg = _ws(lib, d)
+    assert code == -1 and "exceeds" in msg
+
+
+def test_split_batch_keeps_every_node():
+    prob = W.flame_batch(n_flames=5, len_range=(3, 9), seed=11)
+    parts = W.split_batch(prob)
+    assert [p.nx for p in parts] == list(prob.segments)
+    for k, p in enumerate(parts):
+        idx = W.batch_nodes(prob, k)
+        assert np.array_equal(p.T, prob.T[idx]) and np.array_equal(p.Y, prob.Y[:, idx])
+        assert np.array_equal(p.rho, prob.rho[idx])
+    assert np.array_equal(np.sort(np.concatenate([W.batch_nodes(prob, k) for k in range(5)])), np.arange(prob.N))
