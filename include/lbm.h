@@ -171,6 +171,15 @@ lbm_status lbm_step(lbm_handle h, int32_t n_steps, void *stream);
                              collision of all sets), 1 psi stencil, 2 correction stencil, 3 ghosts */
 lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms_out);
 
+/* Same result as lbm_step, bit for bit.  The launches of n_steps steps are recorded
+ * once into a HIP graph (per handle, per n_steps and per parity of the number of steps
+ * taken so far; the 8 most recent recordings are kept) and replayed by one graph launch
+ * on the stream.  This removes the per-kernel launch cost of small lattices and batches
+ * of short ones.  A recording holds kernel launches only (no allocation, no memset);
+ * it is captured on a stream of the handle, created at the first call, and released
+ * by lbm_destroy. */
+lbm_status lbm_step_graph(lbm_handle h, int32_t n_steps, void *stream);
+
 /* Macroscopic fields of the current (pre-collision) state into device FP64
  * arrays, any of which may be NULL: rho[N], u[3][N], T[N], P[N] (lattice
  * pressure rho R T), Y[M][N].  Does not modify the state. */

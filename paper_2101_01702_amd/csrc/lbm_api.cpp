@@ -305,6 +305,14 @@ void build_reference(const lbm_desc &d, const Tables &t, CollideConsts &kc) {
 
 }  // namespace
 
+// a recorded sequence of steps: n_steps steps from a state of the given ping-pong parity
+struct GraphEntry {
+  int32_t n_steps;
+  int parity;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 struct lbm_ctx {
   lbm_desc d{};
   std::vector<double> molar_mass, nasa7, diff;
@@ -320,6 +328,8 @@ struct lbm_ctx {
   int cur = 0;
   int device = 0;
   std::string err;
+  std::vector<GraphEntry> graphs;   // lbm_step_graph recordings, most recent last
+  hipStream_t capture = nullptr;    // stream the recordings are captured on
 };
 
 namespace {
@@ -467,6 +477,13 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
 }
 
 lbm_status lbm_destroy(lbm_handle h) {
+  if (h) {
+    for (GraphEntry &ge : h->graphs) {
+      (void)hipGraphExecDestroy(ge.exec);
+      (void)hipGraphDestroy(ge.graph);
+    }
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+  }
   delete h;
   return LBM_OK;
 }
@@ -535,6 +552,50 @@ lbm_status lbm_step_timed(lbm_handle h, int32_t n_steps, void *stream, float *ms
   if (n_steps < 0) return arg_fail(h, "n_steps must be >= 0");
   if (!ms_out) return arg_fail(h, "ms_out is NULL");
   return run_steps(h, n_steps, static_cast<hipStream_t>(stream), ms_out);
+}
+
+lbm_status lbm_step_graph(lbm_handle h, int32_t n_steps, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (n_steps < 0) return arg_fail(h, "n_steps must be >= 0");
+  if (n_steps == 0) return LBM_OK;
+  const int parity = h->cur;
+  GraphEntry *ge = nullptr;
+  for (GraphEntry &g : h->graphs)
+    if (g.n_steps == n_steps && g.parity == parity) ge = &g;
+  if (!ge) {
+    hipError_t e = hipSuccess;
+    if (!h->capture) e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+    // recording launches nothing: the ping-pong parity is restored after it
+    const lbm_status st = run_steps(h, n_steps, h->capture, nullptr);
+    h->cur = parity;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(h->capture, &graph);
+    if (st != LBM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(h, e, "hipGraphInstantiate");
+    }
+    if (h->graphs.size() >= 8) {   // keep the 8 most recent recordings
+      (void)hipGraphExecDestroy(h->graphs.front().exec);
+      (void)hipGraphDestroy(h->graphs.front().graph);
+      h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back(GraphEntry{n_steps, parity, graph, exec});
+    ge = &h->graphs.back();
+  }
+  const hipError_t e = hipGraphLaunch(ge->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+  h->cur = parity ^ (n_steps & 1);
+  return LBM_OK;
 }
 
 lbm_status lbm_macros(lbm_handle h, double *d_rho, double *d_u, double *d_T, double *d_P, double *d_Y,

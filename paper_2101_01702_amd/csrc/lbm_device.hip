@@ -1319,13 +1319,25 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
 }
 
 // ---- X_alpha = -d_alpha psi_alpha; Cg = sum_a w_a grad Y_a ---------------------------
-// One workgroup per tile of CT_X x CT_Y x CT_Z nodes (32 x 4 x 4 measured fastest of
+// One workgroup per tile of X x Y x Z nodes (32 x 4 x 4 measured fastest of
 // 16x4x4, 32x4x2, 32x4x4 and 64x2x2).  psi (3 fields) and Y_a (M fields)
 // of the tile and its one-cell halo are staged in LDS with loads along x, and each node
 // then sums its 26 neighbours from LDS.  A halo cell holds the neighbour the gradient
 // stencil takes: wrapped on periodic axes, clamped on open ones (zero gradient).
-constexpr int CT_X = 32, CT_Y = 4, CT_Z = 4, CT_THREADS = CT_X * CT_Y * CT_Z;
-constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_CELLS = CH_X * CH_Y * CH_Z;
+// A lattice one node thick in y and z (quasi-1D flames and their batches) takes a tile
+// of 256 x 1 x 1 with no y or z halo: its y and z neighbours are the node's own row
+// (wrapped on periodic axes, clamped on open ones), so 32 x 4 x 4 tiles would leave 15
+// of 16 threads idle.
+template <bool THIN>
+struct CorrTile {
+  static constexpr int X = 32, Y = 4, Z = 4, HX = X + 2, HY = Y + 2, HZ = Z + 2;
+  static constexpr int THREADS = X * Y * Z, CELLS = HX * HY * HZ;
+};
+template <>
+struct CorrTile<true> {
+  static constexpr int X = 256, Y = 1, Z = 1, HX = X + 2, HY = 1, HZ = 1;
+  static constexpr int THREADS = X, CELLS = HX;
+};
 
 __device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
   if (periodic) {
@@ -1335,25 +1347,32 @@ __device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
   return v < 0 ? 0 : (v >= n ? n - 1 : v);
 }
 
+inline bool corr_thin(const Geom &g) { return g.ny == 1 && g.nz == 1; }
+
+template <bool THIN>
 inline int64_t corr_tiles(const Geom &g) {
-  return (int64_t)((g.nx + CT_X - 1) / CT_X) * ((g.ny + CT_Y - 1) / CT_Y) * ((g.nz + CT_Z - 1) / CT_Z);
+  using T = CorrTile<THIN>;
+  return (int64_t)((g.nx + T::X - 1) / T::X) * ((g.ny + T::Y - 1) / T::Y) * ((g.nz + T::Z - 1) / T::Z);
 }
 
-template <int M, typename RT, typename CT>
-__global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
+template <int M, typename RT, typename CT, bool THIN>
+__global__ __launch_bounds__(CorrTile<THIN>::THREADS) void k_corr(Geom g, Buffers b) {
+  using T = CorrTile<THIN>;
+  constexpr int CH_X = T::HX, CH_Y = T::HY, CH_CELLS = T::CELLS;
   __shared__ RT sh[(M + 3) * CH_CELLS];   // field f of halo cell c at f * CH_CELLS + c
-  const int tiles_x = (g.nx + CT_X - 1) / CT_X, tiles_y = (g.ny + CT_Y - 1) / CT_Y;
+  const int tiles_x = (g.nx + T::X - 1) / T::X, tiles_y = (g.ny + T::Y - 1) / T::Y;
   const int64_t t = xcd_tile();
-  const int x0 = (int)(t % tiles_x) * CT_X, y0 = (int)((t / tiles_x) % tiles_y) * CT_Y,
-            z0 = (int)(t / ((int64_t)tiles_x * tiles_y)) * CT_Z;
+  const int x0 = (int)(t % tiles_x) * T::X, y0 = (int)((t / tiles_x) % tiles_y) * T::Y,
+            z0 = (int)(t / ((int64_t)tiles_x * tiles_y)) * T::Z;
   const RT *psi = static_cast<const RT *>(b.psi);
   const RT *Yf = static_cast<const RT *>(b.side_Y);
   const RT *wf = static_cast<const RT *>(b.side_w);
   const int64_t N = g.N;
-  for (int c = threadIdx.x; c < CH_CELLS; c += CT_THREADS) {
+  for (int c = threadIdx.x; c < CH_CELLS; c += T::THREADS) {
     const int hx = c % CH_X, hy = (c / CH_X) % CH_Y, hz = c / (CH_X * CH_Y);
-    const int gx = halo_coord(x0 + hx - 1, g.nx, g.per[0]), gy = halo_coord(y0 + hy - 1, g.ny, g.per[1]),
-              gz = halo_coord(z0 + hz - 1, g.nz, g.per[2]);
+    const int gx = halo_coord(x0 + hx - 1, g.nx, g.per[0]);
+    const int gy = THIN ? 0 : halo_coord(y0 + hy - 1, g.ny, g.per[1]);
+    const int gz = THIN ? 0 : halo_coord(z0 + hz - 1, g.nz, g.per[2]);
     const int64_t nn = ((int64_t)gz * g.ny + gy) * g.nx + gx;
 #pragma unroll
     for (int f = 0; f < 3; ++f) sh[f * CH_CELLS + c] = psi[f * N + nn];
@@ -1361,11 +1380,11 @@ __global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
     for (int a = 0; a < M; ++a) sh[(3 + a) * CH_CELLS + c] = Yf[a * N + nn];
   }
   __syncthreads();
-  const int lx = threadIdx.x % CT_X, ly = (threadIdx.x / CT_X) % CT_Y, lz = threadIdx.x / (CT_X * CT_Y);
+  const int lx = threadIdx.x % T::X, ly = (threadIdx.x / T::X) % T::Y, lz = threadIdx.x / (T::X * T::Y);
   const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
   if (x >= g.nx || y >= g.ny || z >= g.nz) return;
   const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
-  const int c0 = ((lz + 1) * CH_Y + (ly + 1)) * CH_X + (lx + 1);
+  const int c0 = THIN ? lx + 1 : ((lz + 1) * CH_Y + (ly + 1)) * CH_X + (lx + 1);
   // x neighbours stay within the node's segment: at its ends the stencil takes the node
   // itself (the halo cell beyond the lattice's ends holds the same value)
   const XSeg xsg = x_segment(g, x);
@@ -1379,7 +1398,7 @@ __global__ __launch_bounds__(CT_THREADS) void k_corr(Geom g, Buffers b) {
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     if constexpr (I != 13) {
-      const int nc = c0 + (cz * CH_Y + cy) * CH_X + (cx < 0 ? dxm : (cx > 0 ? dxp : 0));
+      const int nc = c0 + (THIN ? 0 : (cz * CH_Y + cy) * CH_X) + (cx < 0 ? dxm : (cx > 0 ? dxp : 0));
       constexpr double w = 3.0 * wgt(I);
       if constexpr (cx != 0) X[0] -= (cx * w) * double(sh[0 * CH_CELLS + nc]);
       if constexpr (cy != 0) X[1] -= (cy * w) * double(sh[1 * CH_CELLS + nc]);
@@ -1884,7 +1903,12 @@ struct RunStep {
 template <int M, typename ST, typename RT>
 struct RunCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
-    hipLaunchKernelGGL((k_corr<M, RT, RT>), dim3((unsigned)corr_tiles(g)), dim3(CT_THREADS), 0, st, g, b);
+    if (corr_thin(g))
+      hipLaunchKernelGGL((k_corr<M, RT, RT, true>), dim3((unsigned)corr_tiles<true>(g)),
+                         dim3(CorrTile<true>::THREADS), 0, st, g, b);
+    else
+      hipLaunchKernelGGL((k_corr<M, RT, RT, false>), dim3((unsigned)corr_tiles<false>(g)),
+                         dim3(CorrTile<false>::THREADS), 0, st, g, b);
     return hipGetLastError();
   }
 };

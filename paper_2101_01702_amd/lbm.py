@@ -53,7 +53,7 @@ class LbmError(RuntimeError):
 _lib = None
 
 EXPORTS = ("lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_step",
-           "lbm_step_timed", "lbm_macros", "lbm_populations", "lbm_diagnostics", "lbm_adjoint_step",
+           "lbm_step_timed", "lbm_step_graph", "lbm_macros", "lbm_populations", "lbm_diagnostics", "lbm_adjoint_step",
            "lbm_status_sync", "lbm_last_error")
 DIAG_TOTALS = 4   # heat release rate, nodes with T >= T_iso, mass, total energy
 
@@ -74,6 +74,7 @@ def load(path: Optional[str] = None):
     lib.lbm_init_fields.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.lbm_step.argtypes = [vp, C.c_int32, vp]
     lib.lbm_step_timed.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_float)]
+    lib.lbm_step_graph.argtypes = [vp, C.c_int32, vp]
     lib.lbm_macros.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.lbm_populations.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
     lib.lbm_diagnostics.argtypes = [vp, C.c_double, vp, vp, vp]
@@ -215,6 +216,10 @@ class Solver:
 
     def step(self, n: int = 1):
         self._check(self.lib.lbm_step(self.h, int(n), self._stream()), self.h)
+
+    def step_graph(self, n: int = 1):
+        """n steps replayed from a HIP graph recorded at the first call of that n."""
+        self._check(self.lib.lbm_step_graph(self.h, int(n), self._stream()), self.h)
 
     def step_timed(self, n: int = 1) -> Dict[str, float]:
         ms = (C.c_float * NUM_KERNELS)()
