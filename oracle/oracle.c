@@ -679,6 +679,84 @@ uint32_t orc_macros(orc_sim *s, double *rho, double *u, double *T, double *P, do
   return anom;
 }
 
+/* Flame-front diagnostics of the current state (Sec. 5.2).  Displacement speed (eq. sd):
+ *   S_d = [ -sum_a H_a rho_dot_a + div(lambda grad T) - rho (sum_a C_p,a Y_a du_a) . grad T ]
+ *         / (rho C_p |grad T|),
+ * with the conductivity of eq. lambda, lambda = (1/omega1 - 1/2) P C_p (dt = 1), the
+ * mixture C_p = sum_a Y_a C_p,a, the diffusion velocities du_a of the Stefan-Maxwell
+ * solve (eq. transform1), and the isotropic lattice gradient for grad and for each term
+ * of div (reading R3; lambda dT/dx_alpha is odd under a mirror normal to alpha).  The
+ * absolute speed is S_a = S_d + u . n with n = -grad T / |grad T|.  Where grad T = 0
+ * both are set to 0.  w is the weight of a node in a mean over the surface T = T_iso:
+ * max(0, 1 - |T - T_iso| / |grad T|), a hat one cell wide across the surface, which
+ * turns the surface integral of eq. rmean into a sum over nodes.
+ * out[3][N]: S_d, S_a, w.  totals[5]: sum w, sum w S_d, sum w S_a, sum w rho S_d,
+ * sum w |x - centre| (the last over sum w is the mean radius of eq. rmean). */
+uint32_t orc_flame_speeds(orc_sim *s, double T_iso, const double *centre, double *out, double *totals) {
+  const int M = s->p.M;
+  const int64_t N = s->N;
+  uint32_t anom = 0;
+  node_t *d = (node_t *)calloc((size_t)N, sizeof(node_t));
+  double *T = (double *)malloc(sizeof(double) * (size_t)N);
+  double *gT = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *G = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *lam = (double *)malloc(sizeof(double) * (size_t)N);
+  double *cp = (double *)malloc(sizeof(double) * (size_t)N);
+  for (int64_t n = 0; n < N; ++n) {
+    anom |= node_local(s, n, s->Tstore[n], &d[n], 1);
+    T[n] = d[n].T;
+    cp[n] = 0.0;
+    for (int sp = 0; sp < M; ++sp) cp[n] += d[n].Y[sp] * (spec_Cv(s, sp, T[n]) + gas_const(s, sp));
+    lam[n] = (1.0 / s->p.omega1 - 0.5) * d[n].P * cp[n];
+  }
+  for (int64_t n = 0; n < N; ++n)
+    for (int a = 0; a < 3; ++a) gT[a * N + n] = iso_grad(s, T, n, a);
+  for (int a = 0; a < 3; ++a)
+    for (int64_t n = 0; n < N; ++n) G[a * N + n] = lam[n] * gT[a * N + n];
+  for (int k = 0; k < 5; ++k) totals[k] = 0.0;
+  for (int64_t n = 0; n < N; ++n) {
+    double div = 0.0;
+    for (int a = 0; a < 3; ++a) div += iso_grad_v(s, G + a * N, n, a, a);
+    double hrr = 0.0;
+    for (int sp = 0; sp < M; ++sp) hrr -= d[n].H_a[sp] * d[n].rdot[sp];
+    double flux = 0.0;   /* (sum_a C_p,a Y_a du_a) . grad T */
+    for (int sp = 0; sp < M; ++sp) {
+      const double c = (spec_Cv(s, sp, T[n]) + gas_const(s, sp)) * d[n].Y[sp];
+      for (int a = 0; a < 3; ++a) flux += c * d[n].du[sp][a] * gT[a * N + n];
+    }
+    const double g2 = gT[n] * gT[n] + gT[N + n] * gT[N + n] + gT[2 * N + n] * gT[2 * N + n];
+    const double mag = sqrt(g2);
+    double Sd = 0.0, Sa = 0.0, w = 0.0;
+    if (mag > 0.0) {
+      Sd = (hrr + div - d[n].rho * flux) / (d[n].rho * cp[n] * mag);
+      double un = 0.0;
+      for (int a = 0; a < 3; ++a) un -= d[n].u[a] * gT[a * N + n] / mag;
+      Sa = Sd + un;
+      w = 1.0 - fabs(T[n] - T_iso) / mag;
+      if (w < 0.0) w = 0.0;
+    }
+    out[n] = Sd;
+    out[N + n] = Sa;
+    out[2 * N + n] = w;
+    int xyz[3];
+    node_coords(s, n, &xyz[0], &xyz[1], &xyz[2]);
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) r2 += (xyz[a] - centre[a]) * (xyz[a] - centre[a]);
+    totals[0] += w;
+    totals[1] += w * Sd;
+    totals[2] += w * Sa;
+    totals[3] += w * d[n].rho * Sd;
+    totals[4] += w * sqrt(r2);
+  }
+  free(d);
+  free(T);
+  free(gT);
+  free(G);
+  free(lam);
+  free(cp);
+  return anom;
+}
+
 void orc_get_state(const orc_sim *s, double *pop, double *T) {
   if (pop) memcpy(pop, s->pop, sizeof(double) * (size_t)s->S * Q * s->N);
   if (T) memcpy(T, s->Tstore, sizeof(double) * (size_t)s->N);

@@ -55,6 +55,8 @@ void orc_destroy(orc_sim *s);
 void orc_init(orc_sim *s, const double *rho, const double *u, const double *T, const double *Y);
 uint32_t orc_step(orc_sim *s, int32_t nsteps, int32_t nthreads);
 uint32_t orc_macros(orc_sim *s, double *rho, double *u, double *T, double *P, double *Y);
+/* S_d, S_a (eq. sd) and isosurface weights of the current state; out[3][N], totals[5] */
+uint32_t orc_flame_speeds(orc_sim *s, double T_iso, const double *centre, double *out, double *totals);
 void orc_get_state(const orc_sim *s, double *pop, double *T);
 void orc_set_state(orc_sim *s, const double *pop, const double *T);
 void orc_get_post(const orc_sim *s, double *post);

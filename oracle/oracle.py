@@ -49,6 +49,8 @@ def load(path=None):
     lib.orc_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
     lib.orc_macros.restype = C.c_uint32
     lib.orc_macros.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_flame_speeds.restype = C.c_uint32
+    lib.orc_flame_speeds.argtypes = [C.c_void_p, C.c_double, _dp, _dp, _dp]
     lib.orc_get_state.argtypes = [C.c_void_p, _dp, _dp]
     lib.orc_set_state.argtypes = [C.c_void_p, _dp, _dp]
     lib.orc_get_post.argtypes = [C.c_void_p, _dp]
@@ -150,6 +152,15 @@ class OracleSim:
         rho, u, T, P, Y = np.zeros(N), np.zeros((3, N)), np.zeros(N), np.zeros(N), np.zeros((M, N))
         anom = self._lib.orc_macros(self._h, _d(rho), _d(u), _d(T), _d(P), _d(Y))
         return dict(rho=rho, u=u, T=T, P=P, Y=Y, anomaly=int(anom))
+
+    def flame_speeds(self, T_iso, centre=(0.0, 0.0, 0.0)):
+        """S_d, S_a (eq. sd) and isosurface weights w per node of the current state, and
+        the sums [w, w S_d, w S_a, w rho S_d, w |x - centre|]."""
+        out = np.zeros((3, self.N))
+        tot = np.zeros(5)
+        c = _c64(np.asarray(centre, np.float64))
+        anom = self._lib.orc_flame_speeds(self._h, float(T_iso), _d(c), _d(out), _d(tot))
+        return dict(Sd=out[0], Sa=out[1], w=out[2], totals=tot, anomaly=int(anom))
 
     def state(self):
         pop = np.zeros((self.S, 27, self.N))

@@ -1,0 +1,105 @@
+"""Pins of the oracle's flame-front diagnostics (Sec. 5.2, eq. sd): displacement speed
+S_d, absolute speed S_a and the isosurface weights of the mean of eq. rmean.
+
+The displacement speed is the speed of a temperature isosurface relative to the fluid,
+S_d = (DT/Dt) / |grad T|, and eq. sd is the low-Mach energy balance for DT/Dt.  The
+oracle's own dynamics give DT/Dt and dT/dt by central differences over two steps; the
+pressure work (Dp/Dt) / (rho C_p), which the low-Mach form leaves out, is measured from
+the same run and added.  Three cases make each term of eq. sd dominant in turn:
+conduction (a temperature step), enthalpy diffusion (a composition step across it, the
+diffusion term larger than DT/Dt itself), and heat release (a burning flame)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2101_01702_amd import workloads as W
+
+R_U = 8.314462618
+
+
+def _central(f):
+    return 0.5 * (np.concatenate([f[1:], f[-1:]]) - np.concatenate([f[:1], f[:-1]]))
+
+
+def _run(prob, settle):
+    sim = orc.OracleSim(prob).init()
+    sim.step(settle, 8)
+    m0 = sim.macros()
+    sim.step(1, 8)
+    m1 = sim.macros()
+    fs = sim.flame_speeds(T_iso=float(np.median(m1["T"])))
+    sim.step(1, 8)
+    m2 = sim.macros()
+    assert m0["anomaly"] == m1["anomaly"] == m2["anomaly"] == fs["anomaly"] == 0
+    T = m1["T"]
+    g = _central(T)                       # x-only field: the isotropic gradient is central
+    u = m1["u"][0]
+    dTdt = 0.5 * (m2["T"] - m0["T"])
+    DpDt = 0.5 * (m2["P"] - m0["P"]) + u * _central(m1["P"])
+    Ra = prob.kappa * R_U / (prob.mech.molar_mass * 1e-3)
+    n7 = prob.mech.nasa7
+    cpa = np.array([Ra[a] * sum(n7[a, k] * T ** k for k in range(5)) for a in range(prob.M)])
+    pw = DpDt / (m1["rho"] * (m1["Y"] * cpa).sum(axis=0))
+    return fs, g, u, dTdt, pw
+
+
+def _composition_step(prob, phi_hot):
+    x = np.arange(prob.nx, dtype=np.float64)
+    s = W.tanh_profile(x - (prob.nx / 2 - 0.5), 6.0)
+    X = W.premixed_h2air_X(prob.mech, 1.0)[:, None] * (1 - s) + W.premixed_h2air_X(prob.mech, phi_hot)[:, None] * s
+    prob.Y = W.mole_to_mass(X, prob.mech.molar_mass)
+    prob.rho = W.lattice_density(np.full(prob.nx, W.P_ATM), prob.T, W.mean_molar_mass(X, prob.mech.molar_mass),
+                                 prob.rho_ref)
+    return prob
+
+
+CASES = {
+    "conduction": (lambda: W.flame1d(nx=128, hot_cells=64, T_hot=420.0, edge=6.0), 300, 0.3, 0.06),
+    "enthalpy diffusion": (lambda: _composition_step(W.flame1d(nx=128, hot_cells=64, T_hot=420.0, edge=6.0), 2.5),
+                           300, 0.3, 0.06),
+    "heat release": (lambda: W.flame1d(nx=512, hot_cells=64), 1500, 0.2, 0.12),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_displacement_speed_moves_the_isotherms(case):
+    make, settle, frac, tol = CASES[case]
+    fs, g, u, dTdt, pw = _run(make(), settle)
+    mag = np.abs(g)
+    sel = mag > frac * mag.max()
+    DTDt = dTdt + u * g
+    scale = np.abs(DTDt[sel]).max()
+    err_d = np.abs(fs["Sd"] * mag + pw - DTDt)[sel].max() / scale
+    err_a = np.abs(fs["Sa"] * mag + pw - dTdt)[sel].max() / np.abs(dTdt[sel]).max()
+    print(f"[{case}] S_d {err_d:.3f}, S_a {err_a:.3f} over {sel.sum()} nodes")
+    assert err_d <= tol and err_a <= tol
+
+
+def test_isosurface_weights_measure_area_and_radius():
+    """A spherical temperature field: the weights sum to the area 4 pi R^2 of the
+    isosurface and their radius-weighted mean is R; a linear planar profile gives
+    exactly one unit of area per unit of cross-section."""
+    R0, n, edge = 10.0, 44, 8.0
+    prob = W.sphere3d(shape=(n, n, n), radius=R0, edge=edge, T_ig=1500.0, storage=W.STORE_F64)
+    c = np.array([(n - 1) / 2] * 3) + np.array([0.13, -0.21, 0.34])
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2).reshape(-1)
+    prob.T = 300.0 + 1200.0 * W.tanh_profile(R0 - r, edge)
+    prob.rho = W.lattice_density(np.full(prob.N, W.P_ATM), prob.T,
+                                 np.full(prob.N, W.mean_molar_mass(W.premixed_h2air_X(prob.mech, 0.8),
+                                                                    prob.mech.molar_mass)), prob.rho_ref)
+    sim = orc.OracleSim(prob).init()
+    fs = sim.flame_speeds(T_iso=900.0, centre=c)
+    tot = fs["totals"]
+    print(f"area {tot[0] / (4 * np.pi * R0 ** 2) - 1:+.4f}, radius {tot[4] / tot[0] - R0:+.4f}")
+    assert abs(tot[0] / (4 * np.pi * R0 ** 2) - 1) < 0.03, tot[0]
+    assert abs(tot[4] / tot[0] - R0) < 0.1, tot[4] / tot[0]
+    np.testing.assert_allclose(tot[0], fs["w"].sum(), rtol=1e-12)
+    # a linear profile along x crosses T_iso between two nodes whose weights sum to 1,
+    # the area of the 1 x 1 cross-section (the recovered temperature is the given one to
+    # the Newton tolerance)
+    plan = W.flame1d(nx=24, hot_cells=12, T_hot=400.0, edge=6.0)
+    plan.T = 300.0 + 5.0 * np.arange(24.0)
+    simp = orc.OracleSim(plan).init()
+    fp = simp.flame_speeds(T_iso=352.5)
+    np.testing.assert_allclose(fp["totals"][0], 1.0, rtol=1e-9)
