@@ -205,6 +205,29 @@ lbm_status lbm_populations(lbm_handle h, const int64_t *d_nodes, int64_t n_nodes
 #define LBM_DIAG_TOTALS 4
 lbm_status lbm_diagnostics(lbm_handle h, double T_iso, double *d_hrr, double *d_totals, void *stream);
 
+/* Flame-front speeds of the current state (Sec. 5.2, eq. sd), all in FP64:
+ *   S_d = [ -sum_a H_a rho_dot_a + div(lambda grad T) - rho (sum_a C_p,a Y_a du_a) . grad T ]
+ *         / (rho C_p |grad T|)
+ * with lambda = (1/omega1 - 1/2) P C_p (eq. lambda, dt = 1), C_p = sum_a Y_a C_p,a, the
+ * diffusion velocities du_a of the Stefan-Maxwell system (eq. transform1) and the
+ * isotropic lattice gradient for grad and for each term of div; the absolute speed
+ * S_a = S_d + u . n with n = -grad T / |grad T| (both 0 where grad T = 0); and the
+ * weight w = max(0, 1 - |T - T_iso| / |grad T|) of each node in a mean over the surface
+ * T = T_iso (a hat one cell wide across the surface, so that sums over nodes stand for
+ * surface integrals as in eq. rmean).  The density-weighted speed of the paper is
+ * rho S_d / rho_u.
+ *   d_work    device scratch of LBM_FLAME_WORK x N doubles (overwritten)
+ *   d_out     [3][N] device: S_d, S_a, w (may be NULL)
+ *   d_totals  [LBM_FLAME_TOTALS] device: sum w (isosurface area), sum w S_d, sum w S_a,
+ *             sum w rho S_d, sum w |x - centre| (over sum w: the mean radius of eq.
+ *             rmean), in a fixed order (may be NULL)
+ *   centre    host [3] lattice coordinates (may be NULL: the origin)
+ * Uses the workspace's partial-sum area: calls that overlap on one handle race. */
+#define LBM_FLAME_WORK 17
+#define LBM_FLAME_TOTALS 5
+lbm_status lbm_flame_speeds(lbm_handle h, double T_iso, const double *centre, double *d_work,
+                            double *d_out, double *d_totals, void *stream);
+
 /* Discrete adjoint of one step.  Not provided by this build: returns
  * LBM_ERR_UNSUPPORTED. */
 lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, double *d_grad_params,

@@ -81,7 +81,7 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.psi = take(3 * N * ct);
   L.corr_bytes = 6 * (size_t)g.NPAD * ct;   // deferred corrections, padded planes
   L.corr = take(L.corr_bytes);
-  L.diag = take((size_t)LBM_DIAG_TOTALS * ((N + 127) / 128) * 8);   // diagnostics partial sums
+  L.diag = take((size_t)8 * ((N + 127) / 128) * 8);   // partial sums of the diagnostics (up to 8 totals)
   L.total = off;
   return L;
 }
@@ -625,6 +625,24 @@ lbm_status lbm_diagnostics(lbm_handle h, double T_iso, double *d_hrr, double *d_
   hipError_t e = launch_diag(h->g, h->b, h->kc, h->d.storage, h->cur, T_iso, d_hrr, d_totals,
                              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(h, e, "diagnostics");
+  return LBM_OK;
+}
+
+lbm_status lbm_flame_speeds(lbm_handle h, double T_iso, const double *centre, double *d_work, double *d_out,
+                            double *d_totals, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!std::isfinite(T_iso)) return arg_fail(h, "T_iso must be finite");
+  if (!d_work) return arg_fail(h, "d_work must not be NULL");
+  if (!d_out && !d_totals) return LBM_OK;
+  double c[3] = {0.0, 0.0, 0.0};
+  if (centre)
+    for (int k = 0; k < 3; ++k) {
+      if (!std::isfinite(centre[k])) return arg_fail(h, "centre must be finite");
+      c[k] = centre[k];
+    }
+  hipError_t e = launch_flame(h->g, h->b, h->kc, h->d.storage, h->cur, T_iso, c, d_work, d_out, d_totals,
+                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "flame speeds");
   return LBM_OK;
 }
 

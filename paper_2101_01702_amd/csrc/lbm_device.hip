@@ -1865,6 +1865,212 @@ __global__ __launch_bounds__(DIAG_SUM_BLOCK) void k_diag_sum(const double *part,
   if (threadIdx.x == 0) totals[k] = red[0];
 }
 
+// ---- flame-front speeds (Sec. 5.2, eq. sd) --------------------------------------------
+// Work fields [FS_WORK][N] of the caller: node-local values, then the gradients.
+enum { FS_T, FS_LAM, FS_HRR, FS_RHOCP, FS_V, FS_U = FS_V + 3, FS_RHO = FS_U + 3, FS_GT, FS_G = FS_GT + 3,
+       FS_WORK = FS_G + 3 };
+static_assert(FS_WORK == LBM_FLAME_WORK, "work fields of lbm_flame_speeds");
+
+// Node-local part: T (Newton), heat release -sum_a H_a rho_dot_a, C_p = sum_a Y_a C_p,a,
+// the conductivity lambda = (1/omega1 - 1/2) P C_p (eq. lambda, dt = 1), and the
+// enthalpy-diffusion vector V = sum_a C_p,a Y_a du_a with du_a from the Stefan-Maxwell
+// system (1 + 1/(2 tau_a)) du_a - 1/2 sum_b K_ab Y_b du_b = u_a - u (eqs. tauab,
+// transform1), solved by elimination without pivoting (strictly diagonally dominant).
+template <int M, typename ST, typename RT>
+__global__ __launch_bounds__(128) void k_fs_local(Geom g, Buffers b, CollideConsts kc, int cur, double *work) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  using Side = typename Fmt<ST>::Side;
+  const Corr<Side> cr{static_cast<const Side *>(b.corr), static_cast<const Side *>(b.corr) + 3 * g.NPAD, g.NPAD};
+  Macro<M> m;
+  node_moments<M, ST>(g, static_cast<const ST *>(b.pop[cur]), cr, kc, x, y, z, m);
+  const Tables &tb = *b.tab;
+  double T;
+  node_temperature<M>(tb, m, b.T[n], T);
+  double rdot[M];
+  node_rates<M>(tb, m.rs, T, rdot);
+  const double invT = 1.0 / T, inv_rho = 1.0 / m.rho;
+  double Y[M], cpa[M], za[M];
+  double hrr = 0.0, cp = 0.0, zeta = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    Y[a] = m.rs[a] * inv_rho;
+    const double *c = tb.nasa[a];
+    za[a] = tb.Ra[a] * T;
+    cpa[a] = tb.Ra[a] * (c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4]))));
+    hrr -= za[a] * h_RT(c, T, invT) * rdot[a];
+    cp += Y[a] * cpa[a];
+    zeta += Y[a] * za[a];
+  }
+  double A[M][M], r[M][3];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double it = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const double K = (a == c) ? 0.0 : za[a] * za[c] * tb.invD[a][c] / zeta;
+      A[a][c] = -0.5 * K * Y[c];
+      it += Y[c] * K;
+    }
+    A[a][a] = 1.0 + 0.5 * it;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) r[a][d] = m.du0[a][d];
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+#pragma unroll
+    for (int q = k + 1; q < M; ++q) {
+      const double l = A[q][k] / A[k][k];
+#pragma unroll
+      for (int c = k; c < M; ++c) A[q][c] -= l * A[k][c];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) r[q][d] -= l * r[k][d];
+    }
+  double V[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = M - 1; q >= 0; --q)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double v = r[q][d];
+#pragma unroll
+      for (int c = q + 1; c < M; ++c) v -= A[q][c] * r[c][d];
+      r[q][d] = v / A[q][q];
+      V[d] += cpa[q] * Y[q] * r[q][d];
+    }
+  const int64_t N = g.N;
+  work[FS_T * N + n] = T;
+  work[FS_LAM * N + n] = (1.0 / tb.omega1 - 0.5) * m.rho * zeta * cp;
+  work[FS_HRR * N + n] = hrr;
+  work[FS_RHOCP * N + n] = m.rho * cp;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    work[(FS_V + d) * N + n] = V[d];
+    work[(FS_U + d) * N + n] = m.u[d];
+  }
+  work[FS_RHO * N + n] = m.rho;
+}
+
+// neighbour coordinates of the isotropic gradient (wrapped on periodic axes, clamped at
+// open and symmetry faces and at the ends of a segment), and the sign of a component
+// normal to a symmetry face across it
+struct Nbr {
+  int xs[3], ys[3], zs[3];
+  double sg[3][3];
+};
+__device__ __forceinline__ Nbr neighbours(const Geom &g, int x, int y, int z) {
+  const XSeg xsg = x_segment(g, x);
+  Nbr r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.xs[k] = g.per[0] ? nb_coord(x, k - 1, g.nx, true) : min(max(x + k - 1, xsg.x0), xsg.x1);
+    r.ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
+    r.zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
+  }
+  const int xyz[3] = {x, y, z}, lo3[3] = {xsg.x0, 0, 0}, hi3[3] = {xsg.x1, g.ny - 1, g.nz - 1};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.sg[a][0] = (xyz[a] == lo3[a] && g.bc[2 * a] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+    r.sg[a][1] = 1.0;
+    r.sg[a][2] = (xyz[a] == hi3[a] && g.bc[2 * a + 1] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+  }
+  return r;
+}
+
+// grad T, and G = lambda grad T
+__global__ __launch_bounds__(256) void k_fs_grad(Geom g, double *work) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.N) return;
+  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  const Nbr nb = neighbours(g, x, y, z);
+  const int64_t N = g.N;
+  const double *T = work + FS_T * N;
+  double gr[3] = {0.0, 0.0, 0.0};
+  static_for<27>([&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+    if constexpr (I != 13) {
+      const int64_t nn = ((int64_t)nb.zs[cz + 1] * g.ny + nb.ys[cy + 1]) * g.nx + nb.xs[cx + 1];
+      constexpr double w = 3.0 * wgt(I);
+      const double v = T[nn];
+      if constexpr (cx != 0) gr[0] += (cx * w) * v;
+      if constexpr (cy != 0) gr[1] += (cy * w) * v;
+      if constexpr (cz != 0) gr[2] += (cz * w) * v;
+    }
+  });
+  const double lam = work[FS_LAM * N + n];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    work[(FS_GT + d) * N + n] = gr[d];
+    work[(FS_G + d) * N + n] = lam * gr[d];
+  }
+}
+
+// S_d (eq. sd), S_a = S_d + u.n, isosurface weight w, and per-workgroup partial sums
+// [w, w S_d, w S_a, w rho S_d, w |x - centre|] (fixed tree, added by k_diag_sum)
+__global__ __launch_bounds__(DIAG_BLOCK) void k_fs_final(Geom g, const double *work, double T_iso, double cx0,
+                                                         double cy0, double cz0, double *out, double *part) {
+  __shared__ double red[LBM_FLAME_TOTALS][DIAG_BLOCK];
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[LBM_FLAME_TOTALS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (n < g.N) {
+    const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+    const Nbr nb = neighbours(g, x, y, z);
+    const int64_t N = g.N;
+    const double *G = work + FS_G * N;
+    double div = 0.0;
+    static_for<27>([&](auto Ic) {
+      constexpr int I = decltype(Ic)::value;
+      constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+      if constexpr (I != 13) {
+        const int64_t nn = ((int64_t)nb.zs[cz + 1] * g.ny + nb.ys[cy + 1]) * g.nx + nb.xs[cx + 1];
+        constexpr double w = 3.0 * wgt(I);
+        if constexpr (cx != 0) div += (cx * w) * (nb.sg[0][cx + 1] * G[nn]);
+        if constexpr (cy != 0) div += (cy * w) * (nb.sg[1][cy + 1] * G[N + nn]);
+        if constexpr (cz != 0) div += (cz * w) * (nb.sg[2][cz + 1] * G[2 * N + nn]);
+      }
+    });
+    double gt[3], flux = 0.0, g2 = 0.0, ug = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      gt[d] = work[(FS_GT + d) * N + n];
+      flux += work[(FS_V + d) * N + n] * gt[d];
+      g2 += gt[d] * gt[d];
+      ug += work[(FS_U + d) * N + n] * gt[d];
+    }
+    const double mag = sqrt(g2), rho = work[FS_RHO * N + n], T = work[FS_T * N + n];
+    double Sd = 0.0, Sa = 0.0, wt = 0.0;
+    if (mag > 0.0) {
+      Sd = (work[FS_HRR * N + n] + div - rho * flux) / (work[FS_RHOCP * N + n] * mag);
+      Sa = Sd - ug / mag;
+      wt = fmax(0.0, 1.0 - fabs(T - T_iso) / mag);
+    }
+    if (out) {
+      out[n] = Sd;
+      out[N + n] = Sa;
+      out[2 * N + n] = wt;
+    }
+    const double dx = x - cx0, dy = y - cy0, dz = z - cz0;
+    v[0] = wt;
+    v[1] = wt * Sd;
+    v[2] = wt * Sa;
+    v[3] = wt * rho * Sd;
+    v[4] = wt * sqrt(dx * dx + dy * dy + dz * dz);
+  }
+#pragma unroll
+  for (int k = 0; k < LBM_FLAME_TOTALS; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = DIAG_BLOCK / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int k = 0; k < LBM_FLAME_TOTALS; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < LBM_FLAME_TOTALS; ++k) part[(int64_t)k * gridDim.x + blockIdx.x] = red[k][0];
+}
+
 __global__ void k_zero(uint32_t *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -1955,6 +2161,28 @@ inline bool any_symmetry(const Geom &g) {
   return false;
 }
 template <int M, typename ST, typename RT>
+struct RunFlame {
+  static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double T_iso,
+                        const double *centre, double *work, double *out, double *totals, hipStream_t st) {
+    hipLaunchKernelGGL((k_fs_local<M, ST, RT>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, kc, cur, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fs_grad, dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, work);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nb = blocks_for(g.N, DIAG_BLOCK);
+    hipLaunchKernelGGL(k_fs_final, dim3(nb), dim3(DIAG_BLOCK), 0, st, g, (const double *)work, T_iso, centre[0],
+                       centre[1], centre[2], out, b.diag);
+    e = hipGetLastError();
+    if (e == hipSuccess && totals) {
+      hipLaunchKernelGGL(k_diag_sum, dim3(LBM_FLAME_TOTALS), dim3(DIAG_SUM_BLOCK), 0, st, b.diag, (int64_t)nb,
+                         totals);
+      e = hipGetLastError();
+    }
+    return e;
+  }
+};
+template <int M, typename ST, typename RT>
 struct RunGhostCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
     if (!any_symmetry(g)) return hipSuccess;
@@ -2023,6 +2251,11 @@ hipError_t launch_ghost(const Geom &g, const Buffers &b, const CollideConsts &kc
 hipError_t launch_diag(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
                        double *hrr, double *totals, hipStream_t st) {
   return dispatch<RunDiag>(g.M, store, g, b, kc, cur, T_iso, hrr, totals, st);
+}
+
+hipError_t launch_flame(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
+                        const double *centre, double *work, double *out, double *totals, hipStream_t st) {
+  return dispatch<RunFlame>(g.M, store, g, b, kc, cur, T_iso, centre, work, out, totals, st);
 }
 
 hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,

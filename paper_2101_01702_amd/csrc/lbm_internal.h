@@ -91,7 +91,7 @@ struct Buffers {
   void *psi;                  // [3][N]
   void *corr;                 // [6][NPAD]: X (3), then the energy-flux correction (3); zero in ghost cells
   const CollideConsts *kc;    // device copy of the collision constants
-  double *diag;               // [LBM_DIAG_TOTALS][ceil(N / 128)] partial sums of the diagnostics
+  double *diag;               // [8][ceil(N / 128)] partial sums of the diagnostics
 };
 
 // launchers (lbm_device.hip)
@@ -109,6 +109,8 @@ hipError_t launch_export(const Geom &g, const Buffers &b, const CollideConsts &k
                          const int64_t *nodes, int64_t n_nodes, double *out, double *T_out, hipStream_t st);
 hipError_t launch_diag(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
                        double *hrr, double *totals, hipStream_t st);
+hipError_t launch_flame(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
+                        const double *centre, double *work, double *out, double *totals, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st);
 
 }  // namespace lbm
