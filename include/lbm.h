@@ -112,6 +112,11 @@ enum {
  *                   populations or stencil values.  Node indices, fields and
  *                   populations keep the one-lattice layout of nx x ny x nz.
  *   segment_lengths [n_segments] host array, read when n_segments >= 2
+ *   diff_T_ref, diff_T_exp   temperature dependence of the diffusivities: with
+ *                   diff_T_exp != 0 (|exp| <= 4, diff_T_ref > 0 in K) every binary
+ *                   diffusivity is D_ab (T / diff_T_ref)^diff_T_exp at the node's
+ *                   temperature (a power law standing in for the temperature-dependent
+ *                   transport data of Sec. 3); 0: the constants diff_ab
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -133,6 +138,7 @@ typedef struct {
   int32_t n_segments;
   int32_t reserved2;
   const int32_t *segment_lengths;
+  double diff_T_ref, diff_T_exp;
 } lbm_desc;
 
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost

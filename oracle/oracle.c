@@ -213,13 +213,22 @@ static void production_rates(const orc_sim *s, const double *rho_a, double T, do
 }
 
 /* ---- Stefan-Maxwell relaxation (eqs. fStar, tauab, transform1) ---------------------- */
+/* binary diffusivity at temperature T: the given constant, or with a temperature
+ * exponent the power law D_ab (T / T_ref)^n (a stand-in for the temperature-dependent
+ * transport data of Sec. 3) */
+static double diffusivity(const orc_sim *s, int a, int b, double T) {
+  if (s->p.diff_T_exp == 0.0) return s->diff[a][b];
+  return s->diff[a][b] * pow(T / s->p.diff_T_ref, s->p.diff_T_exp);
+}
+
 /* K_ab = 1/tau_ab with tau_ab = (m_a m_b / (m R_U T)) D_ab, written with lattice
  * R_a T: 1/tau_ab = (R_a T)(R_b T) / ((R T) D_ab). */
-static void relaxation(const orc_sim *s, const double *Y, const double *zeta_a, double zeta,
+static void relaxation(const orc_sim *s, const double *Y, const double *zeta_a, double zeta, double T,
                        double K[MAXM][MAXM], double *inv_tau, double *beta) {
   const int M = s->p.M;
   for (int a = 0; a < M; ++a)
-    for (int b = 0; b < M; ++b) K[a][b] = (a == b) ? 0.0 : zeta_a[a] * zeta_a[b] / (zeta * s->diff[a][b]);
+    for (int b = 0; b < M; ++b)
+      K[a][b] = (a == b) ? 0.0 : zeta_a[a] * zeta_a[b] / (zeta * diffusivity(s, a, b, T));
   for (int a = 0; a < M; ++a) {
     inv_tau[a] = 0.0;
     for (int b = 0; b < M; ++b)
@@ -373,7 +382,7 @@ static uint32_t node_local(const orc_sim *s, int64_t n, double T_start, node_t *
   production_rates(s, d->rho_a, d->T, d->rdot);
 
   /* O4: relaxation times and diffusion velocities */
-  relaxation(s, d->Y, d->zeta_a, d->zeta, d->K, d->inv_tau, d->beta);
+  relaxation(s, d->Y, d->zeta_a, d->zeta, d->T, d->K, d->inv_tau, d->beta);
   double rhs[MAXM][3];
   for (int sp = 0; sp < M; ++sp)
     for (int a = 0; a < 3; ++a) rhs[sp][a] = d->u_a[sp][a] - d->u[a];
@@ -542,6 +551,7 @@ orc_sim *orc_create(const orc_problem *p) {
     if ((lo == ORC_BC_PERIODIC) != (hi == ORC_BC_PERIODIC)) return NULL;
   }
   if (p->omega == p->omega1) return NULL;   /* the printed q^diff and q^corr prefactors are singular */
+  if (p->diff_T_exp != 0.0 && !(p->diff_T_ref > 0.0)) return NULL;
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   s->p = *p;
   const int M = p->M;
@@ -847,7 +857,7 @@ void orc_diffusion(const orc_sim *s, const double *Y, double T, const double *rh
     inv_m += Y[a] / s->molar_mass[a];
   }
   const double zeta = s->p.kappa * R_UNIV * T * inv_m / 1e-3;
-  relaxation(s, Y, zeta_a, zeta, K, inv_tau, beta);
+  relaxation(s, Y, zeta_a, zeta, T, K, inv_tau, beta);
   for (int a = 0; a < M; ++a)
     for (int c = 0; c < 3; ++c) r[a][c] = rhs[a * 3 + c];
   diffusion_velocities(M, K, inv_tau, Y, r, d);

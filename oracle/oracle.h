@@ -45,6 +45,8 @@ typedef struct {
   double dt_phys;              /* s per step */
   double rho_ref;              /* g/cm^3 per lattice density unit */
   double p0;                   /* Pa, standard pressure of the thermo data */
+  double diff_T_ref;           /* K; with diff_T_exp != 0: D_ab(T) = D_ab (T / diff_T_ref)^diff_T_exp */
+  double diff_T_exp;
 } orc_problem;
 
 typedef struct orc_sim orc_sim;

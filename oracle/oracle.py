@@ -26,6 +26,7 @@ class _Problem(C.Structure):
         ("omega", C.c_double), ("omega1", C.c_double),
         ("kappa", C.c_double), ("dt_phys", C.c_double), ("rho_ref", C.c_double),
         ("p0", C.c_double),
+        ("diff_T_ref", C.c_double), ("diff_T_exp", C.c_double),
     ]
 
 
@@ -122,6 +123,8 @@ class OracleSim:
         p.reversible = keep["reversible"].ctypes.data_as(_up)
         p.omega, p.omega1 = prob.omega, prob.omega1
         p.kappa, p.dt_phys, p.rho_ref, p.p0 = prob.kappa, prob.dt_phys, prob.rho_ref, prob.p0
+        p.diff_T_ref = getattr(prob, "diff_T_ref", 0.0)
+        p.diff_T_exp = getattr(prob, "diff_T_exp", 0.0)
         self._p = p
         h = lib.orc_create(C.byref(p))
         if not h:

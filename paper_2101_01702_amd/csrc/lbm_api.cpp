@@ -166,6 +166,10 @@ bool validate(const lbm_desc *d, std::string *err) {
     }
     if (std::fabs(ys - 1.0) > 1e-9) return fail(err, "ref_state: mass fractions sum to %.17g, not 1", ys);
   }
+  if (!std::isfinite(d->diff_T_exp) || std::fabs(d->diff_T_exp) > 4.0)
+    return fail(err, "diff_T_exp = %g must be finite and within [-4, 4]", d->diff_T_exp);
+  if (d->diff_T_exp != 0.0 && (!(d->diff_T_ref > 0.0) || !std::isfinite(d->diff_T_ref)))
+    return fail(err, "diff_T_ref must be > 0 when diff_T_exp != 0");
   if (d->n_segments < 0) return fail(err, "n_segments = %d must be >= 0", d->n_segments);
   if (d->n_segments > 1) {
     if (d->bc[0] == LBM_BC_PERIODIC) return fail(err, "segments along x need non-periodic x faces");
@@ -254,6 +258,8 @@ void build_tables(const lbm_desc &d, Tables &t) {
   t.ln_c0_const = std::log(d.p0 * 1e-6 / R_UNIV);
   t.omega = d.omega;
   t.omega1 = d.omega1;
+  t.dexp = d.diff_T_exp;
+  t.ln_dTref = d.diff_T_exp != 0.0 ? std::log(d.diff_T_ref) : 0.0;
 }
 
 // Reference populations of the deviation formats: the equilibria (eqs. feq, gieq) of

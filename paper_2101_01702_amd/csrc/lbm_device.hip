@@ -285,6 +285,13 @@ __device__ __forceinline__ void static_for(F &&f) {
   static_for_impl(std::make_integer_sequence<int, N>{}, f);
 }
 
+// factor of the diffusivities at temperature T, 1 / (T / T_ref)^n = exp(n (ln T_ref - ln T)):
+// 1/D_ab(T) = s 1/D_ab (exactly 1 for constant diffusivities)
+template <typename TB>
+__device__ __forceinline__ double inv_diff_scale(const TB &tb, double T) {
+  return tb.dexp != 0.0 ? exp(tb.dexp * (tb.ln_dTref - log(T))) : 1.0;
+}
+
 // ---- thermodynamics (eqs. specHa, Umix; NASA-7) -------------------------------------
 template <typename P>
 __device__ __forceinline__ double h_RT(P a, double T, double invT) {
@@ -874,7 +881,7 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 
   {
     constexpr int NP = M * (M - 1) / 2;
     double Bl[NP], Ad[M], Yb[M], zl[M];
-    const double inv_zeta = 1.0 / zeta;
+    const double inv_zeta = inv_diff_scale(tb, T) / zeta;   // with the T factor of 1/D_ab
 #pragma unroll
     for (int a = 0; a < M; ++a) {
       Yb[a] = sh.r(SW::RS + a) * inv_rho;
@@ -940,7 +947,7 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 
   const double om1 = tb.omega1;
   const bool open_any = tb.open_any != 0;
   {
-    const double inv_zeta = 1.0 / zeta;
+    const double inv_zeta = inv_diff_scale(tb, T) / zeta;   // with the T factor of 1/D_ab (F term)
     double hyd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -1904,12 +1911,13 @@ __global__ __launch_bounds__(128) void k_fs_local(Geom g, Buffers b, CollideCons
     zeta += Y[a] * za[a];
   }
   double A[M][M], r[M][3];
+  const double sD = inv_diff_scale(tb, T) / zeta;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
     double it = 0.0;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      const double K = (a == c) ? 0.0 : za[a] * za[c] * tb.invD[a][c] / zeta;
+      const double K = (a == c) ? 0.0 : za[a] * za[c] * tb.invD[a][c] * sD;
       A[a][c] = -0.5 * K * Y[c];
       it += Y[c] * K;
     }

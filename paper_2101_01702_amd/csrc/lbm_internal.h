@@ -38,6 +38,7 @@ struct Tables {
   int32_t prod_idx[MAXR][MAXORD];
   double ln_c0_const;         // ln(p0 * 1e-6 / R_U): ln c0(T) = ln_c0_const - ln T (mol/cm^3)
   double omega, omega1;
+  double dexp, ln_dTref;      // D_ab(T) = D_ab exp(dexp (ln T - ln_dTref)); dexp = 0: constant
 };
 
 // Constants of the collision.  The init, ghost and output kernels take them as a kernel

@@ -91,6 +91,9 @@ class Problem:
     ref_state: Optional[np.ndarray] = None
     # lengths along x of independent lattices side by side (a batch); None: one lattice
     segments: Optional[Tuple[int, ...]] = None
+    # temperature-dependent diffusivities D_ab (T / diff_T_ref)^diff_T_exp (0: constant)
+    diff_T_ref: float = 0.0
+    diff_T_exp: float = 0.0
 
     @property
     def N(self) -> int:

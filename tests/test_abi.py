@@ -246,3 +246,13 @@ def test_split_batch_keeps_every_node():
         assert np.array_equal(p.T, prob.T[idx]) and np.array_equal(p.Y, prob.Y[:, idx])
         assert np.array_equal(p.rho, prob.rho[idx])
     assert np.array_equal(np.sort(np.concatenate([W.batch_nodes(prob, k) for k in range(5)])), np.arange(prob.N))
+
+
+def test_diffusivity_exponent_validation(lib):
+    prob = W.config1()
+    for ref, ex, ok, needle in ((500.0, 1.5, True, ""), (0.0, 0.0, True, ""), (0.0, 1.0, False, "diff_T_ref"),
+                                (500.0, 4.5, False, "diff_T_exp"), (500.0, float("nan"), False, "diff_T_exp")):
+        prob.diff_T_ref, prob.diff_T_exp = ref, ex
+        d, keep = lbm.make_desc(prob)
+        code, _, msg = _ws(lib, d)
+        assert (code == 0) == ok and needle in msg, (ref, ex, msg)

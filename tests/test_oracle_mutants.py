@@ -34,7 +34,8 @@ MUTANTS = {
     "transform_sign": ("-0.5 * K[a][b] * Y[b];", "0.5 * K[a][b] * Y[b];"),
     "stream_direction": ("int v = xyz[a] - CI(i, a);", "int v = xyz[a] + CI(i, a);"),
     "iso_grad_scale": ("return acc / THETA;", "return acc;"),
-    "tau_ab_mixture_mass": ("zeta_a[a] * zeta_a[b] / (zeta * s->diff[a][b])", "zeta_a[a] * zeta_a[b] / (s->diff[a][b])"),
+    "tau_ab_mixture_mass": ("zeta_a[a] * zeta_a[b] / (zeta * diffusivity(s, a, b, T))",
+                            "zeta_a[a] * zeta_a[b] / (diffusivity(s, a, b, T))"),
     "ghost_velocity": ("for (int a = 0; a < 3; ++a) ug[a] = zero_u ? 0.0 : d->u[a];",
                        "for (int a = 0; a < 3; ++a) ug[a] = 0.0;"),
     "slaved_momentum": ("d->j_a[M - 1][a] = d->j[a] - j_sum[a];", "d->j_a[M - 1][a] = d->j[a] + j_sum[a];"),

@@ -469,3 +469,28 @@ def test_flame_response_to_a_perturbation_is_bounded():
         worst.append(max(e.values()) / eps)
     assert max(worst) <= 10.0, worst
     assert abs(worst[0] - worst[1]) <= 0.05 * worst[1], worst
+
+
+@pytest.mark.parametrize("T,exp", [(1000.0, 1.5), (700.0, -0.5)])
+def test_fickian_decay_with_temperature_dependent_diffusivity(T, exp):
+    """D_ab(T) = D_ab (T / T_ref)^n: the binary decay rate follows the diffusivity at the
+    mixture's temperature, D_ref (T / T_ref)^n k^2 (T_ref = 500 K)."""
+    L = 64
+    mech = two_species()
+    x = np.arange(L)
+    eps = 1e-3
+    X1 = 0.5 + eps * np.sin(2 * math.pi * x / L)
+    D_eff = 0.04
+    D_ref = D_eff / (T / 500.0) ** exp
+    prob = lattice_problem(mech, L, X=np.stack([X1, 1 - X1]), D=D_ref, T=T)
+    prob.diff_T_ref, prob.diff_T_exp = 500.0, exp
+    sim = orc.OracleSim(prob).init()
+    k = 2 * math.pi / L
+    amps, ts = [], []
+    for n in range(6):
+        mac = sim.macros()
+        amps.append(fourier_amp(mac["Y"][0] - mac["Y"][0].mean(), L))
+        ts.append(n * 300)
+        sim.step(300)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    assert rate == pytest.approx(D_eff * k * k, rel=0.01)
