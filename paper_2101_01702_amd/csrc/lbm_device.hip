@@ -1342,7 +1342,7 @@ struct CorrTile {
 };
 template <>
 struct CorrTile<true> {
-  static constexpr int X = 256, Y = 1, Z = 1, HX = X + 2, HY = 1, HZ = 1;
+  static constexpr int X = 256, Y = 1, Z = 1, HX = X + 2, HY = 1;
   static constexpr int THREADS = X, CELLS = HX;
 };
 

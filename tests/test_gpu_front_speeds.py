@@ -102,3 +102,17 @@ def test_front_speeds_fp32_storage(lbm_mod):
     print(f"[flame1d fp32] S_d {e:.2e}, sum w {g['totals'][0]:.6f} vs {ref['totals'][0]:.6f}", flush=True)
     assert e <= 1e-3
     s.close()
+
+
+def test_front_speeds_away_from_the_isosurface(lbm_mod):
+    """A uniform state (config 1 at its mean composition, at rest): grad T is rounding
+    noise, no node lies within one cell of T_iso = 1500 K, so every weight and every sum
+    is exactly 0, and the speeds are finite."""
+    prob = W.config1()
+    prob.Y = np.repeat(prob.Y.mean(axis=1)[:, None], prob.N, axis=1)
+    prob.rho = np.full(prob.N, prob.rho.mean())
+    s = lbm_mod.Solver(prob, storage=W.STORE_F64).init()
+    g = s.flame_speeds(1500.0)
+    assert not np.any(g["w"]) and not np.any(g["totals"])
+    assert np.all(np.isfinite(g["Sd"])) and np.all(np.isfinite(g["Sa"]))
+    s.close()

@@ -63,3 +63,15 @@ def test_graph_on_3d_lattice_with_all_kernels(lbm_mod):
         _same(graph.macros(), eager.macros())
     graph.close()
     eager.close()
+
+
+def test_graph_step_counts(lbm_mod):
+    """Zero steps change nothing; a negative count is an argument error."""
+    prob = W.flame_batch(lengths=[40, 9], phis=[1.0, 2.0], hot_cells=8, storage=W.STORE_F64)
+    s = lbm_mod.Solver(prob, storage=W.STORE_F64).init()
+    before = s.macros()
+    s.step_graph(0)
+    _same(s.macros(), before)
+    with pytest.raises(lbm_mod.LbmError):
+        s.step_graph(-1)
+    s.close()
