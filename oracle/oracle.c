@@ -221,6 +221,21 @@ static double diffusivity(const orc_sim *s, int a, int b, double T) {
   return s->diff[a][b] * pow(T / s->p.diff_T_ref, s->p.diff_T_exp);
 }
 
+/* relaxation rates at temperature T: the given omega, omega1, or with a temperature
+ * exponent the rates whose viscosity and conductivity factors 1/omega - 1/2 and
+ * 1/omega1 - 1/2 (eqs. mu, lambda) scale as (T / T_ref)^n (a stand-in for the
+ * temperature-dependent transport data of Sec. 3) */
+static void relaxation_rates(const orc_sim *s, double T, double *om, double *om1) {
+  if (s->p.visc_T_exp == 0.0) {
+    *om = s->p.omega;
+    *om1 = s->p.omega1;
+    return;
+  }
+  const double sc = pow(T / s->p.visc_T_ref, s->p.visc_T_exp);
+  *om = 1.0 / (0.5 + (1.0 / s->p.omega - 0.5) * sc);
+  *om1 = 1.0 / (0.5 + (1.0 / s->p.omega1 - 0.5) * sc);
+}
+
 /* K_ab = 1/tau_ab with tau_ab = (m_a m_b / (m R_U T)) D_ab, written with lattice
  * R_a T: 1/tau_ab = (R_a T)(R_b T) / ((R T) D_ab). */
 static void relaxation(const orc_sim *s, const double *Y, const double *zeta_a, double zeta, double T,
@@ -401,7 +416,8 @@ static void collide(orc_sim *s, int64_t n) {
   const int M = s->p.M;
   const int64_t N = s->N;
   const node_t *d = &s->nd[n];
-  const double om = s->p.omega, om1 = s->p.omega1;
+  double om, om1;
+  relaxation_rates(s, d->T, &om, &om1);
 
   /* mixture f (eq. f) with the isotropy correction A_i . X (eq. Ai) */
   {
@@ -552,6 +568,7 @@ orc_sim *orc_create(const orc_problem *p) {
   }
   if (p->omega == p->omega1) return NULL;   /* the printed q^diff and q^corr prefactors are singular */
   if (p->diff_T_exp != 0.0 && !(p->diff_T_ref > 0.0)) return NULL;
+  if (p->visc_T_exp != 0.0 && !(p->visc_T_ref > 0.0)) return NULL;
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   s->p = *p;
   const int M = p->M;
@@ -635,8 +652,11 @@ static void nonlocal_fields(orc_sim *s, int nthreads) {
   for (int a = 0; a < 3; ++a) {
     for (int64_t n = 0; n < N; ++n) fld[n] = s->nd[n].phi[a];
 #pragma omp parallel for schedule(static) num_threads(nthreads)
-    for (int64_t n = 0; n < N; ++n)
-      s->nd[n].psi[a] = (1.0 / s->p.omega - 0.5) * iso_grad_v(s, fld, n, a, a);
+    for (int64_t n = 0; n < N; ++n) {
+      double om, om1;
+      relaxation_rates(s, s->nd[n].T, &om, &om1);
+      s->nd[n].psi[a] = (1.0 / om - 0.5) * iso_grad_v(s, fld, n, a, a);
+    }
   }
   for (int a = 0; a < 3; ++a) {
     for (int64_t n = 0; n < N; ++n) fld[n] = s->nd[n].psi[a];
@@ -717,7 +737,9 @@ uint32_t orc_flame_speeds(orc_sim *s, double T_iso, const double *centre, double
     T[n] = d[n].T;
     cp[n] = 0.0;
     for (int sp = 0; sp < M; ++sp) cp[n] += d[n].Y[sp] * (spec_Cv(s, sp, T[n]) + gas_const(s, sp));
-    lam[n] = (1.0 / s->p.omega1 - 0.5) * d[n].P * cp[n];
+    double om, om1;
+    relaxation_rates(s, T[n], &om, &om1);
+    lam[n] = (1.0 / om1 - 0.5) * d[n].P * cp[n];
   }
   for (int64_t n = 0; n < N; ++n)
     for (int a = 0; a < 3; ++a) gT[a * N + n] = iso_grad(s, T, n, a);

@@ -47,6 +47,8 @@ typedef struct {
   double p0;                   /* Pa, standard pressure of the thermo data */
   double diff_T_ref;           /* K; with diff_T_exp != 0: D_ab(T) = D_ab (T / diff_T_ref)^diff_T_exp */
   double diff_T_exp;
+  double visc_T_ref;           /* K; with visc_T_exp != 0: 1/omega - 1/2 and 1/omega1 - 1/2 */
+  double visc_T_exp;           /* scale with (T / visc_T_ref)^visc_T_exp at each node */
 } orc_problem;
 
 typedef struct orc_sim orc_sim;

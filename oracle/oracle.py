@@ -27,6 +27,7 @@ class _Problem(C.Structure):
         ("kappa", C.c_double), ("dt_phys", C.c_double), ("rho_ref", C.c_double),
         ("p0", C.c_double),
         ("diff_T_ref", C.c_double), ("diff_T_exp", C.c_double),
+        ("visc_T_ref", C.c_double), ("visc_T_exp", C.c_double),
     ]
 
 
@@ -125,6 +126,8 @@ class OracleSim:
         p.kappa, p.dt_phys, p.rho_ref, p.p0 = prob.kappa, prob.dt_phys, prob.rho_ref, prob.p0
         p.diff_T_ref = getattr(prob, "diff_T_ref", 0.0)
         p.diff_T_exp = getattr(prob, "diff_T_exp", 0.0)
+        p.visc_T_ref = getattr(prob, "visc_T_ref", 0.0)
+        p.visc_T_exp = getattr(prob, "visc_T_exp", 0.0)
         self._p = p
         h = lib.orc_create(C.byref(p))
         if not h:

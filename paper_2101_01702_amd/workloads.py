@@ -94,6 +94,10 @@ class Problem:
     # temperature-dependent diffusivities D_ab (T / diff_T_ref)^diff_T_exp (0: constant)
     diff_T_ref: float = 0.0
     diff_T_exp: float = 0.0
+    # temperature-dependent viscosity and conductivity: 1/omega - 1/2 and 1/omega1 - 1/2
+    # scale as (T / visc_T_ref)^visc_T_exp (0: constant omega, omega1)
+    visc_T_ref: float = 0.0
+    visc_T_exp: float = 0.0
 
     @property
     def N(self) -> int:

@@ -494,3 +494,40 @@ def test_fickian_decay_with_temperature_dependent_diffusivity(T, exp):
         sim.step(300)
     rate = -np.polyfit(ts, np.log(amps), 1)[0]
     assert rate == pytest.approx(D_eff * k * k, rel=0.01)
+
+
+def test_shear_and_thermal_decay_with_temperature_dependent_transport():
+    """1/omega - 1/2 and 1/omega1 - 1/2 scaled by (T / T_ref)^n: at a uniform 1000 K with
+    T_ref = 500 K and n = 0.7 a shear wave decays at nu(T) k^2 and an isobaric thermal
+    mode at the conductivity's rate, both from the scaled rates (eqs. mu, lambda)."""
+    L = 64
+    mech = two_species()
+    x = np.arange(L)
+    k = 2 * math.pi / L
+    sc = (1000.0 / 500.0) ** 0.7
+    u = np.zeros((3, L))
+    u[1] = 1e-3 * np.sin(2 * math.pi * x / L)
+    prob = lattice_problem(mech, L, u=u, omega=1.6)
+    prob.visc_T_ref, prob.visc_T_exp = 500.0, 0.7
+    sim = orc.OracleSim(prob).init()
+    zeta = prob.kappa * W.R_U * 1000.0 / 28e-3
+    nu = (1 / 1.6 - 0.5) * sc * zeta
+    amps, ts = [], []
+    for n in range(5):
+        amps.append(fourier_amp(sim.macros()["u"][1], L))
+        ts.append(n * 200)
+        sim.step(200)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    assert rate == pytest.approx(nu * k * k, rel=0.01)
+    Tf = 1000.0 * (1 + 2e-3 * np.sin(2 * math.pi * x / L))
+    prob = lattice_problem(mech, L, T_field=Tf, omega=1.3, prandtl=0.7)
+    prob.visc_T_ref, prob.visc_T_exp = 500.0, 0.7
+    sim = orc.OracleSim(prob).init()
+    alpha = (1 / prob.omega1 - 0.5) * sc * zeta
+    amps, ts = [], []
+    for n in range(8):
+        amps.append(fourier_amp(sim.macros()["T"] - 1000.0, L))
+        ts.append(n * 150)
+        sim.step(150)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    assert rate == pytest.approx(alpha * k * k, rel=0.03)
