@@ -117,6 +117,12 @@ enum {
  *                   diffusivity is D_ab (T / diff_T_ref)^diff_T_exp at the node's
  *                   temperature (a power law standing in for the temperature-dependent
  *                   transport data of Sec. 3); 0: the constants diff_ab
+ *   visc_T_ref, visc_T_exp   temperature dependence of the viscosity and the
+ *                   conductivity: with visc_T_exp != 0 (|exp| <= 4, visc_T_ref > 0
+ *                   in K) the factors 1/omega - 1/2 and 1/omega1 - 1/2 of eqs. mu and
+ *                   lambda scale with (T / visc_T_ref)^visc_T_exp at each node, which
+ *                   sets that node's relaxation rates (LBM_STORE_F64 and _F32 only);
+ *                   0: the constants omega, omega1
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -139,6 +145,7 @@ typedef struct {
   int32_t reserved2;
   const int32_t *segment_lengths;
   double diff_T_ref, diff_T_exp;
+  double visc_T_ref, visc_T_exp;
 } lbm_desc;
 
 /* Bytes of device workspace the descriptor needs: populations x2 with a ghost

@@ -44,6 +44,7 @@ Geom make_geom(const lbm_desc &d) {
   g.NX = n[0]; g.NY = n[1] + 2 * pad[1]; g.NZ = n[2] + 2 * pad[2];
   g.xg = pad[0];
   g.nseg = d.n_segments > 1 ? d.n_segments : 1;
+  g.vt = d.visc_T_exp != 0.0 ? 1 : 0;
   g.N = (int64_t)d.nx * d.ny * d.nz;
   g.XG = (int64_t)g.NX * g.NY * g.NZ;
   g.NPAD = g.XG + (g.xg ? 2LL * g.nseg * g.NY * g.NZ : 0);
@@ -170,6 +171,12 @@ bool validate(const lbm_desc *d, std::string *err) {
     return fail(err, "diff_T_exp = %g must be finite and within [-4, 4]", d->diff_T_exp);
   if (d->diff_T_exp != 0.0 && (!(d->diff_T_ref > 0.0) || !std::isfinite(d->diff_T_ref)))
     return fail(err, "diff_T_ref must be > 0 when diff_T_exp != 0");
+  if (!std::isfinite(d->visc_T_exp) || std::fabs(d->visc_T_exp) > 4.0)
+    return fail(err, "visc_T_exp = %g must be finite and within [-4, 4]", d->visc_T_exp);
+  if (d->visc_T_exp != 0.0 && (!(d->visc_T_ref > 0.0) || !std::isfinite(d->visc_T_ref)))
+    return fail(err, "visc_T_ref must be > 0 when visc_T_exp != 0");
+  if (d->visc_T_exp != 0.0 && d->storage != LBM_STORE_F64 && d->storage != LBM_STORE_F32)
+    return fail(err, "visc_T_exp != 0 needs LBM_STORE_F64 or LBM_STORE_F32 storage");
   if (d->n_segments < 0) return fail(err, "n_segments = %d must be >= 0", d->n_segments);
   if (d->n_segments > 1) {
     if (d->bc[0] == LBM_BC_PERIODIC) return fail(err, "segments along x need non-periodic x faces");
@@ -260,6 +267,10 @@ void build_tables(const lbm_desc &d, Tables &t) {
   t.omega1 = d.omega1;
   t.dexp = d.diff_T_exp;
   t.ln_dTref = d.diff_T_exp != 0.0 ? std::log(d.diff_T_ref) : 0.0;
+  t.vexp = d.visc_T_exp;
+  t.ln_vTref = d.visc_T_exp != 0.0 ? std::log(d.visc_T_ref) : 0.0;
+  t.c_om = 1.0 / d.omega - 0.5;
+  t.c_om1 = 1.0 / d.omega1 - 0.5;
 }
 
 // Reference populations of the deviation formats: the equilibria (eqs. feq, gieq) of
@@ -448,6 +459,9 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   Tables t;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
+  h->kc.vexp = t.vexp;
+  h->kc.ln_vTref = t.ln_vTref;
+  h->kc.c_om = t.c_om;
   for (int a = 0; a < MAXM; ++a) {
     h->kc.Ra[a] = t.Ra[a];
     h->kc.Raf[a] = (float)t.Ra[a];

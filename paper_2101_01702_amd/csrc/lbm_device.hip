@@ -292,6 +292,20 @@ __device__ __forceinline__ double inv_diff_scale(const TB &tb, double T) {
   return tb.dexp != 0.0 ? exp(tb.dexp * (tb.ln_dTref - log(T))) : 1.0;
 }
 
+// relaxation rates at temperature T: the constants omega, omega1, or the rates whose
+// factors 1/omega - 1/2 and 1/omega1 - 1/2 (eqs. mu, lambda) scale with (T / T_ref)^n
+template <bool VT = true, typename TB>
+__device__ __forceinline__ void relax_rates(const TB &tb, double T, double &om, double &om1) {
+  if (!VT || tb.vexp == 0.0) {
+    om = tb.omega;
+    om1 = tb.omega1;
+  } else {
+    const double s = exp(tb.vexp * (log(T) - tb.ln_vTref));
+    om = 1.0 / (0.5 + tb.c_om * s);
+    om1 = 1.0 / (0.5 + tb.c_om1 * s);
+  }
+}
+
 // ---- thermodynamics (eqs. specHa, Umix; NASA-7) -------------------------------------
 template <typename P>
 __device__ __forceinline__ double h_RT(P a, double T, double invT) {
@@ -723,7 +737,7 @@ __device__ __forceinline__ void moments_pass(const Geom &g, const void *src, con
 // collision coefficients cc, and the side channel of the stencils (O5).  No global
 // store happens before the side channel at the end, so that the constant tables are
 // read with scalar loads throughout.
-template <int M, typename ST>
+template <int M, typename ST, bool VT>
 __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 *kp, const IslStash &sh,
                                            int64_t n, const LaneSrc &l, int cur, CollCoef<M, FT<ST>> &cc) {
   using SW = IslWords<M>;
@@ -812,7 +826,8 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 
       Peq[k] = (k < 3 ? rho * zeta : 0.0) + rho * u[ia[k]] * u[ib[k]];
       Req[k] = h2 * Peq[k] + P * u[ia[k]] * u[ib[k]];
     }
-    const double om_d = tb.omega, om1 = tb.omega1;
+    double om_d, om1;
+    relax_rates<VT>(tb, T, om_d, om1);
     const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
     const double trR = Req[0] + Req[1] + Req[2];
     sh.w(SW::G + 0, om_d * (2.5 * m.rhoE - 1.5 * trR));
@@ -944,7 +959,8 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 
   double Ha[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) Ha[a] = tb.Ra[a] * T * h_RT(tb.nasa[a], T, invT);
-  const double om1 = tb.omega1;
+  double om_n, om1;
+  relax_rates<VT>(tb, T, om_n, om1);
   const bool open_any = tb.open_any != 0;
   {
     const double inv_zeta = inv_diff_scale(tb, T) / zeta;   // with the T factor of 1/D_ab (F term)
@@ -1016,14 +1032,20 @@ __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 
 // with the (cy, cz) part of the bracket summed once per row.  A_i.X and the q^corr part
 // are added by the next pull.
 struct RowFG {
+  double om;       // relaxation rate of f and g at the node (temperature law only)
   double rf;       // rho Psi_cy(u_y) Psi_cz(u_z)
   double R0, R1;   // bracket = R0 + cx R1 + cx^2 A2_xx
   double wyz;      // w1(cy) w1(cz)
 };
 
-template <int M, typename F>
-__device__ __forceinline__ RowFG fg_row(const CollCoef<M, F> &cc, int cy, int cz) {
+template <int M, typename F, bool VT>
+__device__ __forceinline__ RowFG fg_row(const CollCoef<M, F> &cc, int cy, int cz, KC4 *kp) {
   RowFG rw;
+  // the node's rate: the constant, or with a temperature law formed again in each row
+  // rather than held over the pass (the expression of relax_rates, so the same value)
+  const KC4 &kc = *kp;
+  if constexpr (VT)
+    rw.om = kc.vexp == 0.0 ? kc.omega : 1.0 / (0.5 + kc.c_om * exp(kc.vexp * (log(cc.T) - kc.ln_vTref)));
   const double u1 = cc.u1, u2 = cc.u2;
   rw.rf = cc.rho * psi_c<double>(cy, u1, u1 * u1 + cc.zeta) * psi_c<double>(cz, u2, u2 * u2 + cc.zeta);
   const double dy = cy, dz = cz;
@@ -1034,13 +1056,13 @@ __device__ __forceinline__ RowFG fg_row(const CollCoef<M, F> &cc, int cy, int cz
   return rw;
 }
 
-template <int M, typename ST, typename F, int CX, typename K>
+template <int M, typename ST, typename F, int CX, bool VT, typename K>
 __device__ __forceinline__ void collide_fg_dir(const Geom &g, void *dst, const CollCoef<M, F> &cc, const RowFG &rw,
                                                const PulledFG<ST> &p, int i, int cy, int cz, const K &kc,
                                                uint32_t so) {
   double f, gv;
   fg_values<M, ST, CX>(p, i, cy, cz, kc, f, gv);
-  const double om = kc.omega;
+  const double om = VT ? rw.om : kc.omega;
   const double u0 = cc.u0;
   const double feq = rw.rf * psi_c<double>(CX, u0, u0 * u0 + cc.zeta);
   bst<ST>(plane<ST>(dst, g, (M - 1) * Q + i), so, pop_enc<ST>((1.0 - om) * f + om * feq, M - 1, i, kc));
@@ -1155,7 +1177,7 @@ __device__ __forceinline__ void collide_species_dir(const Geom &g, void *dst, co
 
 // O7 + O8 for f and g alone over the 27 directions (the two-pass form of the
 // collision, for formats whose one-pass form holds too many registers)
-template <int M, typename ST, typename F>
+template <int M, typename ST, typename F, bool VT>
 __device__ __forceinline__ void fg_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
                                         const CollCoef<M, F> &cc, const LaneSrc &l) {
   const uint32_t so = row_source(g, l, 0, 0).p0 * (uint32_t)sizeof(ST);
@@ -1167,17 +1189,17 @@ __device__ __forceinline__ void fg_pass(const Geom &g, const void *src, void *ds
     KC4 *k = kp;
     opaque_uniform(k);
     const RowPos s0 = row_source(g, l, cy, cz);
-    const RowFG rw = fg_row<M, F>(cc, cy, cz);
+    const RowFG rw = fg_row<M, F, VT>(cc, cy, cz, k);
     pull_fg<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
-    collide_fg_dir<M, ST, F, -1>(g, dst, cc, rw, pa, 3 * r, cy, cz, *k, so);
+    collide_fg_dir<M, ST, F, -1, VT>(g, dst, cc, rw, pa, 3 * r, cy, cz, *k, so);
     pull_fg<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
-    collide_fg_dir<M, ST, F, 0>(g, dst, cc, rw, pb, 3 * r + 1, cy, cz, *k, so);
+    collide_fg_dir<M, ST, F, 0, VT>(g, dst, cc, rw, pb, 3 * r + 1, cy, cz, *k, so);
     {
       const int rn = r < 8 ? r + 1 : 8;
       const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
       pull_fg<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
     }
-    collide_fg_dir<M, ST, F, 1>(g, dst, cc, rw, pc, 3 * r + 2, cy, cz, *k, so);
+    collide_fg_dir<M, ST, F, 1, VT>(g, dst, cc, rw, pc, 3 * r + 2, cy, cz, *k, so);
   }
 }
 
@@ -1222,7 +1244,7 @@ __device__ __forceinline__ void species_pass(const Geom &g, const void *src, voi
 // O7 + O8 over the 27 directions: f, g and the stored species of one direction from
 // the factors of its row, with the loads of the next direction in flight while the
 // current one is collided
-template <int M, typename ST, typename F>
+template <int M, typename ST, typename F, bool VT>
 __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
                                              const CollCoef<M, F> &cc, const LaneSrc &l) {
   const uint32_t so = row_source(g, l, 0, 0).p0 * (uint32_t)sizeof(ST);
@@ -1237,14 +1259,14 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
     opaque(u0);
     opaque(T);
     const RowPos s0 = row_source(g, l, cy, cz);
-    const RowFG rw = fg_row<M, F>(cc, cy, cz);
+    const RowFG rw = fg_row<M, F, VT>(cc, cy, cz, k);
     RowSpecies<M, F> rs;
     species_row<M, F>(cc, T, cy, cz, *k, rs);
     pull_all<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
-    collide_fg_dir<M, ST, F, -1>(g, dst, cc, rw, pa.fg, 3 * r, cy, cz, *k, so);
+    collide_fg_dir<M, ST, F, -1, VT>(g, dst, cc, rw, pa.fg, 3 * r, cy, cz, *k, so);
     collide_species_dir<M, ST, F, -1>(g, dst, cc, u0, T, rs, pa.fa, 3 * r, *k, so);
     pull_all<M, ST, 1>(g, src, corr, 3 * r + 2, cy, cz, dir_source<1>(g, l, s0), pc);
-    collide_fg_dir<M, ST, F, 0>(g, dst, cc, rw, pb.fg, 3 * r + 1, cy, cz, *k, so);
+    collide_fg_dir<M, ST, F, 0, VT>(g, dst, cc, rw, pb.fg, 3 * r + 1, cy, cz, *k, so);
     collide_species_dir<M, ST, F, 0>(g, dst, cc, u0, T, rs, pb.fa, 3 * r + 1, *k, so);
     {
       // first direction of the next row (the last row reloads its own: no branch, so
@@ -1253,7 +1275,7 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
       const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
       pull_all<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
     }
-    collide_fg_dir<M, ST, F, 1>(g, dst, cc, rw, pc.fg, 3 * r + 2, cy, cz, *k, so);
+    collide_fg_dir<M, ST, F, 1, VT>(g, dst, cc, rw, pc.fg, 3 * r + 2, cy, cz, *k, so);
     collide_species_dir<M, ST, F, 1>(g, dst, cc, u0, T, rs, pc.fa, 3 * r + 2, *k, so);
   }
 }
@@ -1262,7 +1284,9 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
 // registers (FP32 storage; the other formats collide f and g, then the species, in
 // two passes that each hold fewer registers).  The populations are read twice, and no
 // record goes through memory.
-template <int M, typename ST>
+// VT: relaxation rates from the temperature law of the transport (a separate build of
+// the kernel, so that the constant-rate kernel carries none of it)
+template <int M, typename ST, bool VT>
 __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cur) {
   using F = FT<ST>;
   __shared__ double words[IslWords<M>::WORDS * ISL_BLOCK];
@@ -1273,11 +1297,11 @@ __global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cu
 
   KC4 *kp = (KC4 *)b.kc;
   CollCoef<M, F> cc;
-  node_local<M, ST>(g, b, kp, sh, n, l, cur, cc);
+  node_local<M, ST, VT>(g, b, kp, sh, n, l, cur, cc);
   if constexpr (sizeof(ST) == 4 && sizeof(F) == 4) {
-    collide_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
+    collide_pass<M, ST, F, VT>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
   } else {
-    fg_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
+    fg_pass<M, ST, F, VT>(g, b.pop[cur], b.pop[cur ^ 1], b.corr, kp, cc, l);
     species_pass<M, ST, F>(g, b.pop[cur], b.pop[cur ^ 1], kp, cc, l);
   }
 }
@@ -1290,7 +1314,9 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
   const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
   const RT *phi = static_cast<const RT *>(b.side_phi);
   const int64_t N = g.N;
-  const double coef = 1.0 / b.tab->omega - 0.5;
+  double om, om1;
+  relax_rates(*b.tab, b.T[n], om, om1);
+  const double coef = 1.0 / om - 0.5;
   // x neighbours within the node's segment (the whole axis when it is periodic)
   const XSeg xsg = x_segment(g, x);
   int xs[3], ys[3], zs[3];
@@ -1948,7 +1974,9 @@ __global__ __launch_bounds__(128) void k_fs_local(Geom g, Buffers b, CollideCons
     }
   const int64_t N = g.N;
   work[FS_T * N + n] = T;
-  work[FS_LAM * N + n] = (1.0 / tb.omega1 - 0.5) * m.rho * zeta * cp;
+  double om, om1;
+  relax_rates(tb, T, om, om1);
+  work[FS_LAM * N + n] = (1.0 / om1 - 0.5) * m.rho * zeta * cp;
   work[FS_HRR * N + n] = hrr;
   work[FS_RHOCP * N + n] = m.rho * cp;
 #pragma unroll
@@ -2110,7 +2138,15 @@ template <int M, typename ST, typename RT>
 struct RunStep {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
     (void)kc;   // k_step reads the device copy of the constants (Buffers::kc)
-    hipLaunchKernelGGL((k_step<M, ST>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b, cur);
+    if (!g.vt) {
+      hipLaunchKernelGGL((k_step<M, ST, false>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b,
+                         cur);
+    } else if constexpr (sizeof(ST) >= 4) {
+      hipLaunchKernelGGL((k_step<M, ST, true>), dim3(blocks_for(g.N, ISL_BLOCK)), dim3(ISL_BLOCK), 0, st, g, b,
+                         cur);
+    } else {
+      return hipErrorInvalidValue;   // rejected by the descriptor check: FP64 and FP32 storage only
+    }
     return hipGetLastError();
   }
 };

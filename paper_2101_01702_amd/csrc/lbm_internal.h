@@ -39,6 +39,8 @@ struct Tables {
   double ln_c0_const;         // ln(p0 * 1e-6 / R_U): ln c0(T) = ln_c0_const - ln T (mol/cm^3)
   double omega, omega1;
   double dexp, ln_dTref;      // D_ab(T) = D_ab exp(dexp (ln T - ln_dTref)); dexp = 0: constant
+  double vexp, ln_vTref;      // 1/omega(T) - 1/2 = c_om exp(vexp (ln T - ln_vTref)); vexp = 0: constant
+  double c_om, c_om1;         // 1/omega - 1/2 and 1/omega1 - 1/2 at the reference temperature
 };
 
 // Constants of the collision.  The init, ghost and output kernels take them as a kernel
@@ -54,6 +56,7 @@ struct CollideConsts {
   // deviation formats: stored value = (f - ref[s][i]) * isc[s], f = ref[s][i] + sc[s] * stored
   float ref[MAXM + 1][Q];
   float sc[MAXM + 1], isc[MAXM + 1];
+  double vexp, ln_vTref, c_om;           // temperature law of omega (as in Tables)
 };
 
 // A plane of one (set, direction) holds the rows (z, y) of the lattice padded with a
@@ -76,6 +79,8 @@ struct Geom {
   int64_t XG;                 // first x ghost cell, NX NY NZ
   const int32_t *x_seg;       // [nx] segment of each x (nseg > 1)
   const int32_t *seg_off;     // [nseg + 1] first x of each segment, then nx (nseg > 1)
+  int32_t vt;                 // 1: relaxation rates from the temperature law (visc_T_exp != 0)
+  int32_t pad2_;
 };
 
 // Device pointers into the workspace.

@@ -42,6 +42,7 @@ class LbmDesc(C.Structure):
         ("storage", C.c_int32), ("reserved", C.c_int32), ("ref_state", C.c_void_p),
         ("n_segments", C.c_int32), ("reserved2", C.c_int32), ("segment_lengths", _ip),
         ("diff_T_ref", C.c_double), ("diff_T_exp", C.c_double),
+        ("visc_T_ref", C.c_double), ("visc_T_exp", C.c_double),
     ]
 
 
@@ -124,6 +125,8 @@ def make_desc(prob, storage: Optional[int] = None):
     d.storage = prob.storage if storage is None else storage
     d.diff_T_ref = float(getattr(prob, "diff_T_ref", 0.0))
     d.diff_T_exp = float(getattr(prob, "diff_T_exp", 0.0))
+    d.visc_T_ref = float(getattr(prob, "visc_T_ref", 0.0))
+    d.visc_T_exp = float(getattr(prob, "visc_T_exp", 0.0))
     segs = getattr(prob, "segments", None)
     if segs is not None and len(segs) > 1:
         keep["segments"] = np.ascontiguousarray(segs, np.int32)

@@ -256,3 +256,13 @@ def test_diffusivity_exponent_validation(lib):
         d, keep = lbm.make_desc(prob)
         code, _, msg = _ws(lib, d)
         assert (code == 0) == ok and needle in msg, (ref, ex, msg)
+
+
+def test_viscosity_exponent_validation(lib):
+    prob = W.config1()
+    for ref, ex, ok, needle in ((300.0, 0.7, True, ""), (0.0, 0.7, False, "visc_T_ref"),
+                                (300.0, -5.0, False, "visc_T_exp")):
+        prob.visc_T_ref, prob.visc_T_exp = ref, ex
+        d, keep = lbm.make_desc(prob)
+        code, _, msg = _ws(lib, d)
+        assert (code == 0) == ok and needle in msg, (ref, ex, msg)

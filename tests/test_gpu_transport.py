@@ -78,3 +78,58 @@ def test_3d_with_temperature_dependent_diffusivity_fp64(lbm_mod):
     err = field_errors(mac, sim.macros(), zeta_of(prob))
     print(f"[sphere D(T) fp64] worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
     assert max(err.values()) <= TOL64, err
+
+
+# Temperature-dependent viscosity and conductivity: 1/omega - 1/2 and 1/omega1 - 1/2
+# scale with (T / 600 K)^0.5, together with the diffusivity law above; the burnt side
+# relaxes at omega = 0.67 against 1.0 in the unburnt gas.
+def _flame_all():
+    prob = _flame()
+    prob.visc_T_ref, prob.visc_T_exp = 600.0, 0.5
+    return prob
+
+
+def test_flame_with_temperature_dependent_transport_fp64(lbm_mod):
+    prob = _flame_all()
+    s = lbm_mod.Solver(prob, storage=W.STORE_F64).init()
+    s.step(200)
+    mac = s.macros()
+    sim, anom = oracle_run(prob, 200)
+    assert s.status() == 0 and anom == 0
+    err = field_errors(mac, sim.macros(), zeta_of(prob))
+    print(f"[flame mu(T), D(T) fp64] worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
+    assert max(err.values()) <= TOL64, err
+    pop, _ = s.populations(np.arange(prob.N))
+    assert max(pop_errors(pop, sim.state()[0])) <= TOL64
+    g, r = s.flame_speeds(900.0), sim.flame_speeds(900.0)
+    sel = r["w"] > 0
+    assert np.abs(g["Sd"] - r["Sd"])[sel].max() <= 1e-9 * np.abs(r["Sd"][sel]).max()
+    s.close()
+
+
+def test_flame_with_temperature_dependent_transport_fp32(lbm_mod):
+    prob = _flame_all()
+    s = lbm_mod.Solver(prob, storage=W.STORE_F32).init()
+    s.step(1000)
+    mac = s.macros()
+    sim, anom = oracle_run(prob, 1000)
+    assert s.status() == 0 and anom == 0
+    err = field_errors(mac, sim.macros(), zeta_of(prob))
+    flow = {k: v for k, v in err.items() if not k.startswith("Y")}
+    ys = {k: v for k, v in err.items() if k.startswith("Y")}
+    print(f"[flame mu(T), D(T) fp32] flow {max(flow.values()):.2e} Y {max(ys.values()):.2e}", flush=True)
+    assert max(flow.values()) <= TOL32 and max(ys.values()) <= TOL32_Y_IGNITION
+
+
+def test_3d_with_temperature_dependent_viscosity_fp64(lbm_mod):
+    prob = W.perturb_velocity(W.sphere3d(shape=(13, 10, 9), radius=3.0, storage=W.STORE_F64), 2e-3, 9)
+    prob = dataclasses.replace(prob, visc_T_ref=800.0, visc_T_exp=-0.6,
+                               bc=(W.BC_SYMMETRY, W.BC_OPEN, W.BC_OPEN, W.BC_OPEN, W.BC_SYMMETRY, W.BC_OPEN))
+    s = lbm_mod.Solver(prob, storage=W.STORE_F64).init()
+    s.step(60)
+    mac = s.macros()
+    sim, anom = oracle_run(prob, 60)
+    assert s.status() == 0 and anom == 0
+    err = field_errors(mac, sim.macros(), zeta_of(prob))
+    print(f"[sphere mu(T) fp64] worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
+    assert max(err.values()) <= TOL64, err
