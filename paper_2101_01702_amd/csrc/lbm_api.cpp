@@ -667,8 +667,8 @@ lbm_status lbm_flame_speeds(lbm_handle h, double T_iso, const double *centre, do
 }
 
 lbm_status lbm_adjoint_step(lbm_handle h, const void *, void *, double *, void *) {
-  if (h) h->err = "the discrete adjoint step is not provided by this build";
-  else g_last_error = "the discrete adjoint step is not provided by this build";
+  if (h) h->err = "the discrete adjoint step is not provided by this library";
+  else g_last_error = "the discrete adjoint step is not provided by this library";
   return LBM_ERR_UNSUPPORTED;
 }
 
