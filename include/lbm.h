@@ -162,7 +162,11 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 /* Validate the descriptor, copy it, and upload its tables into the caller's
  * device workspace (256-byte aligned, >= lbm_workspace_size bytes, must outlive
  * the handle).  The current HIP device must be the workspace's device.  The
- * upload is synchronous. */
+ * upload is synchronous.  It then times the three tile shapes of the correction
+ * stencil that suit the lattice (four launches each, on the default stream) and keeps
+ * the fastest; LBM_CORR_TILE=k in the environment (0-2 for lattices with a
+ * cross-section, 3-5 for lattices one node thick in y and z) picks shape k instead.
+ * Every shape gives the same bits. */
 lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm_handle *out);
 
 /* Release the host handle (the workspace is untouched). */

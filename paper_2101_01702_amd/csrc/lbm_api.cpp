@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -351,6 +352,50 @@ struct lbm_ctx {
 
 namespace {
 
+// Tile shape of the correction stencil for this lattice: each valid shape is timed over
+// three launches (after one untimed) on the default stream, with the stencil's inputs
+// cleared, and the fastest kept.  LBM_CORR_TILE=k in the environment picks shape k when
+// it is valid for the lattice.  The stencil's output (the corrections) is cleared again
+// by lbm_init_fields.
+hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
+  int cand[3];
+  const int nc = corr_tile_candidates(h->g, cand);
+  h->g.corr_tile = cand[0];
+  if (const char *env = std::getenv("LBM_CORR_TILE")) {
+    const int k = std::atoi(env);
+    for (int i = 0; i < nc; ++i)
+      if (cand[i] == k) {
+        h->g.corr_tile = k;
+        return hipSuccess;
+      }
+  }
+  const Layout &L = h->L;
+  hipError_t e = launch_zero(ws + L.side_Y, (int64_t)((L.corr - L.side_Y) / 4), nullptr);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  float best = 0.f;
+  int choice = cand[0];
+  for (int i = 0; i < nc && e == hipSuccess; ++i) {
+    h->g.corr_tile = cand[i];
+    e = launch_corr_only(h->g, h->b, h->d.storage, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], nullptr);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_corr_only(h->g, h->b, h->d.storage, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+    if (e == hipSuccess && (i == 0 || t < best)) {
+      best = t;
+      choice = cand[i];
+    }
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  h->g.corr_tile = choice;
+  return e;
+}
+
 lbm_status hip_fail(lbm_ctx *h, hipError_t e, const char *what) {
   std::string msg = std::string(what) + ": " + hipGetErrorString(e);
   if (h) h->err = msg; else g_last_error = msg;
@@ -489,6 +534,12 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   }
   if (e != hipSuccess) {
     lbm_status s = hip_fail(nullptr, e, "uploading tables");
+    delete h;
+    return s;
+  }
+  e = tune_corr_tile(h, ws);
+  if (e != hipSuccess) {
+    lbm_status s = hip_fail(nullptr, e, "timing the correction tiles");
     delete h;
     return s;
   }

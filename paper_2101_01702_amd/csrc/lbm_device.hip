@@ -1361,16 +1361,22 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
 // of 256 x 1 x 1 with no y or z halo: its y and z neighbours are the node's own row
 // (wrapped on periodic axes, clamped on open ones), so 32 x 4 x 4 tiles would leave 15
 // of 16 threads idle.
-template <bool THIN>
-struct CorrTile {
-  static constexpr int X = 32, Y = 4, Z = 4, HX = X + 2, HY = Y + 2, HZ = Z + 2;
+template <int TX, int TY, int TZ, bool TH>
+struct CorrTileT {
+  static constexpr bool THIN = TH;
+  static constexpr int X = TX, Y = TY, Z = TZ, HX = X + 2, HY = TH ? 1 : Y + 2, HZ = TH ? 1 : Z + 2;
   static constexpr int THREADS = X * Y * Z, CELLS = HX * HY * HZ;
 };
-template <>
-struct CorrTile<true> {
-  static constexpr int X = 256, Y = 1, Z = 1, HX = X + 2, HY = 1;
-  static constexpr int THREADS = X, CELLS = HX;
-};
+// the tile shapes a lattice chooses from (corr_tile_candidates): 0-2 for lattices with a
+// cross-section, 3-5 for lattices one node thick in y and z
+template <int K>
+struct CorrTile;
+template <> struct CorrTile<0> : CorrTileT<32, 4, 4, false> {};
+template <> struct CorrTile<1> : CorrTileT<64, 2, 2, false> {};
+template <> struct CorrTile<2> : CorrTileT<16, 4, 8, false> {};
+template <> struct CorrTile<3> : CorrTileT<256, 1, 1, true> {};
+template <> struct CorrTile<4> : CorrTileT<128, 1, 1, true> {};
+template <> struct CorrTile<5> : CorrTileT<512, 1, 1, true> {};
 
 __device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
   if (periodic) {
@@ -1380,17 +1386,16 @@ __device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
   return v < 0 ? 0 : (v >= n ? n - 1 : v);
 }
 
-inline bool corr_thin(const Geom &g) { return g.ny == 1 && g.nz == 1; }
-
-template <bool THIN>
+template <int K>
 inline int64_t corr_tiles(const Geom &g) {
-  using T = CorrTile<THIN>;
+  using T = CorrTile<K>;
   return (int64_t)((g.nx + T::X - 1) / T::X) * ((g.ny + T::Y - 1) / T::Y) * ((g.nz + T::Z - 1) / T::Z);
 }
 
-template <int M, typename RT, typename CT, bool THIN>
-__global__ __launch_bounds__(CorrTile<THIN>::THREADS) void k_corr(Geom g, Buffers b) {
-  using T = CorrTile<THIN>;
+template <int M, typename RT, typename CT, int K>
+__global__ __launch_bounds__(CorrTile<K>::THREADS) void k_corr(Geom g, Buffers b) {
+  using T = CorrTile<K>;
+  constexpr bool THIN = T::THIN;
   constexpr int CH_X = T::HX, CH_Y = T::HY, CH_CELLS = T::CELLS;
   __shared__ RT sh[(M + 3) * CH_CELLS];   // field f of halo cell c at f * CH_CELLS + c
   const int tiles_x = (g.nx + T::X - 1) / T::X, tiles_y = (g.ny + T::Y - 1) / T::Y;
@@ -2153,12 +2158,16 @@ struct RunStep {
 template <int M, typename ST, typename RT>
 struct RunCorr {
   static hipError_t run(const Geom &g, const Buffers &b, hipStream_t st) {
-    if (corr_thin(g))
-      hipLaunchKernelGGL((k_corr<M, RT, RT, true>), dim3((unsigned)corr_tiles<true>(g)),
-                         dim3(CorrTile<true>::THREADS), 0, st, g, b);
-    else
-      hipLaunchKernelGGL((k_corr<M, RT, RT, false>), dim3((unsigned)corr_tiles<false>(g)),
-                         dim3(CorrTile<false>::THREADS), 0, st, g, b);
+    switch (g.corr_tile) {
+#define LBM_CORR_CASE(K)                                                                              \
+  case K:                                                                                             \
+    hipLaunchKernelGGL((k_corr<M, RT, RT, K>), dim3((unsigned)corr_tiles<K>(g)), dim3(CorrTile<K>::THREADS), 0, \
+                       st, g, b);                                                                     \
+    break;
+      LBM_CORR_CASE(0) LBM_CORR_CASE(1) LBM_CORR_CASE(2) LBM_CORR_CASE(3) LBM_CORR_CASE(4) LBM_CORR_CASE(5)
+#undef LBM_CORR_CASE
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
 };
@@ -2274,6 +2283,17 @@ hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st
   else
     hipLaunchKernelGGL((k_psi<float>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
   return hipGetLastError();
+}
+
+int corr_tile_candidates(const Geom &g, int *out) {
+  // the thin tiles take the node's own row for every y and z neighbour: one node thick only
+  const bool thin = g.ny == 1 && g.nz == 1;
+  for (int k = 0; k < 3; ++k) out[k] = thin ? 3 + k : k;
+  return 3;
+}
+
+hipError_t launch_corr_only(const Geom &g, const Buffers &b, int store, hipStream_t st) {
+  return dispatch<RunCorr>(g.M, store, g, b, st);
 }
 
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st) {

@@ -80,7 +80,7 @@ struct Geom {
   const int32_t *x_seg;       // [nx] segment of each x (nseg > 1)
   const int32_t *seg_off;     // [nseg + 1] first x of each segment, then nx (nseg > 1)
   int32_t vt;                 // 1: relaxation rates from the temperature law (visc_T_exp != 0)
-  int32_t pad2_;
+  int32_t corr_tile;          // tile shape of the correction stencil (chosen at create time)
 };
 
 // Device pointers into the workspace.
@@ -107,6 +107,10 @@ hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc,
                        hipStream_t st);
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st);
+// the correction-stencil tile shapes valid for the lattice (3 of them), and one launch of
+// the stencil alone with g.corr_tile (for timing them)
+int corr_tile_candidates(const Geom &g, int *out);
+hipError_t launch_corr_only(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_ghost(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
                         hipStream_t st);
 hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
