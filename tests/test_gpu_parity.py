@@ -276,3 +276,27 @@ def test_full_size_256_fp32_sampled(lbm_mod):
 
 def test_full_size_256_fp64_sampled(lbm_mod):
     _full_size_window_check(lbm_mod, W.STORE_F64, TOL64)
+
+
+# --- full-size quasi-1D flame (4096 cells, the flame-speed configuration) --------------
+def test_flame1d_full_size_4096_fp64(lbm_mod):
+    prob = W.flame1d(nx=4096)
+    s, mac, bits = _gpu_run(lbm_mod, prob, 200, W.STORE_F64)
+    sim, anom = oracle_run(prob, 200)
+    assert bits == 0 and anom == 0
+    _assert_fields(mac, sim.macros(), prob, TOL64, "flame1d 4096 fp64")
+    pop, _ = s.populations(np.arange(prob.N))
+    assert max(pop_errors(pop, sim.state()[0])) <= TOL64
+
+
+def test_flame1d_full_size_4096_fp32_1000_steps(lbm_mod):
+    prob = W.flame1d(nx=4096)
+    s, mac, bits = _gpu_run(lbm_mod, prob, 1000, W.STORE_F32)
+    sim, anom = oracle_run(prob, 1000)
+    assert bits == 0 and anom == 0
+    err = field_errors(mac, sim.macros(), zeta_of(prob))
+    flow = {k: v for k, v in err.items() if not k.startswith("Y")}
+    ys = {k: v for k, v in err.items() if k.startswith("Y")}
+    print(f"[flame1d 4096 fp32 1000] flow {max(flow.values()):.3e}, Y {max(ys.values()):.3e}", flush=True)
+    assert max(flow.values()) <= TOL32, flow
+    assert max(ys.values()) <= TOL32_Y_IGNITION, ys
