@@ -282,6 +282,12 @@ class Solver:
             return dict(Sd=o[0], Sa=o[1], w=o[2], totals=tot.cpu().numpy())
         return dict(Sd=out[0], Sa=out[1], w=out[2], totals=tot)
 
+    def mean_radius(self, T_iso: float, centre=(0.0, 0.0, 0.0)) -> float:
+        """Mean distance from ``centre`` over the isosurface T = T_iso (eq. rmean), from
+        the isosurface sums of lbm_flame_speeds; nan when no node lies on the surface."""
+        tot = self.flame_speeds(T_iso, centre)["totals"]
+        return float(tot[4] / tot[0]) if tot[0] > 0 else float("nan")
+
     def populations(self, nodes: Sequence[int], to_numpy: bool = True):
         """Pre-collision populations [S, 27, k] and stored temperatures at node ids."""
         t = self.torch
@@ -304,3 +310,15 @@ class Solver:
         if st not in (LBM_OK, -5):
             self._check(st, self.h)
         return int(bits.value)
+
+
+def growth_exponent(t: Sequence[float], r: Sequence[float]):
+    """Least-squares fit of R = a t^alpha to samples of a mean radius (the growth law of
+    the expanding flame, Sec. 5.2): returns (a, alpha) from a line through ln R against
+    ln t."""
+    lt = np.log(np.asarray(t, dtype=np.float64))
+    lr = np.log(np.asarray(r, dtype=np.float64))
+    if lt.size < 2:
+        raise ValueError("the fit needs at least two samples")
+    alpha, ln_a = np.polyfit(lt, lr, 1)
+    return float(np.exp(ln_a)), float(alpha)

@@ -266,3 +266,12 @@ def test_viscosity_exponent_validation(lib):
         d, keep = lbm.make_desc(prob)
         code, _, msg = _ws(lib, d)
         assert (code == 0) == ok and needle in msg, (ref, ex, msg)
+
+
+def test_growth_exponent_fit():
+    """R = a t^alpha is recovered exactly from noiseless samples."""
+    t = np.array([200.0, 400.0, 800.0, 1600.0, 3200.0])
+    a, alpha = lbm.growth_exponent(t, 0.37 * t ** 1.16)
+    assert abs(alpha - 1.16) < 1e-12 and abs(a - 0.37) < 1e-12
+    with pytest.raises(ValueError):
+        lbm.growth_exponent([1.0], [2.0])

@@ -116,3 +116,25 @@ def test_front_speeds_away_from_the_isosurface(lbm_mod):
     assert not np.any(g["w"]) and not np.any(g["totals"])
     assert np.all(np.isfinite(g["Sd"])) and np.all(np.isfinite(g["Sa"]))
     s.close()
+
+
+def test_mean_radius_of_a_spherical_isotherm(lbm_mod):
+    """Solver.mean_radius (eq. rmean from the isosurface sums) on a spherical isotherm of
+    radius 10: the oracle's value to 1e-9, and 10 cells to 0.1 (the oracle's pin)."""
+    R0, n, edge = 10.0, 44, 8.0
+    prob = W.sphere3d(shape=(n, n, n), radius=R0, edge=edge, T_ig=1500.0, storage=W.STORE_F64)
+    c = np.array([(n - 1) / 2] * 3) + np.array([0.13, -0.21, 0.34])
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2).reshape(-1)
+    prob.T = 300.0 + 1200.0 * W.tanh_profile(R0 - r, edge)
+    prob.rho = W.lattice_density(np.full(prob.N, W.P_ATM), prob.T,
+                                 np.full(prob.N, W.mean_molar_mass(W.premixed_h2air_X(prob.mech, 0.8),
+                                                                    prob.mech.molar_mass)), prob.rho_ref)
+    s = lbm_mod.Solver(prob, storage=W.STORE_F64).init()
+    rg = s.mean_radius(900.0, centre=c)
+    from oracle import oracle as orc
+    tot = orc.OracleSim(prob).init().flame_speeds(900.0, centre=c)["totals"]
+    print(f"[mean radius] gpu {rg:.6f} oracle {tot[4] / tot[0]:.6f}", flush=True)
+    assert abs(rg - tot[4] / tot[0]) <= 1e-9 * R0
+    assert abs(rg - R0) < 0.1
+    s.close()
