@@ -69,21 +69,38 @@ def _problem(case):
         return W.config1()
     if case == "flame1d":
         return W.flame1d(nx=128, hot_cells=32)
-    return W.perturb_velocity(W.sphere3d(shape=(13, 10, 9), radius=3.0), 2e-3, 9)
+    if case == "flame_batch":      # x ghost cells per segment
+        return W.flame_batch(lengths=[60, 17, 40], phis=[1.0, 2.5, 0.7], hot_cells=12)
+    prob = W.perturb_velocity(W.sphere3d(shape=(13, 10, 9), radius=3.0), 2e-3, 9)
+    if case == "sphere3d_symmetry":   # mirror copies of the stored deviations
+        prob.bc = (W.BC_SYMMETRY, W.BC_OPEN, W.BC_SYMMETRY, W.BC_OPEN, W.BC_OPEN_U0, W.BC_SYMMETRY)
+    return prob
+
+
+def _oracle_one_step(prob, pop, T):
+    """The oracle's step from the given state; a batch is stepped lattice by lattice."""
+    want, want_T = np.zeros_like(pop), np.zeros_like(T)
+    parts = W.split_batch(prob)
+    for k, part in enumerate(parts):
+        idx = W.batch_nodes(prob, k) if prob.segments else np.arange(prob.N)
+        sim = orc.OracleSim(part)
+        sim.set_state(np.ascontiguousarray(pop[..., idx]), np.ascontiguousarray(T[idx]))
+        assert sim.step(1) == 0
+        w, wT = sim.state()
+        want[..., idx] = w
+        want_T[idx] = wT
+    return want, want_T
 
 
 @pytest.mark.parametrize("storage", [W.STORE_F16_DEV, W.STORE_BF16_DEV])
-@pytest.mark.parametrize("case", ["config1", "flame1d", "sphere3d"])
+@pytest.mark.parametrize("case", ["config1", "flame1d", "sphere3d", "sphere3d_symmetry", "flame_batch"])
 def test_one_step_within_format_rounding(lbm_mod, storage, case):
     prob = _problem(case)
     s = lbm_mod.Solver(prob, storage=storage).init()
     s.step(3)                                   # non-equilibrium parts, pending corrections
     nodes = np.arange(prob.N)
     pop, T = s.populations(nodes)
-    sim = orc.OracleSim(prob)
-    sim.set_state(pop, T)
-    assert sim.step(1) == 0
-    want, want_T = sim.state()
+    want, want_T = _oracle_one_step(prob, pop, T)
     s.step(1)
     got, got_T = s.populations(nodes)
     assert s.status() == 0
