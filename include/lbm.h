@@ -15,8 +15,10 @@
  *   - Velocity index i = (cx+1) + 3 (cy+1) + 9 (cz+1), c in {-1,0,1}^3.
  *   - Population sets s = 0..M-2 species, s = M-1 mixture f, s = M energy g.
  *   - All device pointers are caller-owned; the library never allocates or frees
- *     device memory.  Device work is enqueued on the given stream (a hipStream_t
- *     passed as void*, NULL = default stream) and is asynchronous; only
+ *     device memory (lbm_step_graph creates a capture stream and graph objects of
+ *     the HIP runtime, released by lbm_destroy).  Device work is enqueued on the
+ *     given stream (a hipStream_t passed as void*, NULL = default stream) and is
+ *     asynchronous; only lbm_create (table upload and tile timing),
  *     lbm_status_sync and lbm_step_timed wait for the device.
  *   - Every call returns an lbm_status; nothing aborts or throws across the ABI.
  *     On error, lbm_last_error(h) explains it (lbm_last_error(NULL) for errors of
@@ -38,7 +40,7 @@ typedef struct lbm_ctx *lbm_handle;
 typedef enum {
   LBM_OK = 0,
   LBM_ERR_ARG = -1,            /* invalid argument or descriptor                 */
-  LBM_ERR_UNSUPPORTED = -2,    /* valid but not provided by this build           */
+  LBM_ERR_UNSUPPORTED = -2,    /* valid but not provided by this library         */
   LBM_ERR_HIP = -3,            /* a HIP runtime call failed                      */
   LBM_ERR_WORKSPACE = -4,      /* workspace too small or misaligned              */
   LBM_ERR_DEVICE_ANOMALY = -5  /* lbm_status_sync found anomaly bits set         */
