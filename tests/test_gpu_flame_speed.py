@@ -68,3 +68,28 @@ def test_flame_speed_matches_oracle(lbm_mod, oracle_speed, storage):
     print(f"[storage={storage}] S_L gpu {speed:.6e} oracle {ref:.6e} cells/step, rel diff {rel:.2e}, "
           f"max front shift {np.abs(xs - ref_xs).max():.2e} cells", flush=True)
     assert rel <= 5e-3
+
+
+def test_full_size_flame_speed_fp32_against_fp64(lbm_mod):
+    """The 4096-cell flame over 20 000 steps: S_L from a least-squares line through the
+    front position every 100 steps over steps 10 000..20 000, FP32 storage against FP64
+    storage (both on the GPU; the FP64 path is the oracle's to 1e-12 at this size),
+    within 0.5%.  The oracle itself would take minutes for this run."""
+    speeds = {}
+    for storage in (W.STORE_F64, W.STORE_F32):
+        prob = W.flame1d(nx=4096)
+        s = lbm_mod.Solver(prob, storage=storage).init()
+        xs, ts = [], []
+        for n in range(100, 20001, 100):
+            s.step_graph(100)
+            if n >= 10000:
+                xs.append(front(s.macros()["T"], 300.0))
+                ts.append(n)
+        assert s.status() == 0
+        speeds[storage] = -np.polyfit(np.array(ts, float), np.array(xs), 1)[0]
+        s.close()
+    ref, got = speeds[W.STORE_F64], speeds[W.STORE_F32]
+    rel = abs(got - ref) / ref
+    print(f"[flame1d 4096, 20k steps] S_L fp64 {ref:.6e} fp32 {got:.6e} cells/step, rel diff {rel:.2e}", flush=True)
+    assert ref > 0.003
+    assert rel <= 5e-3
