@@ -300,3 +300,13 @@ def test_flame1d_full_size_4096_fp32_1000_steps(lbm_mod):
     print(f"[flame1d 4096 fp32 1000] flow {max(flow.values()):.3e}, Y {max(ys.values()):.3e}", flush=True)
     assert max(flow.values()) <= TOL32, flow
     assert max(ys.values()) <= TOL32_Y_IGNITION, ys
+
+
+def test_sphere3d_32_crop_fp32_200_steps(lbm_mod):
+    """The spherical flame's initial condition on a 32^3 crop, FP32 storage, 200 steps
+    against the oracle: 1e-5 on every field."""
+    prob = W.sphere3d(shape=(32, 32, 32))
+    s, mac, bits = _gpu_run(lbm_mod, prob, 200, W.STORE_F32)
+    sim, anom = oracle_run(prob, 200)
+    assert bits == 0 and anom == 0
+    _assert_fields(mac, sim.macros(), prob, TOL32, "sphere3d 32^3 fp32 200")
