@@ -103,3 +103,27 @@ def test_isosurface_weights_measure_area_and_radius():
     simp = orc.OracleSim(plan).init()
     fp = simp.flame_speeds(T_iso=352.5)
     np.testing.assert_allclose(fp["totals"][0], 1.0, rtol=1e-9)
+
+
+def test_front_velocity_matches_absolute_speed_on_the_isoline():
+    """The front-tracking flame speed (the first crossing of T = 3 T_u, as the flame-speed
+    parity measures it) against the isoline mean of S_a from eq. sd at the same time,
+    over the quasi-1D flame's propagation (steps 1500..3500): the isotherm moves at its
+    absolute speed, so the two agree to the interpolation of the front between nodes
+    (measured within 4%; bar 6%)."""
+    def front(T, T_u=300.0):
+        k = int(np.nonzero(T >= 3.0 * T_u)[0][0])
+        return k - 1 + (3.0 * T_u - T[k - 1]) / (T[k] - T[k - 1])
+
+    sim = orc.OracleSim(W.flame1d(nx=512, hot_cells=64)).init()
+    assert sim.step(1500, 8) == 0
+    for k in range(6):
+        x0 = front(sim.macros()["T"])
+        sim.step(25, 8)
+        fs = sim.flame_speeds(900.0)
+        s_a = fs["totals"][2] / fs["totals"][0]
+        sim.step(25, 8)
+        speed = -(front(sim.macros()["T"]) - x0) / 50.0   # the flame moves toward -x
+        print(f"[step {1525 + 400 * k}] front {speed:.5e}, S_a {s_a:.5e}")
+        assert speed > 0.005 and abs(s_a - speed) <= 0.06 * speed
+        sim.step(350, 8)
