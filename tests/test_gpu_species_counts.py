@@ -84,3 +84,29 @@ def test_species_count_fp64(lbm_mod, M):
     assert max(err.values()) <= 1e-12, err
     assert max(pop_errors(pop, sim.state()[0])) <= 1e-12
     s.close()
+
+
+def test_max_reaction_count_fp64(lbm_mod):
+    """LBM_MAX_REACTIONS = 64 reactions: the 19 of the synthetic mechanism repeated with
+    their pre-exponential factors divided by 4 (the repeats add up like one faster
+    reaction), on the M = 9 lattice."""
+    prob = problem(9)
+    mech = prob.mech
+    reps = -(-64 // mech.R)
+    idx = np.arange(64) % mech.R
+    arr = mech.arrhenius[idx].copy()
+    arr[:, 0] = arr[:, 0] / 4.0
+    mech64 = dataclasses.replace(mech, nu_reac=mech.nu_reac[idx], nu_prod=mech.nu_prod[idx], arrhenius=arr,
+                                 reversible=mech.reversible[idx])
+    prob = dataclasses.replace(prob, mech=mech64, name="M9_R64")
+    assert prob.mech.R == 64 and reps >= 3
+    s = lbm_mod.Solver(prob, storage=W.STORE_F64).init()
+    s.step(30)
+    mac = s.macros()
+    assert s.status() == 0
+    sim, anom = oracle_run(prob, 30)
+    assert anom == 0
+    err = field_errors(mac, sim.macros(), zeta_of(prob))
+    print(f"[M=9 R=64] worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
+    assert max(err.values()) <= 1e-12, err
+    s.close()
