@@ -21,8 +21,8 @@ def _central(f):
     return 0.5 * (np.concatenate([f[1:], f[-1:]]) - np.concatenate([f[:1], f[:-1]]))
 
 
-def _run(prob, settle):
-    sim = orc.OracleSim(prob).init()
+def _run(prob, settle, lib=None):
+    sim = orc.OracleSim(prob, lib=lib).init()
     sim.step(settle, 8)
     m0 = sim.macros()
     sim.step(1, 8)

@@ -28,6 +28,15 @@ MUTANTS = {
     "beta_factor": ("f + 2.0 * d->beta[sp] * (feq - f)", "f + d->beta[sp] * (feq - f)"),
     "interspecies_sign": ("(d->beta[sp] - 1.0) * F + src;", "(1.0 - d->beta[sp]) * F + src;"),
     "grad_divisor": ("contr / (2.0 * THETA * THETA)", "contr / (THETA * THETA)"),
+    "psi_mirror_sign": ("iso_grad_v(s, fld, n, a, a);", "iso_grad_v(s, fld, n, a, -1);"),
+    "mirror_direction": ("const int im = mirror_dir(i, mirror);", "const int im = i;"),
+    "diff_T_inverted": ("pow(T / s->p.diff_T_ref, s->p.diff_T_exp)", "pow(s->p.diff_T_ref / T, s->p.diff_T_exp)"),
+    "visc_T_inverted": ("*om = 1.0 / (0.5 + (1.0 / s->p.omega - 0.5) * sc);",
+                        "*om = 1.0 / (0.5 + (1.0 / s->p.omega - 0.5) / sc);"),
+    "sd_drop_enthalpy_flux": ("Sd = (hrr + div - d[n].rho * flux)", "Sd = (hrr + div)"),
+    "sd_lambda_factor": ("lam[n] = (1.0 / om1 - 0.5) * d[n].P * cp[n];", "lam[n] = (1.0 / om1) * d[n].P * cp[n];"),
+    "sa_sign": ("for (int a = 0; a < 3; ++a) un -= d[n].u[a] * gT[a * N + n] / mag;",
+                "for (int a = 0; a < 3; ++a) un += d[n].u[a] * gT[a * N + n] / mag;"),
     "psi_sign": ("if (c == 1) return 0.5 * (xi + s);", "if (c == 1) return 0.5 * (-xi + s);"),
     "kc_sign": ("const double Kc = exp(-dG) * pow(c0, dnu);", "const double Kc = exp(dG) * pow(c0, dnu);"),
     "kinetic_energy_half": ("E - usq / 2.0, T_start", "E - usq, T_start"),
@@ -232,18 +241,63 @@ def pin_sound_galilean(lib):
     return bool(g0 > 0 and abs(g1 / g0 - 1) < 0.15)
 
 
+def pin_symmetry_face(lib):
+    """A half lattice with a symmetry face against the mirror-symmetric full lattice."""
+    from test_oracle_symmetry import _mirror_pair
+    fm, hm, keep = _mirror_pair(0, L=4, other=(3, 2), steps=20, lib=lib)
+    return bool(np.abs(hm["T"] - fm["T"][keep]).max() <= 1e-12 * fm["T"].max()
+                and np.abs(hm["u"][0] - fm["u"][0][keep]).max() <= 1e-12 * np.sqrt(0.05))
+
+
+def pin_transport_laws(lib):
+    """Binary decay at D_ref (T/T_ref)^n k^2 and shear decay at (1/omega(T) - 1/2) R T k^2."""
+    L, T = 48, 1000.0
+    X1 = 0.5 + 1e-3 * np.sin(2 * math.pi * np.arange(L) / L)
+    prob = lattice_problem(two_species(), L, X=np.stack([X1, 1 - X1]), D=0.02, T=T)
+    prob.diff_T_ref, prob.diff_T_exp = 500.0, 1.5
+    r = _rate(orc.OracleSim(prob, lib=lib).init(), lambda m: m["Y"][0] - m["Y"][0].mean(), L, 4, 200)
+    ok = abs(r / (0.02 * 2.0 ** 1.5 * (2 * math.pi / L) ** 2) - 1) < 0.02
+    u = np.zeros((3, L))
+    u[1] = 1e-3 * np.sin(2 * math.pi * np.arange(L) / L)
+    prob = lattice_problem(two_species(), L, u=u, omega=1.6, T=T)
+    prob.visc_T_ref, prob.visc_T_exp = 500.0, 0.7
+    nu = (1 / 1.6 - 0.5) * 2.0 ** 0.7 * prob.kappa * W.R_U * T / 28e-3
+    r = _rate(orc.OracleSim(prob, lib=lib).init(), lambda m: m["u"][1], L, 4, 150)
+    return bool(ok and abs(r / (nu * (2 * math.pi / L) ** 2) - 1) < 0.02)
+
+
+def pin_front_speeds(lib):
+    """S_d and S_a move the isotherms (the conduction and enthalpy-diffusion cases of the
+    flame-speed pins)."""
+    from test_oracle_flame_speeds import CASES, _run
+    for case in ("conduction", "enthalpy diffusion"):
+        make, settle, frac, tol = CASES[case]
+        fs, g, u, dTdt, pw = _run(make(), settle, lib=lib)
+        mag = np.abs(g)
+        sel = mag > frac * mag.max()
+        DTDt = dTdt + u * g
+        if np.abs(fs["Sd"] * mag + pw - DTDt)[sel].max() > tol * np.abs(DTDt[sel]).max():
+            return False
+        if np.abs(fs["Sa"] * mag + pw - dTdt)[sel].max() > tol * np.abs(dTdt[sel]).max():
+            return False
+    return True
+
+
 BATTERY = [pin_viscous_work, pin_sound_galilean, pin_moments, pin_collision, pin_conservation, pin_init_round_trip, pin_fick, pin_shear,
            pin_thermal, pin_interdiffusion, pin_reactor, pin_equilibrium, pin_iso_grad, pin_advection,
-           pin_open_boundary]
+           pin_open_boundary, pin_symmetry_face, pin_transport_laws, pin_front_speeds]
 
 
-def _run_battery(lib):
+def _run_battery(lib, stop_at_failure=False):
+    """Results of the pins on lib; with stop_at_failure, up to the first pin that fails."""
     res = {}
     for pin in BATTERY:
         try:
             res[pin.__name__] = pin(lib)
         except (ValueError, FloatingPointError, np.linalg.LinAlgError):
             res[pin.__name__] = False
+        if stop_at_failure and not res[pin.__name__]:
+            break
     return res
 
 
@@ -268,5 +322,5 @@ def test_pins_catch_planted_mistake(name, mutant_dir):
     (d / "oracle.c").write_text(src.replace(old, new))
     so = obuild.build(src=str(d / "oracle.c"), out=str(d / "liboracle_mutant.so"))
     with np.errstate(all="ignore"):
-        res = _run_battery(orc.load(so))
+        res = _run_battery(orc.load(so), stop_at_failure=True)
     assert not all(res.values()), f"no pin caught mutant {name}"

@@ -55,10 +55,10 @@ def mirror_problems(axis, L, other=(4, 2), seed=3):
     return full, half, keep
 
 
-def _mirror_pair(axis, L, other=(4, 2), seed=3, steps=40):
+def _mirror_pair(axis, L, other=(4, 2), seed=3, steps=40, lib=None):
     full, half, keep = mirror_problems(axis, L, other, seed)
-    fs = orc.OracleSim(full).init()
-    hs = orc.OracleSim(half).init()
+    fs = orc.OracleSim(full, lib=lib).init()
+    hs = orc.OracleSim(half, lib=lib).init()
     assert fs.step(steps, 4) == 0 and hs.step(steps, 4) == 0
     return fs.macros(), hs.macros(), keep
 
