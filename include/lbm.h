@@ -168,7 +168,9 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
  * stencil that suit the lattice (four launches each, on the default stream) and keeps
  * the fastest; LBM_CORR_TILE=k in the environment (0-2 for lattices with a
  * cross-section, 3-5 for lattices one node thick in y and z) picks shape k instead.
- * Every shape gives the same bits. */
+ * Every shape gives the same bits.  The timing overwrites the side channel and the
+ * deferred corrections in the workspace, so a state left there by another handle is
+ * not kept: start from lbm_init_fields. */
 lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm_handle *out);
 
 /* Release the host handle (the workspace is untouched). */
