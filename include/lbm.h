@@ -249,6 +249,20 @@ lbm_status lbm_diagnostics(lbm_handle h, double T_iso, double *d_hrr, double *d_
 lbm_status lbm_flame_speeds(lbm_handle h, double T_iso, const double *centre, double *d_work,
                             double *d_out, double *d_totals, void *stream);
 
+/* lbm_flame_speeds without the caller's work buffer, for callers that cannot allocate
+ * device memory (code under graph capture, serving loops that forbid allocation).  Same
+ * kernels and results as lbm_flame_speeds; the work fields and partial sums live in a
+ * scratch array of the library in device memory, one per GPU, held until the process
+ * ends (LBM_FLAME_STATIC_MAX_NODES x LBM_FLAME_WORK doubles plus the partial sums,
+ * about 9 MB).  Allocates nothing.  Lattices of more than LBM_FLAME_STATIC_MAX_NODES
+ * nodes are rejected with LBM_ERR_ARG.  Every call on one GPU, from any handle, uses
+ * the same scratch array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller.  d_out and d_totals as in lbm_flame_speeds
+ * (either may be NULL). */
+#define LBM_FLAME_STATIC_MAX_NODES 65536
+lbm_status lbm_flame_speeds_static(lbm_handle h, double T_iso, const double *centre, double *d_out,
+                                   double *d_totals, void *stream);
+
 /* Discrete adjoint of one step.  Not provided by this build: returns
  * LBM_ERR_UNSUPPORTED. */
 lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, double *d_grad_params,

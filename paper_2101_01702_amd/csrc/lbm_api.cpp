@@ -537,6 +537,13 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
     delete h;
     return s;
   }
+  // the device address of the scratch array of lbm_flame_speeds_static, once per device
+  e = flame_scratch_resolve(h->device);
+  if (e != hipSuccess) {
+    lbm_status s = hip_fail(nullptr, e, "resolving the scratch array of lbm_flame_speeds_static");
+    delete h;
+    return s;
+  }
   e = tune_corr_tile(h, ws);
   if (e != hipSuccess) {
     lbm_status s = hip_fail(nullptr, e, "timing the correction tiles");
@@ -714,6 +721,29 @@ lbm_status lbm_flame_speeds(lbm_handle h, double T_iso, const double *centre, do
   hipError_t e = launch_flame(h->g, h->b, h->kc, h->d.storage, h->cur, T_iso, c, d_work, d_out, d_totals,
                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(h, e, "flame speeds");
+  return LBM_OK;
+}
+
+lbm_status lbm_flame_speeds_static(lbm_handle h, double T_iso, const double *centre, double *d_out,
+                                   double *d_totals, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!std::isfinite(T_iso)) return arg_fail(h, "T_iso must be finite");
+  if (h->g.N > LBM_FLAME_STATIC_MAX_NODES) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "lattice has %lld nodes; lbm_flame_speeds_static takes at most %d",
+             (long long)h->g.N, LBM_FLAME_STATIC_MAX_NODES);
+    return arg_fail(h, buf);
+  }
+  if (!d_out && !d_totals) return LBM_OK;
+  double c[3] = {0.0, 0.0, 0.0};
+  if (centre)
+    for (int k = 0; k < 3; ++k) {
+      if (!std::isfinite(centre[k])) return arg_fail(h, "centre must be finite");
+      c[k] = centre[k];
+    }
+  hipError_t e = launch_flame_static(h->g, h->b, h->kc, h->d.storage, h->cur, h->device, T_iso, c, d_out,
+                                     d_totals, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "flame speeds (static scratch)");
   return LBM_OK;
 }
 

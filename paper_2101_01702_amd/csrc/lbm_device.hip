@@ -16,6 +16,7 @@
 // kernels compute them from a small side channel, and the next pull adds them back
 // to each population as it is read (deferred correction).  One step therefore moves
 // each population through HBM once in and once out.
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -2216,7 +2217,8 @@ inline bool any_symmetry(const Geom &g) {
 template <int M, typename ST, typename RT>
 struct RunFlame {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double T_iso,
-                        const double *centre, double *work, double *out, double *totals, hipStream_t st) {
+                        const double *centre, double *work, double *part, double *out, double *totals,
+                        hipStream_t st) {
     hipLaunchKernelGGL((k_fs_local<M, ST, RT>), dim3(blocks_for(g.N, 128)), dim3(128), 0, st, g, b, kc, cur, work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -2225,11 +2227,11 @@ struct RunFlame {
     if (e != hipSuccess) return e;
     const unsigned nb = blocks_for(g.N, DIAG_BLOCK);
     hipLaunchKernelGGL(k_fs_final, dim3(nb), dim3(DIAG_BLOCK), 0, st, g, (const double *)work, T_iso, centre[0],
-                       centre[1], centre[2], out, b.diag);
+                       centre[1], centre[2], out, part);
     e = hipGetLastError();
     if (e == hipSuccess && totals) {
-      hipLaunchKernelGGL(k_diag_sum, dim3(LBM_FLAME_TOTALS), dim3(DIAG_SUM_BLOCK), 0, st, b.diag, (int64_t)nb,
-                         totals);
+      hipLaunchKernelGGL(k_diag_sum, dim3(LBM_FLAME_TOTALS), dim3(DIAG_SUM_BLOCK), 0, st, (const double *)part,
+                         (int64_t)nb, totals);
       e = hipGetLastError();
     }
     return e;
@@ -2319,7 +2321,50 @@ hipError_t launch_diag(const Geom &g, const Buffers &b, const CollideConsts &kc,
 
 hipError_t launch_flame(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
                         const double *centre, double *work, double *out, double *totals, hipStream_t st) {
-  return dispatch<RunFlame>(g.M, store, g, b, kc, cur, T_iso, centre, work, out, totals, st);
+  return dispatch<RunFlame>(g.M, store, g, b, kc, cur, T_iso, centre, work, b.diag, out, totals, st);
+}
+
+// ---- scratch of the allocation-free flame speeds ----------------------------------------
+// The work fields (LBM_FLAME_WORK per node) and the per-workgroup partial sums of
+// lbm_flame_speeds_static, for lattices of up to LBM_FLAME_STATIC_MAX_NODES nodes.  Each
+// device holds its own copy for the life of the process.  Host code never passes the
+// name `scratch` to a kernel: it stands for the host shadow of the symbol, not a device
+// address.  The address on each device is resolved once, with that device current, and
+// kept in flame_scratch_ptr.
+constexpr int64_t FLAME_STATIC_PARTS = (LBM_FLAME_STATIC_MAX_NODES + DIAG_BLOCK - 1) / DIAG_BLOCK;
+constexpr int64_t FLAME_STATIC_WORDS =
+    (int64_t)LBM_FLAME_WORK * LBM_FLAME_STATIC_MAX_NODES + (int64_t)LBM_FLAME_TOTALS * FLAME_STATIC_PARTS;
+static __device__ __align__(256) double scratch[FLAME_STATIC_WORDS];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex flame_scratch_mu;
+static double *flame_scratch_ptr[MAX_DEVICES];
+
+hipError_t flame_scratch_resolve(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(flame_scratch_mu);
+  if (flame_scratch_ptr[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  flame_scratch_ptr[device] = static_cast<double *>(p);
+  return hipSuccess;
+}
+
+hipError_t launch_flame_static(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                               int device, double T_iso, const double *centre, double *out, double *totals,
+                               hipStream_t st) {
+  if (g.N > LBM_FLAME_STATIC_MAX_NODES) return hipErrorInvalidValue;
+  double *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(flame_scratch_mu);
+    if (device >= 0 && device < MAX_DEVICES) base = flame_scratch_ptr[device];
+  }
+  if (!base) return hipErrorInvalidSymbol;   // not resolved by lbm_create on this device
+  double *work = base;
+  double *part = base + (int64_t)LBM_FLAME_WORK * LBM_FLAME_STATIC_MAX_NODES;
+  return dispatch<RunFlame>(g.M, store, g, b, kc, cur, T_iso, centre, work, part, out, totals, st);
 }
 
 hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,

@@ -122,5 +122,12 @@ hipError_t launch_diag(const Geom &g, const Buffers &b, const CollideConsts &kc,
 hipError_t launch_flame(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
                         const double *centre, double *work, double *out, double *totals, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st);
+// the scratch array of lbm_flame_speeds_static: its address on `device` (the current
+// device) is resolved once per device; then the flame speeds with their work fields and
+// partial sums in it (g.N <= LBM_FLAME_STATIC_MAX_NODES)
+hipError_t flame_scratch_resolve(int device);
+hipError_t launch_flame_static(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
+                               int device, double T_iso, const double *centre, double *out, double *totals,
+                               hipStream_t st);
 
 }  // namespace lbm

@@ -56,11 +56,12 @@ _lib = None
 
 EXPORTS = ("lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_step",
            "lbm_step_timed", "lbm_step_graph", "lbm_macros", "lbm_populations", "lbm_diagnostics",
-           "lbm_flame_speeds", "lbm_adjoint_step",
+           "lbm_flame_speeds", "lbm_flame_speeds_static", "lbm_adjoint_step",
            "lbm_status_sync", "lbm_last_error")
 DIAG_TOTALS = 4   # heat release rate, nodes with T >= T_iso, mass, total energy
 FLAME_WORK = 17   # FP64 work fields per node of lbm_flame_speeds
 FLAME_TOTALS = 5  # sum w, sum w S_d, sum w S_a, sum w rho S_d, sum w |x - centre|
+FLAME_STATIC_MAX_NODES = 65536   # largest lattice of lbm_flame_speeds_static
 
 
 def load(path: Optional[str] = None):
@@ -84,6 +85,7 @@ def load(path: Optional[str] = None):
     lib.lbm_populations.argtypes = [vp, vp, C.c_int64, vp, vp, vp]
     lib.lbm_diagnostics.argtypes = [vp, C.c_double, vp, vp, vp]
     lib.lbm_flame_speeds.argtypes = [vp, C.c_double, C.POINTER(C.c_double), vp, vp, vp, vp]
+    lib.lbm_flame_speeds_static.argtypes = [vp, C.c_double, C.POINTER(C.c_double), vp, vp, vp]
     lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp]
     lib.lbm_status_sync.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     lib.lbm_last_error.argtypes = [vp]
@@ -276,6 +278,22 @@ class Solver:
         self._check(self.lib.lbm_flame_speeds(self.h, float(T_iso), c, C.c_void_p(work.data_ptr()),
                                               C.c_void_p(out.data_ptr()), C.c_void_p(tot.data_ptr()),
                                               self._stream()), self.h)
+        if to_numpy:
+            t.cuda.synchronize(self.device)
+            o = out.cpu().numpy()
+            return dict(Sd=o[0], Sa=o[1], w=o[2], totals=tot.cpu().numpy())
+        return dict(Sd=out[0], Sa=out[1], w=out[2], totals=tot)
+
+    def flame_speeds_static(self, T_iso: float, centre=(0.0, 0.0, 0.0), to_numpy: bool = True):
+        """``flame_speeds`` through lbm_flame_speeds_static: no work buffer is passed, the
+        library's per-GPU scratch array holds the work fields (lattices of at most
+        FLAME_STATIC_MAX_NODES nodes)."""
+        t = self.torch
+        out = t.empty(3, self.N, dtype=t.float64, device=self.device)
+        tot = t.empty(FLAME_TOTALS, dtype=t.float64, device=self.device)
+        c = (C.c_double * 3)(*[float(v) for v in centre])
+        self._check(self.lib.lbm_flame_speeds_static(self.h, float(T_iso), c, C.c_void_p(out.data_ptr()),
+                                                     C.c_void_p(tot.data_ptr()), self._stream()), self.h)
         if to_numpy:
             t.cuda.synchronize(self.device)
             o = out.cpu().numpy()

@@ -197,6 +197,7 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lbm_diagnostics(None, 1000.0, None, None, None) == -1
     assert lib.lbm_step_graph(None, 2, None) == -1
     assert lib.lbm_flame_speeds(None, 900.0, None, None, None, None, None) == -1
+    assert lib.lbm_flame_speeds_static(None, 900.0, None, None, None, None) == -1
     assert lib.lbm_adjoint_step(None, None, None, None, None) == -2
 
 
