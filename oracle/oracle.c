@@ -45,6 +45,15 @@
 #define Q ORC_Q
 #define MAXM ORC_MAXM
 
+/* Arithmetic type of every quantity that depends on the state or on the Arrhenius
+ * parameters.  Plain double here.  The reverse sweep (oracle_ad.cpp) compiles this
+ * same file with a type that records each operation on a tape in its place, so that
+ * its derivatives come from exactly these steps.  ORC_VAL gives the double value. */
+#ifndef ORC_REAL
+typedef double real;
+#define ORC_VAL(x) (x)
+#endif
+
 static const double R_UNIV = 8.314462618;   /* J/(mol K) */
 static const double THETA = 1.0 / 3.0;      /* lattice reference temperature (Sec. 3) */
 
@@ -60,43 +69,43 @@ static double weight(int i) { return w1d(CX(i)) * w1d(CY(i)) * w1d(CZ(i)); }
 
 typedef struct {
   /* O1: moments */
-  double rho, j[3], u[3], Pt[3][3], rhoE, q[3];
-  double rho_a[MAXM], j_a[MAXM][3], u_a[MAXM][3], Y[MAXM];
+  real rho, j[3], u[3], Pt[3][3], rhoE, q[3];
+  real rho_a[MAXM], j_a[MAXM][3], u_a[MAXM][3], Y[MAXM];
   /* O2: temperature and thermodynamics */
-  double T, m, zeta, zeta_a[MAXM], P, H, H_a[MAXM];
+  real T, m, zeta, zeta_a[MAXM], P, H, H_a[MAXM];
   int newton_iters;
   /* O3: chemistry */
-  double rdot[MAXM];
+  real rdot[MAXM];
   /* O4: Stefan-Maxwell */
-  double K[MAXM][MAXM], inv_tau[MAXM], beta[MAXM], du[MAXM][3];
+  real K[MAXM][MAXM], inv_tau[MAXM], beta[MAXM], du[MAXM][3];
   /* O5/O6: non-local fields */
-  double phi[3], psi[3], X[3], gradY[MAXM][3];
+  real phi[3], psi[3], X[3], gradY[MAXM][3];
 } node_t;
 
 struct orc_sim {
   orc_problem p;
   double molar_mass[MAXM], nasa7[MAXM][7], diff[MAXM][MAXM];
   int32_t nu_reac[ORC_MAXR][MAXM], nu_prod[ORC_MAXR][MAXM];
-  double arrh[ORC_MAXR][3];
+  real arrh[ORC_MAXR][3];
   uint8_t reversible[ORC_MAXR];
   int64_t N;
   int S;
-  double *pop;    /* [S][Q][N] pre-collision, current time */
-  double *post;   /* [S][Q][N] post-collision of the last step */
+  real *pop;      /* [S][Q][N] pre-collision, current time */
+  real *post;     /* [S][Q][N] post-collision of the last step */
   double *Tstore; /* [N] temperature, Newton start value */
   node_t *nd;     /* [N] per-node quantities of the last step */
-  double *scratch;/* [N] */
+  real *scratch;  /* [N] */
 };
 
 /* ---- thermodynamics (Sec. 3 eq. specHa, Umix; NASA-7 form) ------------------------- */
-static double cp_R(const double *a, double T) {
+static real cp_R(const double *a, real T) {
   return a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T;
 }
-static double h_RT(const double *a, double T) {
+static real h_RT(const double *a, real T) {
   return a[0] + a[1] * T / 2.0 + a[2] * T * T / 3.0 + a[3] * T * T * T / 4.0 +
          a[4] * T * T * T * T / 5.0 + a[5] / T;
 }
-static double s_R(const double *a, double T) {
+static real s_R(const double *a, real T) {
   return a[0] * log(T) + a[1] * T + a[2] * T * T / 2.0 + a[3] * T * T * T / 3.0 +
          a[4] * T * T * T * T / 4.0 + a[6];
 }
@@ -105,34 +114,34 @@ static double gas_const(const orc_sim *s, int a) {
   return s->p.kappa * R_UNIV / (s->molar_mass[a] * 1e-3);
 }
 /* U_a = U_a^0 + int C_v: the NASA-7 enthalpy already contains the formation part */
-static double spec_U(const orc_sim *s, int a, double T) {
+static real spec_U(const orc_sim *s, int a, real T) {
   return gas_const(s, a) * T * (h_RT(s->nasa7[a], T) - 1.0);
 }
-static double spec_H(const orc_sim *s, int a, double T) {
+static real spec_H(const orc_sim *s, int a, real T) {
   return gas_const(s, a) * T * h_RT(s->nasa7[a], T);
 }
-static double spec_Cv(const orc_sim *s, int a, double T) {
+static real spec_Cv(const orc_sim *s, int a, real T) {
   return gas_const(s, a) * (cp_R(s->nasa7[a], T) - 1.0);
 }
 
 /* ---- product-form functions (eq. phis) and populations (eqs. feq, fstar, fsource) -- */
-static double psi1d(int c, double xi, double zeta) {
-  const double s = xi * xi + zeta;
+static real psi1d(int c, real xi, real zeta) {
+  const real s = xi * xi + zeta;
   if (c == 0) return 1.0 - s;
   if (c == 1) return 0.5 * (xi + s);
   return 0.5 * (-xi + s);
 }
-static double product_form(int i, double dens, const double v[3], double zeta) {
+static real product_form(int i, real dens, const real v[3], real zeta) {
   return dens * psi1d(CX(i), v[0], zeta) * psi1d(CY(i), v[1], zeta) * psi1d(CZ(i), v[2], zeta);
 }
 
 /* ---- Grad approximation for g (eqs. gieq, giqeq) ---------------------------------- */
-static double grad_form(int i, double rhoE, const double q[3], const double Rt[3][3]) {
-  double qc = 0.0, contr = 0.0;
+static real grad_form(int i, real rhoE, const real q[3], const real Rt[3][3]) {
+  real qc = 0.0, contr = 0.0;
   for (int a = 0; a < 3; ++a) qc += q[a] * CI(i, a);
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
-      const double lhs = Rt[a][b] - (a == b ? rhoE * THETA : 0.0);
+      const real lhs = Rt[a][b] - (a == b ? rhoE * THETA : (real)0.0);
       const double rhs = CI(i, a) * CI(i, b) - (a == b ? THETA : 0.0);
       contr += lhs * rhs;
     }
@@ -141,30 +150,30 @@ static double grad_form(int i, double rhoE, const double q[3], const double Rt[3
 
 /* equilibrium energy flux and second moment (eqs. geq1mom, geq2mom) with
  * P^eq = rho R T I + rho u u */
-static void energy_eq_moments(double rho, const double u[3], double zeta, double H,
-                              double qeq[3], double Peq[3][3], double Req[3][3]) {
-  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const double P = rho * zeta;
+static void energy_eq_moments(real rho, const real u[3], real zeta, real H,
+                              real qeq[3], real Peq[3][3], real Req[3][3]) {
+  const real usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const real P = rho * zeta;
   for (int a = 0; a < 3; ++a) {
     qeq[a] = (H + usq / 2.0) * rho * u[a];
     for (int b = 0; b < 3; ++b) {
-      Peq[a][b] = (a == b ? rho * zeta : 0.0) + rho * u[a] * u[b];
+      Peq[a][b] = (a == b ? rho * zeta : (real)0.0) + rho * u[a] * u[b];
       Req[a][b] = (H + usq / 2.0) * Peq[a][b] + P * u[a] * u[b];
     }
   }
 }
 
 /* ---- temperature from energy (eq. temperature), Newton ----------------------------- */
-static int temperature(const orc_sim *s, const double *Y, double e_target, double T_start,
-                       double *T_out) {
-  double T = T_start;
+static int temperature(const orc_sim *s, const real *Y, real e_target, double T_start,
+                       real *T_out) {
+  real T = T_start;
   for (int it = 1; it <= 50; ++it) {
-    double e = -e_target, de = 0.0;
+    real e = -e_target, de = 0.0;
     for (int a = 0; a < s->p.M; ++a) {
       e += Y[a] * spec_U(s, a, T);
       de += Y[a] * spec_Cv(s, a, T);
     }
-    const double dT = -e / de;
+    const real dT = -e / de;
     T += dT;
     if (fabs(dT) <= 1e-12 * fabs(T)) {
       *T_out = T;
@@ -176,36 +185,37 @@ static int temperature(const orc_sim *s, const double *Y, double e_target, doubl
 }
 
 /* ---- production rates (Sec. 4 item 3; mass action with K_c from NASA-7 Gibbs) ----- */
-static void production_rates(const orc_sim *s, const double *rho_a, double T, double *rdot) {
+static void production_rates(const orc_sim *s, const real *rho_a, real T, real *rdot) {
   const int M = s->p.M;
-  double c[MAXM], g[MAXM], wdot[MAXM];
+  real c[MAXM], g[MAXM], wdot[MAXM];
   for (int a = 0; a < M; ++a) {
     c[a] = rho_a[a] * s->p.rho_ref / s->molar_mass[a];           /* mol/cm^3 */
     g[a] = h_RT(s->nasa7[a], T) - s_R(s->nasa7[a], T);           /* G_a/(R_U T) */
     wdot[a] = 0.0;
   }
   for (int k = 0; k < s->p.R; ++k) {
-    const double A = s->arrh[k][0], b = s->arrh[k][1], Ta = s->arrh[k][2];
-    const double kf = A * pow(T, b) * exp(-Ta / T);
-    double fwd = kf;
+    const real A = s->arrh[k][0], b = s->arrh[k][1], Ta = s->arrh[k][2];
+    const real kf = A * pow(T, b) * exp(-Ta / T);
+    real fwd = kf;
     for (int a = 0; a < M; ++a)
       for (int n = 0; n < s->nu_reac[k][a]; ++n) fwd *= c[a];
-    double rev = 0.0;
+    real rev = 0.0;
     if (s->reversible[k]) {
-      double dnu = 0.0, dG = 0.0;
+      double dnu = 0.0;
+      real dG = 0.0;
       for (int a = 0; a < M; ++a) {
         const double nu = (double)(s->nu_prod[k][a] - s->nu_reac[k][a]);
         dnu += nu;
         dG += nu * g[a];
       }
-      const double c0 = s->p.p0 / (R_UNIV * T) * 1e-6;            /* mol/cm^3 */
-      const double Kc = exp(-dG) * pow(c0, dnu);
-      const double kr = kf / Kc;
+      const real c0 = s->p.p0 / (R_UNIV * T) * 1e-6;              /* mol/cm^3 */
+      const real Kc = exp(-dG) * pow(c0, dnu);
+      const real kr = kf / Kc;
       rev = kr;
       for (int a = 0; a < M; ++a)
         for (int n = 0; n < s->nu_prod[k][a]; ++n) rev *= c[a];
     }
-    const double qk = fwd - rev;
+    const real qk = fwd - rev;
     for (int a = 0; a < M; ++a) wdot[a] += (double)(s->nu_prod[k][a] - s->nu_reac[k][a]) * qk;
   }
   /* g/(cm^3 s) -> lattice density per step */
@@ -216,7 +226,7 @@ static void production_rates(const orc_sim *s, const double *rho_a, double T, do
 /* binary diffusivity at temperature T: the given constant, or with a temperature
  * exponent the power law D_ab (T / T_ref)^n (a stand-in for the temperature-dependent
  * transport data of Sec. 3) */
-static double diffusivity(const orc_sim *s, int a, int b, double T) {
+static real diffusivity(const orc_sim *s, int a, int b, real T) {
   if (s->p.diff_T_exp == 0.0) return s->diff[a][b];
   return s->diff[a][b] * pow(T / s->p.diff_T_ref, s->p.diff_T_exp);
 }
@@ -225,30 +235,30 @@ static double diffusivity(const orc_sim *s, int a, int b, double T) {
  * exponent the rates whose viscosity and conductivity factors 1/omega - 1/2 and
  * 1/omega1 - 1/2 (eqs. mu, lambda) scale as (T / T_ref)^n (a stand-in for the
  * temperature-dependent transport data of Sec. 3) */
-static void relaxation_rates(const orc_sim *s, double T, double *om, double *om1) {
+static void relaxation_rates(const orc_sim *s, real T, real *om, real *om1) {
   if (s->p.visc_T_exp == 0.0) {
     *om = s->p.omega;
     *om1 = s->p.omega1;
     return;
   }
-  const double sc = pow(T / s->p.visc_T_ref, s->p.visc_T_exp);
+  const real sc = pow(T / s->p.visc_T_ref, s->p.visc_T_exp);
   *om = 1.0 / (0.5 + (1.0 / s->p.omega - 0.5) * sc);
   *om1 = 1.0 / (0.5 + (1.0 / s->p.omega1 - 0.5) * sc);
 }
 
 /* K_ab = 1/tau_ab with tau_ab = (m_a m_b / (m R_U T)) D_ab, written with lattice
  * R_a T: 1/tau_ab = (R_a T)(R_b T) / ((R T) D_ab). */
-static void relaxation(const orc_sim *s, const double *Y, const double *zeta_a, double zeta, double T,
-                       double K[MAXM][MAXM], double *inv_tau, double *beta) {
+static void relaxation(const orc_sim *s, const real *Y, const real *zeta_a, real zeta, real T,
+                       real K[MAXM][MAXM], real *inv_tau, real *beta) {
   const int M = s->p.M;
   for (int a = 0; a < M; ++a)
     for (int b = 0; b < M; ++b)
-      K[a][b] = (a == b) ? 0.0 : zeta_a[a] * zeta_a[b] / (zeta * diffusivity(s, a, b, T));
+      K[a][b] = (a == b) ? (real)0.0 : zeta_a[a] * zeta_a[b] / (zeta * diffusivity(s, a, b, T));
   for (int a = 0; a < M; ++a) {
     inv_tau[a] = 0.0;
     for (int b = 0; b < M; ++b)
       if (b != a) inv_tau[a] += Y[b] * K[a][b];
-    const double tau = 1.0 / inv_tau[a];
+    const real tau = 1.0 / inv_tau[a];
     beta[a] = 1.0 / (2.0 * tau + 1.0);
   }
 }
@@ -256,23 +266,23 @@ static void relaxation(const orc_sim *s, const double *Y, const double *zeta_a, 
 /* (1 + 1/(2 tau_a)) du_a - 1/2 sum_{b!=a} (1/tau_ab) Y_b du_b = u_a - u, for each
  * spatial component; Gaussian elimination (the matrix is strictly diagonally
  * dominant by rows, so no pivoting). */
-static void diffusion_velocities(int M, double K[MAXM][MAXM], const double *inv_tau,
-                                 const double *Y, const double rhs[MAXM][3], double du[MAXM][3]) {
-  double A[MAXM][MAXM], B[MAXM][3];
+static void diffusion_velocities(int M, real K[MAXM][MAXM], const real *inv_tau,
+                                 const real *Y, const real rhs[MAXM][3], real du[MAXM][3]) {
+  real A[MAXM][MAXM], B[MAXM][3];
   for (int a = 0; a < M; ++a) {
     for (int b = 0; b < M; ++b) A[a][b] = (a == b) ? 1.0 + 0.5 * inv_tau[a] : -0.5 * K[a][b] * Y[b];
     for (int d = 0; d < 3; ++d) B[a][d] = rhs[a][d];
   }
   for (int k = 0; k < M; ++k) {
     for (int r = k + 1; r < M; ++r) {
-      const double l = A[r][k] / A[k][k];
+      const real l = A[r][k] / A[k][k];
       for (int c = k; c < M; ++c) A[r][c] -= l * A[k][c];
       for (int d = 0; d < 3; ++d) B[r][d] -= l * B[k][d];
     }
   }
   for (int r = M - 1; r >= 0; --r)
     for (int d = 0; d < 3; ++d) {
-      double v = B[r][d];
+      real v = B[r][d];
       for (int c = r + 1; c < M; ++c) v -= A[r][c] * du[c][d];
       du[r][d] = v / A[r][r];
     }
@@ -316,17 +326,17 @@ static int64_t grad_neighbour(const orc_sim *s, int64_t n, int i, int *mirror) {
 /* isotropic lattice gradient, component alpha, of a nodal field that is a scalar
  * (vec_axis < 0) or the vec_axis component of a vector: that component changes sign
  * in the mirror image beyond a symmetry face normal to its axis */
-static double iso_grad_v(const orc_sim *s, const double *field, int64_t n, int alpha, int vec_axis) {
-  double acc = 0.0;
+static real iso_grad_v(const orc_sim *s, const real *field, int64_t n, int alpha, int vec_axis) {
+  real acc = 0.0;
   for (int i = 0; i < Q; ++i) {
     int mirror;
-    double v = field[grad_neighbour(s, n, i, &mirror)];
+    real v = field[grad_neighbour(s, n, i, &mirror)];
     if (vec_axis >= 0 && (mirror >> vec_axis & 1)) v = -v;
     acc += weight(i) * CI(i, alpha) * v;
   }
   return acc / THETA;
 }
-static double iso_grad(const orc_sim *s, const double *field, int64_t n, int alpha) {
+static real iso_grad(const orc_sim *s, const real *field, int64_t n, int alpha) {
   return iso_grad_v(s, field, n, alpha, -1);
 }
 
@@ -334,16 +344,16 @@ static double iso_grad(const orc_sim *s, const double *field, int64_t n, int alp
 static uint32_t node_local(const orc_sim *s, int64_t n, double T_start, node_t *d, int with_source) {
   const int M = s->p.M, S = s->S;
   const int64_t N = s->N;
-  const double *pf = s->pop + (int64_t)(M - 1) * Q * N;   /* mixture f */
-  const double *pg = s->pop + (int64_t)M * Q * N;         /* energy g */
+  const real *pf = s->pop + (int64_t)(M - 1) * Q * N;   /* mixture f */
+  const real *pg = s->pop + (int64_t)M * Q * N;         /* energy g */
   uint32_t anom = 0;
   (void)S;
   memset(d, 0, sizeof(*d));
 
   /* mixture moments (Sec. 3): rho, rho u, pressure tensor, rho E, q */
   for (int i = 0; i < Q; ++i) {
-    const double f = pf[(int64_t)i * N + n];
-    const double g = pg[(int64_t)i * N + n];
+    const real f = pf[(int64_t)i * N + n];
+    const real g = pg[(int64_t)i * N + n];
     d->rho += f;
     d->rhoE += g;
     for (int a = 0; a < 3; ++a) {
@@ -355,11 +365,11 @@ static uint32_t node_local(const orc_sim *s, int64_t n, double T_start, node_t *
   for (int a = 0; a < 3; ++a) d->u[a] = d->j[a] / d->rho;
 
   /* species moments (eq. Pa); the last species is slaved (eq. strongest) */
-  double rho_sum = 0.0, j_sum[3] = {0, 0, 0};
+  real rho_sum = 0.0, j_sum[3] = {0.0, 0.0, 0.0};
   for (int sp = 0; sp < M - 1; ++sp) {
-    const double *pa = s->pop + (int64_t)sp * Q * N;
+    const real *pa = s->pop + (int64_t)sp * Q * N;
     for (int i = 0; i < Q; ++i) {
-      const double f = pa[(int64_t)i * N + n];
+      const real f = pa[(int64_t)i * N + n];
       d->rho_a[sp] += f;
       for (int a = 0; a < 3; ++a) d->j_a[sp][a] += f * CI(i, a);
     }
@@ -376,11 +386,11 @@ static uint32_t node_local(const orc_sim *s, int64_t n, double T_start, node_t *
   if (!(d->rho > 0.0) || !(d->rho_a[M - 1] > 0.0)) anom |= ORC_ANOM_NEG_DENSITY;
 
   /* O2: temperature from E - u^2/2 (eq. temperature), then EOS (eq. eosIdealGas) */
-  const double usq = d->u[0] * d->u[0] + d->u[1] * d->u[1] + d->u[2] * d->u[2];
-  const double E = d->rhoE / d->rho;
+  const real usq = d->u[0] * d->u[0] + d->u[1] * d->u[1] + d->u[2] * d->u[2];
+  const real E = d->rhoE / d->rho;
   d->newton_iters = temperature(s, d->Y, E - usq / 2.0, T_start, &d->T);
   if (d->newton_iters < 0) anom |= ORC_ANOM_NEWTON;
-  double inv_m = 0.0;
+  real inv_m = 0.0;
   for (int sp = 0; sp < M; ++sp) inv_m += d->Y[sp] / s->molar_mass[sp];
   d->m = 1.0 / inv_m;
   d->zeta = s->p.kappa * R_UNIV * d->T / (d->m * 1e-3);
@@ -398,7 +408,7 @@ static uint32_t node_local(const orc_sim *s, int64_t n, double T_start, node_t *
 
   /* O4: relaxation times and diffusion velocities */
   relaxation(s, d->Y, d->zeta_a, d->zeta, d->T, d->K, d->inv_tau, d->beta);
-  double rhs[MAXM][3];
+  real rhs[MAXM][3];
   for (int sp = 0; sp < M; ++sp)
     for (int a = 0; a < 3; ++a) rhs[sp][a] = d->u_a[sp][a] - d->u[a];
   diffusion_velocities(M, d->K, d->inv_tau, d->Y, rhs, d->du);
@@ -416,18 +426,18 @@ static void collide(orc_sim *s, int64_t n) {
   const int M = s->p.M;
   const int64_t N = s->N;
   const node_t *d = &s->nd[n];
-  double om, om1;
+  real om, om1;
   relaxation_rates(s, d->T, &om, &om1);
 
   /* mixture f (eq. f) with the isotropy correction A_i . X (eq. Ai) */
   {
-    const double *pf = s->pop + (int64_t)(M - 1) * Q * N;
-    double *of = s->post + (int64_t)(M - 1) * Q * N;
+    const real *pf = s->pop + (int64_t)(M - 1) * Q * N;
+    real *of = s->post + (int64_t)(M - 1) * Q * N;
     for (int i = 0; i < Q; ++i) {
-      const double f = pf[(int64_t)i * N + n];
-      const double feq = product_form(i, d->rho, d->u, d->zeta);
+      const real f = pf[(int64_t)i * N + n];
+      const real feq = product_form(i, d->rho, d->u, d->zeta);
       const int c2 = CX(i) * CX(i) + CY(i) * CY(i) + CZ(i) * CZ(i);
-      double AX = 0.0;
+      real AX = 0.0;
       if (c2 == 1)
         for (int a = 0; a < 3; ++a) AX += 0.5 * CI(i, a) * d->X[a];
       of[(int64_t)i * N + n] = f + om * (feq - f) + AX;
@@ -436,67 +446,67 @@ static void collide(orc_sim *s, int64_t n) {
 
   /* species a < M (eq. finalNumericalEquations with F_ai of eq. fStar) */
   for (int sp = 0; sp < M - 1; ++sp) {
-    const double *pa = s->pop + (int64_t)sp * Q * N;
-    double *oa = s->post + (int64_t)sp * Q * N;
+    const real *pa = s->pop + (int64_t)sp * Q * N;
+    real *oa = s->post + (int64_t)sp * Q * N;
     for (int i = 0; i < Q; ++i) {
-      const double f = pa[(int64_t)i * N + n];
-      const double feq = product_form(i, d->rho_a[sp], d->u, d->zeta_a[sp]);
-      double F = 0.0;
+      const real f = pa[(int64_t)i * N + n];
+      const real feq = product_form(i, d->rho_a[sp], d->u, d->zeta_a[sp]);
+      real F = 0.0;
       for (int b = 0; b < M; ++b) {
         if (b == sp) continue;
-        double ub[3];
+        real ub[3];
         for (int a = 0; a < 3; ++a) ub[a] = d->u[a] + d->du[b][a];
-        const double feq_b = product_form(i, d->rho_a[b], d->u, d->zeta_a[b]);
-        const double fst_b = product_form(i, d->rho_a[b], ub, d->zeta_a[b]);
+        const real feq_b = product_form(i, d->rho_a[b], d->u, d->zeta_a[b]);
+        const real fst_b = product_form(i, d->rho_a[b], ub, d->zeta_a[b]);
         F += d->K[sp][b] * (feq_b - fst_b);
       }
       F *= d->Y[sp];
-      const double src = product_form(i, d->rdot[sp], d->u, d->zeta_a[sp]);   /* eq. fsource */
+      const real src = product_form(i, d->rdot[sp], d->u, d->zeta_a[sp]);   /* eq. fsource */
       oa[(int64_t)i * N + n] = f + 2.0 * d->beta[sp] * (feq - f) + (d->beta[sp] - 1.0) * F + src;
     }
   }
 
   /* energy g (eq. g) */
   {
-    const double *pg = s->pop + (int64_t)M * Q * N;
-    double *og = s->post + (int64_t)M * Q * N;
-    double qeq[3], Peq[3][3], Req[3][3];
+    const real *pg = s->pop + (int64_t)M * Q * N;
+    real *og = s->post + (int64_t)M * Q * N;
+    real qeq[3], Peq[3][3], Req[3][3];
     energy_eq_moments(d->rho, d->u, d->zeta, d->H, qeq, Peq, Req);
-    double hyd[3] = {0, 0, 0}, hgrad[3] = {0, 0, 0};
+    real hyd[3] = {0.0, 0.0, 0.0}, hgrad[3] = {0.0, 0.0, 0.0};
     for (int sp = 0; sp < M; ++sp)
       for (int a = 0; a < 3; ++a) {
         hyd[a] += d->H_a[sp] * d->Y[sp] * d->du[sp][a];
         hgrad[a] += d->H_a[sp] * d->gradY[sp][a];
       }
-    double qstar[3];
+    real qstar[3];
     for (int a = 0; a < 3; ++a) {
-      double uPdiff = 0.0;   /* (u . (P - P^eq))_a */
+      real uPdiff = 0.0;   /* (u . (P - P^eq))_a */
       for (int b = 0; b < 3; ++b) uPdiff += d->u[b] * (d->Pt[b][a] - Peq[b][a]);
-      const double qdiff = (om1 / (om - om1)) * d->rho * hyd[a];                 /* eq. qdiff */
-      const double qcorr = 0.5 * ((om1 - 2.0) / (om1 - om)) * d->P * hgrad[a];  /* eq. corrFourier */
+      const real qdiff = (om1 / (om - om1)) * d->rho * hyd[a];                 /* eq. qdiff */
+      const real qcorr = 0.5 * ((om1 - 2.0) / (om1 - om)) * d->P * hgrad[a];  /* eq. corrFourier */
       qstar[a] = d->q[a] - uPdiff + qdiff + qcorr;                               /* eq. gstareq1mom */
     }
     for (int i = 0; i < Q; ++i) {
-      const double g = pg[(int64_t)i * N + n];
-      const double geq = grad_form(i, d->rhoE, qeq, Req);
-      const double gst = grad_form(i, d->rhoE, qstar, Req);
+      const real g = pg[(int64_t)i * N + n];
+      const real geq = grad_form(i, d->rhoE, qeq, Req);
+      const real gst = grad_form(i, d->rhoE, qstar, Req);
       og[(int64_t)i * N + n] = g + om1 * (geq - g) + (om - om1) * (gst - g);
     }
   }
 }
 
 /* ---- O8: ghost equilibrium at an open face (Sec. 5.1) -------------------------------- */
-static double ghost_value(const orc_sim *s, int set, int i, const node_t *d, int zero_u) {
+static real ghost_value(const orc_sim *s, int set, int i, const node_t *d, int zero_u) {
   const int M = s->p.M;
-  double ug[3];
-  for (int a = 0; a < 3; ++a) ug[a] = zero_u ? 0.0 : d->u[a];
+  real ug[3];
+  for (int a = 0; a < 3; ++a) ug[a] = zero_u ? (real)0.0 : d->u[a];
   if (set < M - 1) return product_form(i, d->rho_a[set], ug, d->zeta_a[set]);
   if (set == M - 1) return product_form(i, d->rho, ug, d->zeta);
-  const double usq = ug[0] * ug[0] + ug[1] * ug[1] + ug[2] * ug[2];
-  double U = 0.0;
+  const real usq = ug[0] * ug[0] + ug[1] * ug[1] + ug[2] * ug[2];
+  real U = 0.0;
   for (int sp = 0; sp < M; ++sp) U += d->Y[sp] * spec_U(s, sp, d->T);
-  const double rhoE = d->rho * (U + usq / 2.0);
-  double qeq[3], Peq[3][3], Req[3][3];
+  const real rhoE = d->rho * (U + usq / 2.0);
+  real qeq[3], Peq[3][3], Req[3][3];
   energy_eq_moments(d->rho, ug, d->zeta, d->H, qeq, Peq, Req);
   return grad_form(i, rhoE, qeq, Req);
 }
@@ -548,7 +558,7 @@ static void stream_node(orc_sim *s, int64_t n) {
     const int64_t m = node_index(s, src[0], src[1], src[2]);
     const int im = mirror_dir(i, mirror);
     for (int set = 0; set < S; ++set) {
-      double v;
+      real v;
       if (open_out)
         v = ghost_value(s, set, im, &s->nd[m], zero_u);
       else
@@ -591,11 +601,11 @@ orc_sim *orc_create(const orc_problem *p) {
   s->p.reversible = NULL;
   s->N = (int64_t)p->nx * p->ny * p->nz;
   s->S = M + 1;
-  s->pop = (double *)calloc((size_t)s->S * Q * s->N, sizeof(double));
-  s->post = (double *)calloc((size_t)s->S * Q * s->N, sizeof(double));
+  s->pop = (real *)calloc((size_t)s->S * Q * s->N, sizeof(real));
+  s->post = (real *)calloc((size_t)s->S * Q * s->N, sizeof(real));
   s->Tstore = (double *)calloc((size_t)s->N, sizeof(double));
   s->nd = (node_t *)calloc((size_t)s->N, sizeof(node_t));
-  s->scratch = (double *)calloc((size_t)s->N, sizeof(double));
+  s->scratch = (real *)calloc((size_t)s->N, sizeof(real));
   if (!s->pop || !s->post || !s->Tstore || !s->nd || !s->scratch) {
     orc_destroy(s);
     return NULL;
@@ -614,7 +624,7 @@ void orc_destroy(orc_sim *s) {
 }
 
 /* initial state: equilibrium populations at the given fields (no non-equilibrium part) */
-void orc_init(orc_sim *s, const double *rho, const double *u, const double *T, const double *Y) {
+static void init_fields(orc_sim *s, const real *rho, const real *u, const real *T, const real *Y) {
   const int M = s->p.M;
   const int64_t N = s->N;
   for (int64_t n = 0; n < N; ++n) {
@@ -623,7 +633,7 @@ void orc_init(orc_sim *s, const double *rho, const double *u, const double *T, c
     d.rho = rho[n];
     for (int a = 0; a < 3; ++a) d.u[a] = u[a * N + n];
     d.T = T[n];
-    double inv_m = 0.0;
+    real inv_m = 0.0;
     for (int sp = 0; sp < M; ++sp) {
       d.Y[sp] = Y[sp * N + n];
       d.rho_a[sp] = d.rho * d.Y[sp];
@@ -638,14 +648,20 @@ void orc_init(orc_sim *s, const double *rho, const double *u, const double *T, c
     for (int set = 0; set < s->S; ++set)
       for (int i = 0; i < Q; ++i)
         s->pop[((int64_t)set * Q + i) * N + n] = ghost_value(s, set, i, &d, 0);
-    s->Tstore[n] = T[n];
+    s->Tstore[n] = ORC_VAL(T[n]);
   }
 }
+
+#ifndef ORC_REAL
+void orc_init(orc_sim *s, const double *rho, const double *u, const double *T, const double *Y) {
+  init_fields(s, rho, u, T, Y);
+}
+#endif
 
 static void nonlocal_fields(orc_sim *s, int nthreads) {
   const int M = s->p.M;
   const int64_t N = s->N;
-  double *fld = s->scratch;
+  real *fld = s->scratch;
   (void)nthreads;
   /* psi_alpha = (1/omega - 1/2) d_alpha phi_alpha ; X_alpha = -d_alpha psi_alpha (eq. Xalpha).
    * phi_alpha is odd under a mirror normal to alpha (it is odd in u_alpha), psi_alpha even */
@@ -653,7 +669,7 @@ static void nonlocal_fields(orc_sim *s, int nthreads) {
     for (int64_t n = 0; n < N; ++n) fld[n] = s->nd[n].phi[a];
 #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (int64_t n = 0; n < N; ++n) {
-      double om, om1;
+      real om, om1;
       relaxation_rates(s, s->nd[n].T, &om, &om1);
       s->nd[n].psi[a] = (1.0 / om - 0.5) * iso_grad_v(s, fld, n, a, a);
     }
@@ -685,13 +701,14 @@ uint32_t orc_step(orc_sim *s, int32_t nsteps, int32_t nthreads) {
     for (int64_t n = 0; n < N; ++n) collide(s, n);
 #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (int64_t n = 0; n < N; ++n) stream_node(s, n);
-    for (int64_t n = 0; n < N; ++n) s->Tstore[n] = s->nd[n].T;
+    for (int64_t n = 0; n < N; ++n) s->Tstore[n] = ORC_VAL(s->nd[n].T);
     anom_all |= anom;
   }
   return anom_all;
 }
 
-uint32_t orc_macros(orc_sim *s, double *rho, double *u, double *T, double *P, double *Y) {
+/* O9: the macroscopic fields of the current state (O1-O2 at every node) */
+static uint32_t macros_fields(orc_sim *s, real *rho, real *u, real *T, real *P, real *Y) {
   const int M = s->p.M;
   const int64_t N = s->N;
   uint32_t anom = 0;
@@ -707,6 +724,11 @@ uint32_t orc_macros(orc_sim *s, double *rho, double *u, double *T, double *P, do
       for (int sp = 0; sp < M; ++sp) Y[sp * N + n] = d.Y[sp];
   }
   return anom;
+}
+
+#ifndef ORC_REAL
+uint32_t orc_macros(orc_sim *s, double *rho, double *u, double *T, double *P, double *Y) {
+  return macros_fields(s, rho, u, T, P, Y);
 }
 
 /* Flame-front diagnostics of the current state (Sec. 5.2).  Displacement speed (eq. sd):
@@ -789,18 +811,25 @@ uint32_t orc_flame_speeds(orc_sim *s, double T_iso, const double *centre, double
   return anom;
 }
 
+#endif /* ORC_REAL */
+
 void orc_get_state(const orc_sim *s, double *pop, double *T) {
-  if (pop) memcpy(pop, s->pop, sizeof(double) * (size_t)s->S * Q * s->N);
+  const int64_t n = (int64_t)s->S * Q * s->N;
+  if (pop)
+    for (int64_t k = 0; k < n; ++k) pop[k] = ORC_VAL(s->pop[k]);
   if (T) memcpy(T, s->Tstore, sizeof(double) * (size_t)s->N);
 }
 
 void orc_set_state(orc_sim *s, const double *pop, const double *T) {
-  if (pop) memcpy(s->pop, pop, sizeof(double) * (size_t)s->S * Q * s->N);
+  const int64_t n = (int64_t)s->S * Q * s->N;
+  if (pop)
+    for (int64_t k = 0; k < n; ++k) s->pop[k] = pop[k];
   if (T) memcpy(s->Tstore, T, sizeof(double) * (size_t)s->N);
 }
 
 void orc_get_post(const orc_sim *s, double *post) {
-  memcpy(post, s->post, sizeof(double) * (size_t)s->S * Q * s->N);
+  const int64_t n = (int64_t)s->S * Q * s->N;
+  for (int64_t k = 0; k < n; ++k) post[k] = ORC_VAL(s->post[k]);
 }
 
 void orc_get_field(const orc_sim *s, int32_t which, double *out) {
@@ -809,29 +838,29 @@ void orc_get_field(const orc_sim *s, int32_t which, double *out) {
   for (int64_t n = 0; n < N; ++n) {
     const node_t *d = &s->nd[n];
     switch (which) {
-      case ORC_F_T: out[n] = d->T; break;
+      case ORC_F_T: out[n] = ORC_VAL(d->T); break;
       case ORC_F_RDOT:
-        for (int sp = 0; sp < M; ++sp) out[sp * N + n] = d->rdot[sp];
+        for (int sp = 0; sp < M; ++sp) out[sp * N + n] = ORC_VAL(d->rdot[sp]);
         break;
       case ORC_F_DU:
         for (int sp = 0; sp < M; ++sp)
-          for (int a = 0; a < 3; ++a) out[(sp * 3 + a) * N + n] = d->du[sp][a];
+          for (int a = 0; a < 3; ++a) out[(sp * 3 + a) * N + n] = ORC_VAL(d->du[sp][a]);
         break;
       case ORC_F_BETA:
-        for (int sp = 0; sp < M; ++sp) out[sp * N + n] = d->beta[sp];
+        for (int sp = 0; sp < M; ++sp) out[sp * N + n] = ORC_VAL(d->beta[sp]);
         break;
       case ORC_F_X:
-        for (int a = 0; a < 3; ++a) out[a * N + n] = d->X[a];
+        for (int a = 0; a < 3; ++a) out[a * N + n] = ORC_VAL(d->X[a]);
         break;
       case ORC_F_GRADY:
         for (int sp = 0; sp < M; ++sp)
-          for (int a = 0; a < 3; ++a) out[(sp * 3 + a) * N + n] = d->gradY[sp][a];
+          for (int a = 0; a < 3; ++a) out[(sp * 3 + a) * N + n] = ORC_VAL(d->gradY[sp][a]);
         break;
       case ORC_F_PHI:
-        for (int a = 0; a < 3; ++a) out[a * N + n] = d->phi[a];
+        for (int a = 0; a < 3; ++a) out[a * N + n] = ORC_VAL(d->phi[a]);
         break;
       case ORC_F_PSI:
-        for (int a = 0; a < 3; ++a) out[a * N + n] = d->psi[a];
+        for (int a = 0; a < 3; ++a) out[a * N + n] = ORC_VAL(d->psi[a]);
         break;
       case ORC_F_NEWTON: out[n] = (double)d->newton_iters; break;
       default: break;
@@ -840,6 +869,7 @@ void orc_get_field(const orc_sim *s, int32_t which, double *out) {
 }
 
 /* ---- pieces exposed for unit pins ---------------------------------------------------- */
+#ifndef ORC_REAL
 void orc_product_form(double dens, const double *v, double zeta, double *out27) {
   for (int i = 0; i < Q; ++i) out27[i] = product_form(i, dens, v, zeta);
 }
@@ -891,3 +921,4 @@ void orc_iso_grad(const orc_sim *s, const double *field, double *grad3) {
   for (int64_t n = 0; n < s->N; ++n)
     for (int a = 0; a < 3; ++a) grad3[a * s->N + n] = iso_grad(s, field, n, a);
 }
+#endif /* ORC_REAL */

@@ -21,6 +21,10 @@
 
 #include <stdint.h>
 
+#ifdef __cplusplus
+extern "C" {
+#endif
+
 #define ORC_Q 27
 #define ORC_MAXM 16
 #define ORC_MAXR 64
@@ -89,5 +93,9 @@ void orc_rates(const orc_sim *s, const double *rho_a, double T, double *rdot);
 void orc_diffusion(const orc_sim *s, const double *Y, double T, const double *rhs,
                    double *du, double *beta);
 void orc_iso_grad(const orc_sim *s, const double *field, double *grad3);
+
+#ifdef __cplusplus
+}
+#endif
 
 #endif

@@ -8,6 +8,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+LIB_AD_PATH = os.path.join(HERE, "liboracle_ad.so")
 
 F_T, F_RDOT, F_DU, F_BETA, F_X, F_GRADY, F_PHI, F_PSI, F_NEWTON = range(9)
 
@@ -69,6 +70,33 @@ def load(path=None):
     return lib
 
 
+def load_ad(path=None):
+    """Load the reverse sweep of the oracle (liboracle_ad.so: the same source on a
+    recording arithmetic type; see oracle_ad.cpp)."""
+    path = path or LIB_AD_PATH
+    if path in _libs:
+        return _libs[path]
+    if path == LIB_AD_PATH and not os.path.exists(LIB_AD_PATH):
+        from . import build as _b
+        _b.build_ad()
+    lib = C.CDLL(path)
+    lib.orc_create.restype = C.c_void_p
+    lib.orc_create.argtypes = [C.POINTER(_Problem)]
+    lib.orc_destroy.argtypes = [C.c_void_p]
+    lib.orc_step.restype = C.c_uint32
+    lib.orc_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    lib.orc_get_state.argtypes = [C.c_void_p, _dp, _dp]
+    lib.orc_set_state.argtypes = [C.c_void_p, _dp, _dp]
+    lib.orc_ad_step_vjp.restype = C.c_uint32
+    lib.orc_ad_step_vjp.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    lib.orc_ad_macros_vjp.restype = C.c_uint32
+    lib.orc_ad_macros_vjp.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_ad_init_vjp.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_ad_tape_entries.restype = C.c_int64
+    _libs[path] = lib
+    return lib
+
+
 def _d(a):
     return a.ctypes.data_as(_dp)
 
@@ -92,7 +120,7 @@ def grad_form(rhoE, q, Rt, lib=None):
 class OracleSim:
     """One lattice held by the oracle; arrays in the layouts of oracle.h."""
 
-    def __init__(self, prob, lib=None):
+    def __init__(self, prob, lib=None, arrhenius=None):
         lib = lib or load()
         self.prob = prob
         mech = prob.mech
@@ -103,7 +131,7 @@ class OracleSim:
             molar_mass=_c64(mech.molar_mass), nasa7=_c64(mech.nasa7), diff=_c64(prob.diff),
             nu_reac=np.ascontiguousarray(mech.nu_reac, np.int32).reshape(-1),
             nu_prod=np.ascontiguousarray(mech.nu_prod, np.int32).reshape(-1),
-            arrhenius=_c64(mech.arrhenius).reshape(-1),
+            arrhenius=_c64(mech.arrhenius if arrhenius is None else arrhenius).reshape(-1),
             reversible=np.ascontiguousarray(mech.reversible, np.uint8))
         if keep["nu_reac"].size == 0:
             keep["nu_reac"] = np.zeros(1, np.int32)
@@ -219,3 +247,53 @@ class OracleSim:
         out = np.zeros((3, self.N))
         self._lib.orc_iso_grad(self._h, _d(_c64(field)), _d(out))
         return out
+
+
+class OracleAdjoint(OracleSim):
+    """The oracle on its recording arithmetic type: the same forward steps, plus the
+    vector-Jacobian products of one step, of the macroscopic fields and of the
+    equilibrium initial state, by a reverse pass over the recorded operations."""
+
+    def __init__(self, prob, arrhenius=None):
+        super().__init__(prob, lib=load_ad(), arrhenius=arrhenius)
+
+    def init(self, rho=None, u=None, T=None, Y=None):
+        self.init_vjp(np.zeros((self.S, 27, self.N)), rho, u, T, Y)
+        return self
+
+    def macros(self):
+        raise NotImplementedError("use OracleSim for forward fields")
+
+    def step_vjp(self, lam_next):
+        """(lam_prev [S, 27, N], grad [R, 3] w.r.t. (ln A, b, Ta), anomaly bits); the
+        state advances by one step."""
+        lam_next = _c64(lam_next).reshape(self.S, 27, self.N)
+        lam_prev = np.zeros_like(lam_next)
+        R = self.prob.mech.R
+        grad = np.zeros((max(R, 1), 3))
+        anom = self._lib.orc_ad_step_vjp(self._h, _d(lam_next), _d(lam_prev), _d(grad))
+        return lam_prev, grad[:R], int(anom)
+
+    def macros_vjp(self, w_rho=None, w_u=None, w_T=None, w_P=None, w_Y=None):
+        """Adjoint populations [S, 27, N] of sum(w_rho rho + w_u u + w_T T + w_P P + w_Y Y)
+        over the lattice, at the current state."""
+        lam = np.zeros((self.S, 27, self.N))
+        ws = [None if w is None else _c64(w) for w in (w_rho, w_u, w_T, w_P, w_Y)]
+        ptrs = [C.cast(None, _dp) if w is None else _d(w) for w in ws]
+        self._lib.orc_ad_macros_vjp(self._h, *ptrs, _d(lam))
+        return lam
+
+    def init_vjp(self, lam0, rho=None, u=None, T=None, Y=None):
+        """Gradients (rho [N], u [3, N], T [N], Y [M, N]) of sum(lam0 * pop_0) for the
+        equilibrium initial state of the given fields; sets that state."""
+        pr = self.prob
+        N, M = self.N, self.M
+        f = [_c64(pr.rho if rho is None else rho), _c64(pr.u if u is None else u),
+             _c64(pr.T if T is None else T), _c64(pr.Y if Y is None else Y)]
+        g = [np.zeros(N), np.zeros((3, N)), np.zeros(N), np.zeros((M, N))]
+        lam0 = _c64(lam0).reshape(self.S, 27, N)
+        self._lib.orc_ad_init_vjp(self._h, *(_d(a) for a in f), _d(lam0), *(_d(a) for a in g))
+        return dict(rho=g[0], u=g[1], T=g[2], Y=g[3])
+
+    def tape_entries(self):
+        return int(self._lib.orc_ad_tape_entries())

@@ -38,14 +38,14 @@ MUTANTS = {
     "sa_sign": ("for (int a = 0; a < 3; ++a) un -= d[n].u[a] * gT[a * N + n] / mag;",
                 "for (int a = 0; a < 3; ++a) un += d[n].u[a] * gT[a * N + n] / mag;"),
     "psi_sign": ("if (c == 1) return 0.5 * (xi + s);", "if (c == 1) return 0.5 * (-xi + s);"),
-    "kc_sign": ("const double Kc = exp(-dG) * pow(c0, dnu);", "const double Kc = exp(dG) * pow(c0, dnu);"),
+    "kc_sign": ("const real Kc = exp(-dG) * pow(c0, dnu);", "const real Kc = exp(dG) * pow(c0, dnu);"),
     "kinetic_energy_half": ("E - usq / 2.0, T_start", "E - usq, T_start"),
     "transform_sign": ("-0.5 * K[a][b] * Y[b];", "0.5 * K[a][b] * Y[b];"),
     "stream_direction": ("int v = xyz[a] - CI(i, a);", "int v = xyz[a] + CI(i, a);"),
     "iso_grad_scale": ("return acc / THETA;", "return acc;"),
     "tau_ab_mixture_mass": ("zeta_a[a] * zeta_a[b] / (zeta * diffusivity(s, a, b, T))",
                             "zeta_a[a] * zeta_a[b] / (diffusivity(s, a, b, T))"),
-    "ghost_velocity": ("for (int a = 0; a < 3; ++a) ug[a] = zero_u ? 0.0 : d->u[a];",
+    "ghost_velocity": ("for (int a = 0; a < 3; ++a) ug[a] = zero_u ? (real)0.0 : d->u[a];",
                        "for (int a = 0; a < 3; ++a) ug[a] = 0.0;"),
     "slaved_momentum": ("d->j_a[M - 1][a] = d->j[a] - j_sum[a];", "d->j_a[M - 1][a] = d->j[a] + j_sum[a];"),
     "phi_cubic_sign": ("- d->rho * d->u[a] * d->u[a] * d->u[a];", "+ d->rho * d->u[a] * d->u[a] * d->u[a];"),
