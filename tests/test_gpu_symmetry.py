@@ -7,12 +7,11 @@ import numpy as np
 import pytest
 
 from paper_2101_01702_amd import workloads as W
-from gpu_cases import field_errors, oracle_run, pop_errors, zeta_of
+from gpu_cases import check_fp32, check_fp64, field_errors, oracle_run, pop_errors, zeta_of
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -67,9 +66,7 @@ def test_symmetry_faces_fp64(lbm_mod, shape, bc):
     mac = s.macros()
     sim, anom = oracle_run(prob, 100)
     assert s.status() == 0 and anom == 0
-    err = field_errors(mac, sim.macros(), zeta_of(prob))
-    print(f"[{prob.name} {bc}] fp64 worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
-    assert max(err.values()) <= TOL64, err
+    check_fp64(field_errors(mac, sim.macros(), zeta_of(prob)), f"{prob.name} {bc}")
     pop, _ = s.populations(np.arange(prob.N))
     assert max(pop_errors(pop, sim.state()[0])) <= TOL64
     s.close()
@@ -83,9 +80,7 @@ def test_symmetry_faces_fp32(lbm_mod, shape, bc):
     mac = s.macros()
     sim, anom = oracle_run(prob, 500)
     assert s.status() == 0 and anom == 0
-    err = field_errors(mac, sim.macros(), zeta_of(prob))
-    print(f"[{prob.name}] fp32 worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
-    assert max(err.values()) <= TOL32, err
+    check_fp32(field_errors(mac, sim.macros(), zeta_of(prob)), prob.name)
     s.close()
 
 
@@ -105,5 +100,4 @@ def test_symmetry_face_matches_mirrored_full_lattice_on_gpu(lbm_mod, axis):
     fm, hm = out
     err = field_errors(hm, {k: (v[..., keep] if k in ("u", "Y") else v[keep]) for k, v in fm.items()},
                        zeta_of(full))
-    print(f"[mirror axis {axis}] worst {max(err, key=err.get)} {max(err.values()):.2e}", flush=True)
-    assert max(err.values()) <= TOL64, err
+    check_fp64(err, f"mirror axis {axis}")
