@@ -125,6 +125,12 @@ enum {
  *                   lambda scale with (T / visc_T_ref)^visc_T_exp at each node, which
  *                   sets that node's relaxation rates (LBM_STORE_F64 and _F32 only);
  *                   0: the constants omega, omega1
+ *   adjoint         nonzero: the workspace also holds the work buffers of the discrete
+ *                   adjoint (lbm_adjoint_*), about 0.48 (M + 1) kB more per node.  The
+ *                   adjoint covers LBM_STORE_F64 and _F32, constant transport
+ *                   (diff_T_exp = visc_T_exp = 0) and periodic, open and zero-velocity
+ *                   faces of one lattice (n_segments <= 1); other descriptors with
+ *                   adjoint != 0 get LBM_ERR_UNSUPPORTED
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -141,7 +147,7 @@ typedef struct {
   double omega, omega1;
   double kappa, dt_phys, rho_ref, p0;
   int32_t storage;
-  int32_t reserved;
+  int32_t adjoint;
   const double *ref_state;
   int32_t n_segments;
   int32_t reserved2;
@@ -263,14 +269,65 @@ lbm_status lbm_flame_speeds(lbm_handle h, double T_iso, const double *centre, do
 lbm_status lbm_flame_speeds_static(lbm_handle h, double T_iso, const double *centre, double *d_out,
                                    double *d_totals, void *stream);
 
-/* Discrete adjoint of one step.  Not provided by this build: returns
- * LBM_ERR_UNSUPPORTED. */
+/* State snapshots, for checkpoints and for the adjoint's recomputation.  A snapshot is
+ * the current pre-collision state as the next step reads it: the populations of the
+ * current buffer (with their ghost cells), the deferred corrections and the stored
+ * temperature, in lbm_state_size bytes of caller-owned device memory (256-byte aligned).
+ * Saving and loading are stream-ordered device copies; loading replaces the handle's
+ * current state (the side fields are recomputed by the next step). */
+lbm_status lbm_state_size(lbm_handle h, size_t *bytes);
+lbm_status lbm_state_save(lbm_handle h, void *d_state, void *stream);
+lbm_status lbm_state_load(lbm_handle h, const void *d_state, void *stream);
+
+/* Replace the Arrhenius parameters (host [R][3]: A >= 0 CGS, b, Ta in K; Sec. 4) of the
+ * handle's reactions, for sensitivity studies.  Waits for the stream, then copies the
+ * rebuilt tables on it and waits again. */
+lbm_status lbm_set_arrhenius(lbm_handle h, const double *arrhenius, void *stream);
+
+/*
+ * Discrete adjoint (handles created with lbm_desc.adjoint != 0).  Adjoint populations are
+ * device FP64 arrays [S][27][N] in node order: the adjoint of the pulled pre-collision
+ * populations of a state.  d_state is a snapshot of lbm_state_save, or NULL for the
+ * handle's current state.  All arithmetic is FP64 (on an FP32-stored state, the adjoint
+ * of the FP32-stored trajectory).  Calls on one handle share the adjoint work buffers of
+ * the workspace: they must not overlap.
+ *
+ * lbm_adjoint_step: one step of the method, F_{n+1} = step(F_n) (Sec. 2-4: moments,
+ *   temperature by Newton on the energy (eq. temperature), mass-action rates,
+ *   Stefan-Maxwell relaxation (eqs. tauab, transform1, fStar), the stencils of X and
+ *   grad Y (eqs. Xalpha, corrFourier), the collisions of eqs. finalNumericalEquations, f
+ *   and g, equilibrium ghosts at open faces (Sec. 5.1) and streaming), reversed at the
+ *   state F_n held in d_state: d_adj holds lambda_{n+1} on entry and lambda_n =
+ *   (dF_{n+1}/dF_n)^T lambda_{n+1} on return, and d_grad_params[R][3] (device, may be
+ *   NULL) is incremented by (dF_{n+1}/d(ln A_k, b_k, Ta_k))^T lambda_{n+1}.
+ */
 lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, double *d_grad_params,
                             void *stream);
+
+/* Adjoint of lbm_macros at the state d_state: d_adj[S][27][N] = the gradient with respect
+ * to the populations of sum over nodes of w_rho rho + w_u . u + w_T T + w_P P + w_Y . Y
+ * (device FP64 weights [N], [3][N], [N], [N], [M][N]; any may be NULL: zero).  T enters
+ * through the implicit function of eq. temperature. */
+lbm_status lbm_adjoint_macros(lbm_handle h, const void *d_state, const double *d_w_rho, const double *d_w_u,
+                              const double *d_w_T, const double *d_w_P, const double *d_w_Y, double *d_adj,
+                              void *stream);
+
+/* Adjoint of lbm_init_fields at the fields d_rho[N], d_u[3][N], d_T[N], d_Y[M][N]: from the
+ * adjoint d_adj[S][27][N] of the initial populations, the gradients g_rho[N], g_u[3][N],
+ * g_T[N], g_Y[M][N] (device FP64, any may be NULL) of the equilibrium initial state
+ * (eqs. feq, gieq; each field varied with the others held). */
+lbm_status lbm_adjoint_init(lbm_handle h, const double *d_rho, const double *d_u, const double *d_T,
+                            const double *d_Y, const double *d_adj, double *d_g_rho, double *d_g_u, double *d_g_T,
+                            double *d_g_Y, void *stream);
 
 /* Wait for the stream, return the latched anomaly bits and clear them.  Returns
  * LBM_ERR_DEVICE_ANOMALY when any bit was set. */
 lbm_status lbm_status_sync(lbm_handle h, void *stream, uint32_t *anomaly_bits);
+
+/* Measurement aid: copy `bytes` (a multiple of 16, 16-byte aligned buffers) with a plain
+ * streaming kernel of 16-byte loads and stores, the read + write bandwidth ceiling of a
+ * streaming kernel on the device the stream belongs to. */
+lbm_status lbm_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *stream);
 
 /* Message of the last failed call on h (or of a handle-less call for NULL);
  * valid until the next call on the same handle. */

@@ -31,18 +31,22 @@ def build(verbose: bool = False, extra_device_flags=None) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     t0 = time.time()
     dev_obj = os.path.join(BUILD_DIR, "lbm_device.o")
+    adj_obj = os.path.join(BUILD_DIR, "lbm_adjoint.o")
     api_obj = os.path.join(BUILD_DIR, "lbm_api.o")
     procs = [
         subprocess.Popen([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS,
                           *(extra_device_flags or []), "-c", os.path.join(CSRC, "lbm_device.hip"),
                           "-o", dev_obj]),
+        subprocess.Popen([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS,
+                          "-c", os.path.join(CSRC, "lbm_adjoint.hip"), "-o", adj_obj]),
         subprocess.Popen([HIPCC, f"--offload-arch={ARCH}", *COMMON, "-c",
                           os.path.join(CSRC, "lbm_api.cpp"), "-o", api_obj]),
     ]
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_obj, api_obj, "-o", LIB + ".tmp"], verbose)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", dev_obj, adj_obj, api_obj, "-o", LIB + ".tmp"],
+         verbose)
     os.replace(LIB + ".tmp", LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f} s", flush=True)

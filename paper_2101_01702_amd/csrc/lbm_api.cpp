@@ -27,7 +27,14 @@ size_t round_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t status, tables, consts, segs, pop0, pop1, T, side_Y, side_w, side_phi, side_rho, side_u, psi, corr, diag,
       total;
-  size_t corr_bytes;
+  size_t corr_bytes, pop_bytes;
+  // discrete adjoint (lbm_desc.adjoint != 0)
+  size_t adj_P, adj_Ln, adj_fY, adj_fw, adj_lX, adj_lgY, adj_lpsi, adj_lphi, adj_lYs, adj_part, adj_nodes;
+};
+
+// sections of a state snapshot (lbm_state_save): populations, corrections, temperature
+struct StateLayout {
+  size_t pop, corr, T, total;
 };
 
 Geom make_geom(const lbm_desc &d) {
@@ -84,8 +91,32 @@ Layout make_layout(const lbm_desc &d, const Geom &g) {
   L.corr_bytes = 6 * (size_t)g.NPAD * ct;   // deferred corrections, padded planes
   L.corr = take(L.corr_bytes);
   L.diag = take((size_t)8 * ((N + 127) / 128) * 8);   // partial sums of the diagnostics (up to 8 totals)
+  L.pop_bytes = S * Q * (size_t)g.NPAD * st;
+  if (d.adjoint) {
+    const size_t R = (size_t)d.n_reactions;
+    L.adj_P = take(S * Q * N * 8);
+    L.adj_Ln = take(S * Q * N * 8);
+    L.adj_fY = take(M * N * 8);
+    L.adj_fw = take(M * N * 8);
+    L.adj_lX = take(3 * N * 8);
+    L.adj_lgY = take(3 * M * N * 8);
+    L.adj_lpsi = take(3 * N * 8);
+    L.adj_lphi = take(3 * N * 8);
+    L.adj_lYs = take(M * N * 8);
+    L.adj_part = take(3 * (R > 0 ? R : 1) * ((N + 7) / 8) * 8);
+    L.adj_nodes = take(N * 8);
+  }
   L.total = off;
   return L;
+}
+
+StateLayout make_state_layout(const Layout &L, const Geom &g) {
+  StateLayout S{};
+  S.pop = 0;
+  S.corr = round_up(L.pop_bytes);
+  S.T = S.corr + round_up(L.corr_bytes);
+  S.total = S.T + round_up((size_t)g.N * 8);
+  return S;
 }
 
 bool fail(std::string *where, const char *fmt, ...) {
@@ -201,6 +232,20 @@ bool validate(const lbm_desc *d, std::string *err) {
       return fail(err, "lattice has %.0f padded nodes; a plane of %.0f-byte values must stay below 2 GiB",
                   padded, word);
   }
+  return true;
+}
+
+// The discrete adjoint covers FP64 and FP32 storage, constant transport, and periodic,
+// open and zero-velocity faces of one lattice.
+bool adjoint_supported(const lbm_desc *d, std::string *err) {
+  if (!d->adjoint) return true;
+  if (d->storage != LBM_STORE_F64 && d->storage != LBM_STORE_F32)
+    return fail(err, "the adjoint needs LBM_STORE_F64 or LBM_STORE_F32 storage");
+  for (int k = 0; k < 6; ++k)
+    if (d->bc[k] == LBM_BC_SYMMETRY) return fail(err, "the adjoint does not cover symmetry faces");
+  if (d->n_segments > 1) return fail(err, "the adjoint does not cover batches of segments");
+  if (d->diff_T_exp != 0.0 || d->visc_T_exp != 0.0)
+    return fail(err, "the adjoint covers constant diffusivities, viscosity and conductivity only");
   return true;
 }
 
@@ -348,6 +393,9 @@ struct lbm_ctx {
   std::string err;
   std::vector<GraphEntry> graphs;   // lbm_step_graph recordings, most recent last
   hipStream_t capture = nullptr;    // stream the recordings are captured on
+  AdjBufHost adj{};                 // work buffers of the adjoint (lbm_desc.adjoint != 0)
+  int64_t *adj_nodes = nullptr;
+  Tables tab_host{};                // host copy of the tables (lbm_set_arrhenius)
 };
 
 namespace {
@@ -418,6 +466,10 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes) {
     g_last_error = err;
     return LBM_ERR_ARG;
   }
+  if (!adjoint_supported(desc, &err)) {
+    g_last_error = err;
+    return LBM_ERR_UNSUPPORTED;
+  }
   const Geom g = make_geom(*desc);
   *bytes = make_layout(*desc, g).total;
   return LBM_OK;
@@ -430,6 +482,10 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   if (!validate(desc, &err)) {
     g_last_error = err;
     return LBM_ERR_ARG;
+  }
+  if (!adjoint_supported(desc, &err)) {
+    g_last_error = err;
+    return LBM_ERR_UNSUPPORTED;
   }
   if (!d_workspace) return arg_fail(nullptr, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_workspace) % ALIGN != 0) {
@@ -497,11 +553,26 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   b.corr = ws + L.corr;
   b.kc = reinterpret_cast<const CollideConsts *>(ws + L.consts);
   b.diag = reinterpret_cast<double *>(ws + L.diag);
+  if (h->d.adjoint) {
+    AdjBufHost &a = h->adj;
+    a.P = reinterpret_cast<double *>(ws + L.adj_P);
+    a.Ln = reinterpret_cast<double *>(ws + L.adj_Ln);
+    a.T0 = nullptr;
+    a.fY = reinterpret_cast<double *>(ws + L.adj_fY);
+    a.fw = reinterpret_cast<double *>(ws + L.adj_fw);
+    a.lX = reinterpret_cast<double *>(ws + L.adj_lX);
+    a.lgY = reinterpret_cast<double *>(ws + L.adj_lgY);
+    a.lpsi = reinterpret_cast<double *>(ws + L.adj_lpsi);
+    a.lphi = reinterpret_cast<double *>(ws + L.adj_lphi);
+    a.lYs = reinterpret_cast<double *>(ws + L.adj_lYs);
+    a.part = reinterpret_cast<double *>(ws + L.adj_part);
+    h->adj_nodes = reinterpret_cast<int64_t *>(ws + L.adj_nodes);
+  }
   if (h->g.nseg > 1) {
     h->g.x_seg = reinterpret_cast<const int32_t *>(ws + L.segs);
     h->g.seg_off = h->g.x_seg + h->d.nx;
   }
-  Tables t;
+  Tables &t = h->tab_host;
   build_tables(h->d, t);
   h->kc.omega = t.omega;
   h->kc.vexp = t.vexp;
@@ -531,6 +602,11 @@ lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm
   if (e == hipSuccess) {
     uint32_t zero[16] = {0};
     e = hipMemcpy(ws + L.status, zero, sizeof(zero), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess && h->d.adjoint) {   // node list 0..N-1 of the population export
+    std::vector<int64_t> ids((size_t)h->g.N);
+    for (int64_t k = 0; k < h->g.N; ++k) ids[(size_t)k] = k;
+    e = hipMemcpy(h->adj_nodes, ids.data(), ids.size() * 8, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     lbm_status s = hip_fail(nullptr, e, "uploading tables");
@@ -747,10 +823,136 @@ lbm_status lbm_flame_speeds_static(lbm_handle h, double T_iso, const double *cen
   return LBM_OK;
 }
 
-lbm_status lbm_adjoint_step(lbm_handle h, const void *, void *, double *, void *) {
-  if (h) h->err = "the discrete adjoint step is not provided by this library";
-  else g_last_error = "the discrete adjoint step is not provided by this library";
-  return LBM_ERR_UNSUPPORTED;
+lbm_status lbm_state_size(lbm_handle h, size_t *bytes) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!bytes) return arg_fail(h, "bytes is NULL");
+  *bytes = make_state_layout(h->L, h->g).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_state_save(lbm_handle h, void *d_state, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!d_state) return arg_fail(h, "state buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(d_state) % ALIGN != 0) return arg_fail(h, "state buffer must be 256-byte aligned");
+  const StateLayout S = make_state_layout(h->L, h->g);
+  char *dst = static_cast<char *>(d_state);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(dst + S.pop, h->b.pop[h->cur], h->L.pop_bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst + S.corr, h->b.corr, h->L.corr_bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst + S.T, h->b.T, (size_t)h->g.N * 8, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(h, e, "state save");
+  return LBM_OK;
+}
+
+lbm_status lbm_state_load(lbm_handle h, const void *d_state, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!d_state) return arg_fail(h, "state buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(d_state) % ALIGN != 0) return arg_fail(h, "state buffer must be 256-byte aligned");
+  const StateLayout S = make_state_layout(h->L, h->g);
+  const char *src = static_cast<const char *>(d_state);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(h->b.pop[h->cur], src + S.pop, h->L.pop_bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->b.corr, src + S.corr, h->L.corr_bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->b.T, src + S.T, (size_t)h->g.N * 8, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(h, e, "state load");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_arrhenius(lbm_handle h, const double *arrhenius, void *stream) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  const int R = h->d.n_reactions;
+  if (R == 0) return LBM_OK;
+  if (!arrhenius) return arg_fail(h, "arrhenius is NULL");
+  for (int k = 0; k < R; ++k) {
+    const double A = arrhenius[3 * k], b = arrhenius[3 * k + 1], Ta = arrhenius[3 * k + 2];
+    if (!(A >= 0.0) || !std::isfinite(A) || !std::isfinite(b) || !std::isfinite(Ta))
+      return arg_fail(h, "Arrhenius parameters must be finite with A >= 0");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the host tables are the source of the copy: no copy of the previous call may be pending
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(h, e, "set_arrhenius");
+  h->arrh.assign(arrhenius, arrhenius + 3 * R);
+  h->d.arrhenius = h->arrh.data();
+  build_tables(h->d, h->tab_host);
+  e = hipMemcpyAsync(const_cast<Tables *>(h->b.tab), &h->tab_host, sizeof(Tables), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(h, e, "set_arrhenius");
+  return LBM_OK;
+}
+
+namespace {
+
+// export the pulled populations (FP64, node order) of a snapshot, or of the current
+// state when d_state is NULL, into the adjoint work buffer; the Newton start is returned
+hipError_t adjoint_forward_state(lbm_handle h, const void *d_state, hipStream_t st, const double **T0) {
+  Buffers b = h->b;
+  if (d_state) {
+    const StateLayout S = make_state_layout(h->L, h->g);
+    char *src = const_cast<char *>(static_cast<const char *>(d_state));
+    b.pop[h->cur] = src + S.pop;
+    b.corr = src + S.corr;
+    b.T = reinterpret_cast<double *>(src + S.T);
+  }
+  *T0 = b.T;
+  return launch_export(h->g, b, h->kc, h->d.storage, h->cur, h->adj_nodes, h->g.N, h->adj.P, nullptr, st);
+}
+
+lbm_status adjoint_ready(lbm_handle h) {
+  if (!h) return arg_fail(nullptr, "handle is NULL");
+  if (!h->d.adjoint) {
+    h->err = "the handle was created without the adjoint work buffers (lbm_desc.adjoint = 0)";
+    return LBM_ERR_UNSUPPORTED;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, double *d_grad_params, void *stream) {
+  lbm_status s = adjoint_ready(h);
+  if (s != LBM_OK) return s;
+  if (!d_adj) return arg_fail(h, "d_adj must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double *T0 = nullptr;
+  hipError_t e = adjoint_forward_state(h, d_state, st, &T0);
+  const size_t pop_words = (size_t)(h->d.n_species + 1) * Q * (size_t)h->g.N;
+  if (e == hipSuccess) e = hipMemcpyAsync(h->adj.Ln, d_adj, pop_words * 8, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    AdjBufHost a = h->adj;
+    a.T0 = T0;
+    e = launch_adjoint_step(h->g, h->b.tab, a, h->d.omega, h->d.omega1, h->d.n_reactions, static_cast<double *>(d_adj),
+                            d_grad_params, st);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint step");
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_macros(lbm_handle h, const void *d_state, const double *d_w_rho, const double *d_w_u,
+                              const double *d_w_T, const double *d_w_P, const double *d_w_Y, double *d_adj,
+                              void *stream) {
+  lbm_status s = adjoint_ready(h);
+  if (s != LBM_OK) return s;
+  if (!d_adj) return arg_fail(h, "d_adj must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double *T0 = nullptr;
+  hipError_t e = adjoint_forward_state(h, d_state, st, &T0);
+  if (e == hipSuccess)
+    e = launch_adjoint_macros(h->g, h->b.tab, h->adj.P, T0, d_w_rho, d_w_u, d_w_T, d_w_P, d_w_Y, d_adj, st);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint of the macroscopic fields");
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_init(lbm_handle h, const double *d_rho, const double *d_u, const double *d_T,
+                            const double *d_Y, const double *d_adj, double *d_g_rho, double *d_g_u, double *d_g_T,
+                            double *d_g_Y, void *stream) {
+  lbm_status s = adjoint_ready(h);
+  if (s != LBM_OK) return s;
+  if (!d_rho || !d_u || !d_T || !d_Y || !d_adj) return arg_fail(h, "fields and d_adj must not be NULL");
+  hipError_t e = launch_adjoint_init(h->g, h->b.tab, d_rho, d_u, d_T, d_Y, d_adj, d_g_rho, d_g_u, d_g_T, d_g_Y,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint of the initial state");
+  return LBM_OK;
 }
 
 lbm_status lbm_status_sync(lbm_handle h, void *stream, uint32_t *anomaly_bits) {
@@ -767,6 +969,15 @@ lbm_status lbm_status_sync(lbm_handle h, void *stream, uint32_t *anomaly_bits) {
     h->err = "device anomaly bits set";
     return LBM_ERR_DEVICE_ANOMALY;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *stream) {
+  if (!d_src || !d_dst) return arg_fail(nullptr, "buffers must not be NULL");
+  if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(d_src) % 16 != 0 || reinterpret_cast<uintptr_t>(d_dst) % 16 != 0)
+    return arg_fail(nullptr, "buffers and size must be multiples of 16 bytes");
+  const hipError_t e = launch_stream_copy(d_src, d_dst, (int64_t)bytes, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "stream copy");
   return LBM_OK;
 }
 

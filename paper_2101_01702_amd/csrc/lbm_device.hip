@@ -557,7 +557,7 @@ __device__ __forceinline__ LaneSrc lane_src(const Geom &g, int64_t n) {
 
 // source row of the directions (*, cy, cz), y - cy and z - cz wrapped on periodic axes
 // (an open axis has a ghost layer and never wraps): the padded row and the index of
-// its cell x (24-bit products: a plane has far fewer than 2^24 rows and cells per row)
+// its cell x (32-bit products: a padded plane has fewer than 2^31 cells)
 struct RowPos {
   uint32_t row, p0;
 };
@@ -566,8 +566,8 @@ __device__ __forceinline__ RowPos row_source(const Geom &g, const LaneSrc &l, in
   if (g.per[1] && cy != 0) sy += (l.y == (cy > 0 ? 0 : g.ny - 1)) ? cy * g.ny : 0;
   if (g.per[2] && cz != 0) sz += (l.z == (cz > 0 ? 0 : g.nz - 1)) ? cz * g.nz : 0;
   RowPos r;
-  r.row = __umul24((uint32_t)(sz + g.pz), (uint32_t)g.NY) + (uint32_t)(sy + g.py);
-  r.p0 = __umul24(r.row, (uint32_t)g.NX) + (uint32_t)l.x;
+  r.row = (uint32_t)(sz + g.pz) * (uint32_t)g.NY + (uint32_t)(sy + g.py);
+  r.p0 = r.row * (uint32_t)g.NX + (uint32_t)l.x;
   return r;
 }
 // index of the source of direction (CX, cy, cz) in its row: x - CX, wrapped on a
@@ -739,24 +739,37 @@ __device__ __forceinline__ void moments_pass(const Geom &g, const void *src, con
 // store happens before the side channel at the end, so that the constant tables are
 // read with scalar loads throughout.
 template <int M, typename ST, bool VT>
+__device__ __forceinline__ void node_local_post(const Geom &g, const Buffers &b, const IslStash &sh, int64_t n,
+                                                const double (&mo)[14], const double (&sp)[M - 1][4],
+                                                CollCoef<M, FT<ST>> &cc);
+
+template <int M, typename ST, bool VT>
 __device__ __forceinline__ void node_local(const Geom &g, const Buffers &b, KC4 *kp, const IslStash &sh,
                                            int64_t n, const LaneSrc &l, int cur, CollCoef<M, FT<ST>> &cc) {
+  // O1: moments of the pulled populations
+  double mo[14], sp[M - 1][4];
+  moments_pass<M, ST>(g, b.pop[cur], b.corr, l, kp, mo, sp);
+  node_local_post<M, ST, VT>(g, b, sh, n, mo, sp, cc);
+}
+
+// Everything of the step that is local to the node, from its moments: temperature (O2),
+// production rates (O3), Stefan-Maxwell solve (O4), the collision coefficients cc and
+// the side channel of the stencils (O5).
+template <int M, typename ST, bool VT>
+__device__ __forceinline__ void node_local_post(const Geom &g, const Buffers &b, const IslStash &sh, int64_t n,
+                                                const double (&mo)[14], const double (&sp)[M - 1][4],
+                                                CollCoef<M, FT<ST>> &cc) {
   using SW = IslWords<M>;
   using F = FT<ST>;
   using Side = typename Fmt<ST>::Side;
   // the constant tables through the constant address space: their loads are scalar
   // wherever they stand, also after stores and opaque() barriers
   TB4 &tb = *(TB4 *)b.tab;
-  const void *src = b.pop[cur];
-  const void *corr = b.corr;
   const int64_t N = g.N;
   const double T0 = b.T[n];
 
-  // O1: moments
   Macro<M> m;
   {
-    double mo[14], sp[M - 1][4];
-    moments_pass<M, ST>(g, src, corr, l, kp, mo, sp);
     m.rho = mo[0];
     const double inv_rho = 1.0 / mo[0];
     m.u[0] = mo[1] * inv_rho;
@@ -1058,11 +1071,22 @@ __device__ __forceinline__ RowFG fg_row(const CollCoef<M, F> &cc, int cy, int cz
 }
 
 template <int M, typename ST, typename F, int CX, bool VT, typename K>
+__device__ __forceinline__ void collide_fg_core(const Geom &g, void *dst, const CollCoef<M, F> &cc, const RowFG &rw,
+                                                double f, double gv, int i, const K &kc, uint32_t so);
+
+template <int M, typename ST, typename F, int CX, bool VT, typename K>
 __device__ __forceinline__ void collide_fg_dir(const Geom &g, void *dst, const CollCoef<M, F> &cc, const RowFG &rw,
                                                const PulledFG<ST> &p, int i, int cy, int cz, const K &kc,
                                                uint32_t so) {
   double f, gv;
   fg_values<M, ST, CX>(p, i, cy, cz, kc, f, gv);
+  collide_fg_core<M, ST, F, CX, VT>(g, dst, cc, rw, f, gv, i, kc, so);
+}
+
+// f and g of one direction from their pulled values (with the deferred corrections)
+template <int M, typename ST, typename F, int CX, bool VT, typename K>
+__device__ __forceinline__ void collide_fg_core(const Geom &g, void *dst, const CollCoef<M, F> &cc, const RowFG &rw,
+                                                double f, double gv, int i, const K &kc, uint32_t so) {
   const double om = VT ? rw.om : kc.omega;
   const double u0 = cc.u0;
   const double feq = rw.rf * psi_c<double>(CX, u0, u0 * u0 + cc.zeta);
@@ -1244,12 +1268,49 @@ __device__ __forceinline__ void species_pass(const Geom &g, const void *src, voi
 
 // O7 + O8 over the 27 directions: f, g and the stored species of one direction from
 // the factors of its row, with the loads of the next direction in flight while the
-// current one is collided
+// current one is collided.  The directions go in the reverse order of the moments pass
+// (last row first, cx = +1, 0, -1), so that the populations read last by the moments
+// pass, the likeliest to be still in cache, are read again first.
+#ifndef LBM_COLLIDE_REVERSED
+#define LBM_COLLIDE_REVERSED 1
+#endif
 template <int M, typename ST, typename F, bool VT>
 __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, void *dst, const void *corr, KC4 *kp,
                                              const CollCoef<M, F> &cc, const LaneSrc &l) {
   const uint32_t so = row_source(g, l, 0, 0).p0 * (uint32_t)sizeof(ST);
   PulledAll<M, ST> pa, pb, pc;
+#if LBM_COLLIDE_REVERSED
+  pull_all<M, ST, 1>(g, src, corr, 26, 1, 1, dir_source<1>(g, l, row_source(g, l, 1, 1)), pc);
+#pragma unroll 1
+  for (int rr = 0; rr < 9; ++rr) {
+    const int r = 8 - rr;
+    const int cy = __builtin_amdgcn_readfirstlane(r % 3 - 1), cz = __builtin_amdgcn_readfirstlane(r / 3 - 1);
+    KC4 *k = kp;
+    opaque_uniform(k);
+    double u0 = cc.u0, T = cc.T;
+    opaque(u0);
+    opaque(T);
+    const RowPos s0 = row_source(g, l, cy, cz);
+    const RowFG rw = fg_row<M, F, VT>(cc, cy, cz, k);
+    RowSpecies<M, F> rs;
+    species_row<M, F>(cc, T, cy, cz, *k, rs);
+    pull_all<M, ST, 0>(g, src, corr, 3 * r + 1, cy, cz, dir_source<0>(g, l, s0), pb);
+    collide_fg_dir<M, ST, F, 1, VT>(g, dst, cc, rw, pc.fg, 3 * r + 2, cy, cz, *k, so);
+    collide_species_dir<M, ST, F, 1>(g, dst, cc, u0, T, rs, pc.fa, 3 * r + 2, *k, so);
+    pull_all<M, ST, -1>(g, src, corr, 3 * r, cy, cz, dir_source<-1>(g, l, s0), pa);
+    collide_fg_dir<M, ST, F, 0, VT>(g, dst, cc, rw, pb.fg, 3 * r + 1, cy, cz, *k, so);
+    collide_species_dir<M, ST, F, 0>(g, dst, cc, u0, T, rs, pb.fa, 3 * r + 1, *k, so);
+    {
+      // last direction of the next row (the last row reloads its own: no branch, so
+      // that the wait counts stay exact)
+      const int rn = r > 0 ? r - 1 : 0;
+      const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
+      pull_all<M, ST, 1>(g, src, corr, 3 * rn + 2, ny, nz, dir_source<1>(g, l, row_source(g, l, ny, nz)), pc);
+    }
+    collide_fg_dir<M, ST, F, -1, VT>(g, dst, cc, rw, pa.fg, 3 * r, cy, cz, *k, so);
+    collide_species_dir<M, ST, F, -1>(g, dst, cc, u0, T, rs, pa.fa, 3 * r, *k, so);
+  }
+#else
   pull_all<M, ST, -1>(g, src, corr, 0, -1, -1, dir_source<-1>(g, l, row_source(g, l, -1, -1)), pa);
 #pragma unroll 1
   for (int r = 0; r < 9; ++r) {
@@ -1270,8 +1331,6 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
     collide_fg_dir<M, ST, F, 0, VT>(g, dst, cc, rw, pb.fg, 3 * r + 1, cy, cz, *k, so);
     collide_species_dir<M, ST, F, 0>(g, dst, cc, u0, T, rs, pb.fa, 3 * r + 1, *k, so);
     {
-      // first direction of the next row (the last row reloads its own: no branch, so
-      // that the wait counts stay exact)
       const int rn = r < 8 ? r + 1 : 8;
       const int ny = __builtin_amdgcn_readfirstlane(rn % 3 - 1), nz = __builtin_amdgcn_readfirstlane(rn / 3 - 1);
       pull_all<M, ST, -1>(g, src, corr, 3 * rn, ny, nz, dir_source<-1>(g, l, row_source(g, l, ny, nz)), pa);
@@ -1279,6 +1338,7 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
     collide_fg_dir<M, ST, F, 1, VT>(g, dst, cc, rw, pc.fg, 3 * r + 2, cy, cz, *k, so);
     collide_species_dir<M, ST, F, 1>(g, dst, cc, u0, T, rs, pc.fa, 3 * r + 2, *k, so);
   }
+#endif
 }
 
 // Fused step: the node-local part, then the collide pass from the coefficients in
@@ -1287,8 +1347,11 @@ __device__ __forceinline__ void collide_pass(const Geom &g, const void *src, voi
 // record goes through memory.
 // VT: relaxation rates from the temperature law of the transport (a separate build of
 // the kernel, so that the constant-rate kernel carries none of it)
+#ifndef LBM_STEP_WAVES_PER_SIMD
+#define LBM_STEP_WAVES_PER_SIMD 2
+#endif
 template <int M, typename ST, bool VT>
-__global__ __launch_bounds__(ISL_BLOCK, 2) void k_step(Geom g, Buffers b, int cur) {
+__global__ __launch_bounds__(ISL_BLOCK, LBM_STEP_WAVES_PER_SIMD) void k_step(Geom g, Buffers b, int cur) {
   using F = FT<ST>;
   __shared__ double words[IslWords<M>::WORDS * ISL_BLOCK];
   const IslStash sh{(lds_double *)&words[threadIdx.x]};
@@ -2375,6 +2438,38 @@ hipError_t launch_macros(const Geom &g, const Buffers &b, const CollideConsts &k
 hipError_t launch_export(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
                          const int64_t *nodes, int64_t n_nodes, double *out, double *T_out, hipStream_t st) {
   return dispatch<RunExport>(g.M, store, g, b, kc, cur, nodes, n_nodes, out, T_out, st);
+}
+
+// Streaming copy with 16-byte loads and stores, four per lane in flight, grid-stride
+// over the buffer: the read + write bandwidth a streaming kernel reaches on the chip.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                     int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * 256 * 4;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * 4 + threadIdx.x; base < n16; base += stride) {
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = base + (int64_t)k * 256;
+      if (i < n16) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = base + (int64_t)k * 256;
+      if (i < n16) dst[i] = v[k];
+    }
+  }
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t st) {
+  const int64_t n16 = bytes / 16;
+  if (n16 <= 0) return hipSuccess;
+  // 8 workgroups of 256 lanes per CU on the 256 CUs, each lane 4 x 16 bytes per round
+  const int64_t want = (n16 + 1023) / 1024;
+  const unsigned grid = (unsigned)(want < 2048 ? want : 2048);
+  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, static_cast<const u32x4 *>(src),
+                     static_cast<u32x4 *>(dst), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st) {

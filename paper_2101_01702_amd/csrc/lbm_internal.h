@@ -100,6 +100,18 @@ struct Buffers {
   double *diag;               // [8][ceil(N / 128)] partial sums of the diagnostics
 };
 
+// Work buffers of the discrete adjoint (in the workspace when lbm_desc.adjoint != 0).
+struct AdjBufHost {
+  double *P;            // [S][27][N] pulled populations of the forward state being reversed
+  double *Ln;           // [S][27][N] copy of the incoming adjoint
+  const double *T0;     // [N] stored temperature of that state (Newton start)
+  double *fY, *fw;      // [M][N] mass fractions and Cg weights of the forward state
+  double *lX, *lgY;     // [3][N] adjoint of X; [M][3][N] adjoint of grad Y_a
+  double *lpsi, *lphi;  // [3][N]
+  double *lYs;          // [M][N] adjoint of Y_a from the gradient stencil
+  double *part;         // [3R][ceil(N / 8)] Arrhenius gradient partials
+};
+
 // launchers (lbm_device.hip)
 hipError_t launch_init(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, const double *rho,
                        const double *u, const double *T, const double *Y, int cur, hipStream_t st);
@@ -122,10 +134,20 @@ hipError_t launch_diag(const Geom &g, const Buffers &b, const CollideConsts &kc,
 hipError_t launch_flame(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur, double T_iso,
                         const double *centre, double *work, double *out, double *totals, hipStream_t st);
 hipError_t launch_zero(void *p, int64_t n_words32, hipStream_t st);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
 // the scratch array of lbm_flame_speeds_static: its address on `device` (the current
 // device) is resolved once per device; then the flame speeds with their work fields and
 // partial sums in it (g.N <= LBM_FLAME_STATIC_MAX_NODES)
 hipError_t flame_scratch_resolve(int device);
+// launchers of the discrete adjoint (lbm_adjoint.hip); tb is the device copy of the tables
+hipError_t launch_adjoint_step(const Geom &g, const Tables *tb, const AdjBufHost &h, double omega, double omega1,
+                               int R, double *adj, double *grad, hipStream_t st);
+hipError_t launch_adjoint_macros(const Geom &g, const Tables *tb, const double *P, const double *T0,
+                                 const double *w_rho, const double *w_u, const double *w_T, const double *w_P,
+                                 const double *w_Y, double *adj, hipStream_t st);
+hipError_t launch_adjoint_init(const Geom &g, const Tables *tb, const double *rho, const double *u, const double *T,
+                               const double *Y, const double *lam, double *g_rho, double *g_u, double *g_T,
+                               double *g_Y, hipStream_t st);
 hipError_t launch_flame_static(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
                                int device, double T_iso, const double *centre, double *out, double *totals,
                                hipStream_t st);

@@ -39,7 +39,7 @@ class LbmDesc(C.Structure):
         ("nu_reac", _ip), ("nu_prod", _ip), ("arrhenius", _dp), ("reversible", _up),
         ("omega", C.c_double), ("omega1", C.c_double),
         ("kappa", C.c_double), ("dt_phys", C.c_double), ("rho_ref", C.c_double), ("p0", C.c_double),
-        ("storage", C.c_int32), ("reserved", C.c_int32), ("ref_state", C.c_void_p),
+        ("storage", C.c_int32), ("adjoint", C.c_int32), ("ref_state", C.c_void_p),
         ("n_segments", C.c_int32), ("reserved2", C.c_int32), ("segment_lengths", _ip),
         ("diff_T_ref", C.c_double), ("diff_T_exp", C.c_double),
         ("visc_T_ref", C.c_double), ("visc_T_exp", C.c_double),
@@ -56,7 +56,9 @@ _lib = None
 
 EXPORTS = ("lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_init_fields", "lbm_step",
            "lbm_step_timed", "lbm_step_graph", "lbm_macros", "lbm_populations", "lbm_diagnostics",
-           "lbm_flame_speeds", "lbm_flame_speeds_static", "lbm_adjoint_step",
+           "lbm_flame_speeds", "lbm_flame_speeds_static", "lbm_state_size", "lbm_state_save",
+           "lbm_state_load", "lbm_set_arrhenius", "lbm_adjoint_step", "lbm_adjoint_macros", "lbm_adjoint_init",
+           "lbm_stream_copy",
            "lbm_status_sync", "lbm_last_error")
 DIAG_TOTALS = 4   # heat release rate, nodes with T >= T_iso, mass, total energy
 FLAME_WORK = 17   # FP64 work fields per node of lbm_flame_speeds
@@ -86,7 +88,14 @@ def load(path: Optional[str] = None):
     lib.lbm_diagnostics.argtypes = [vp, C.c_double, vp, vp, vp]
     lib.lbm_flame_speeds.argtypes = [vp, C.c_double, C.POINTER(C.c_double), vp, vp, vp, vp]
     lib.lbm_flame_speeds_static.argtypes = [vp, C.c_double, C.POINTER(C.c_double), vp, vp, vp]
+    lib.lbm_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.lbm_state_save.argtypes = [vp, vp, vp]
+    lib.lbm_state_load.argtypes = [vp, vp, vp]
+    lib.lbm_set_arrhenius.argtypes = [vp, C.POINTER(C.c_double), vp]
     lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_adjoint_macros.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.lbm_adjoint_init.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
     lib.lbm_status_sync.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = C.c_char_p
@@ -102,7 +111,7 @@ def _c64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def make_desc(prob, storage: Optional[int] = None):
+def make_desc(prob, storage: Optional[int] = None, adjoint: bool = False):
     """lbm_desc of a workloads.Problem; returns (desc, arrays kept alive)."""
     mech = prob.mech
     keep = dict(molar_mass=_c64(mech.molar_mass), nasa7=_c64(mech.nasa7), diff=_c64(prob.diff),
@@ -125,6 +134,7 @@ def make_desc(prob, storage: Optional[int] = None):
     d.omega, d.omega1 = prob.omega, prob.omega1
     d.kappa, d.dt_phys, d.rho_ref, d.p0 = prob.kappa, prob.dt_phys, prob.rho_ref, prob.p0
     d.storage = prob.storage if storage is None else storage
+    d.adjoint = 1 if adjoint else 0
     d.diff_T_ref = float(getattr(prob, "diff_T_ref", 0.0))
     d.diff_T_exp = float(getattr(prob, "diff_T_exp", 0.0))
     d.visc_T_ref = float(getattr(prob, "visc_T_ref", 0.0))
@@ -159,7 +169,7 @@ def workspace_size(prob, storage: Optional[int] = None) -> int:
 class Solver:
     """One lattice on one HIP device, advanced by the HIP library."""
 
-    def __init__(self, prob, storage: Optional[int] = None, device=None):
+    def __init__(self, prob, storage: Optional[int] = None, device=None, adjoint: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the reactive LBM step runs only on the GPU")
@@ -171,7 +181,8 @@ class Solver:
         self.N = prob.N
         self.device = (torch.device(device) if device is not None
                        else torch.device("cuda", torch.cuda.current_device()))
-        self.desc, self._keep = make_desc(prob, storage)
+        self.desc, self._keep = make_desc(prob, storage, adjoint)
+        self.adjoint = bool(adjoint)
         self.storage = self.desc.storage
         self.ref_state = self._keep.get("ref_state")
         n = C.c_size_t(0)
@@ -321,6 +332,68 @@ class Solver:
             t.cuda.synchronize(self.device)
             return out.cpu().numpy(), Tn.cpu().numpy()
         return out, Tn
+
+    # ---- state snapshots and the discrete adjoint -------------------------------------
+    def state_size(self) -> int:
+        n = C.c_size_t(0)
+        self._check(self.lib.lbm_state_size(self.h, C.byref(n)), self.h)
+        return int(n.value)
+
+    def new_state_buffer(self):
+        """A device buffer for one state snapshot (256-byte aligned view of a uint8 tensor)."""
+        t = self.torch
+        n = self.state_size()
+        raw = t.empty(n + 256, dtype=t.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        return raw[off:off + n]
+
+    def state_save(self, buf=None):
+        buf = self.new_state_buffer() if buf is None else buf
+        self._check(self.lib.lbm_state_save(self.h, C.c_void_p(buf.data_ptr()), self._stream()), self.h)
+        return buf
+
+    def state_load(self, buf):
+        self._check(self.lib.lbm_state_load(self.h, C.c_void_p(buf.data_ptr()), self._stream()), self.h)
+
+    def set_arrhenius(self, arrhenius):
+        """Replace the reactions' (A, b, Ta) [R, 3] (host values)."""
+        arr = np.ascontiguousarray(arrhenius, dtype=np.float64).reshape(-1)
+        self._keep["arrhenius_set"] = arr
+        self._check(self.lib.lbm_set_arrhenius(self.h, arr.ctypes.data_as(_dp), self._stream()), self.h)
+
+    def _ptr(self, a):
+        return C.c_void_p(0) if a is None else C.c_void_p(a.data_ptr())
+
+    def adjoint_macros(self, state=None, w_rho=None, w_u=None, w_T=None, w_P=None, w_Y=None):
+        """Adjoint populations [S, 27, N] (device FP64) of sum over nodes of the weighted
+        macroscopic fields at a snapshot (None: the current state)."""
+        t = self.torch
+        ws = [None if w is None else self._dev(w) for w in (w_rho, w_u, w_T, w_P, w_Y)]
+        out = t.empty(self.S, 27, self.N, dtype=t.float64, device=self.device)
+        self._check(self.lib.lbm_adjoint_macros(self.h, self._ptr(state), *(self._ptr(w) for w in ws),
+                                                C.c_void_p(out.data_ptr()), self._stream()), self.h)
+        return out
+
+    def adjoint_step(self, lam, state=None, grad=None):
+        """lambda_n from lambda_{n+1} (device FP64 [S, 27, N], updated in place) at the
+        snapshot of step n; grad [R, 3] (device FP64) is incremented."""
+        self._check(self.lib.lbm_adjoint_step(self.h, self._ptr(state), C.c_void_p(lam.data_ptr()),
+                                              self._ptr(grad), self._stream()), self.h)
+        return lam
+
+    def adjoint_init(self, lam0, rho=None, u=None, T=None, Y=None):
+        """Gradients (rho, u, T, Y) of sum(lam0 * pop_0) through the equilibrium initial
+        state of the given fields (default: the problem's)."""
+        t = self.torch
+        p = self.prob
+        N, M = self.N, self.M
+        f = [self._dev(p.rho if rho is None else rho).reshape(N), self._dev(p.u if u is None else u).reshape(3, N),
+             self._dev(p.T if T is None else T).reshape(N), self._dev(p.Y if Y is None else Y).reshape(M, N)]
+        g = [t.empty_like(a) for a in f]
+        self._check(self.lib.lbm_adjoint_init(self.h, *(C.c_void_p(a.data_ptr()) for a in f),
+                                              C.c_void_p(lam0.data_ptr()), *(C.c_void_p(a.data_ptr()) for a in g),
+                                              self._stream()), self.h)
+        return dict(rho=g[0], u=g[1], T=g[2], Y=g[3])
 
     def status(self) -> int:
         bits = C.c_uint32(0)

@@ -406,6 +406,15 @@ def flame1d(nx: int = 4096, seed: int = FLAME_SEED, phi: float = 1.0, T_u: float
                    rho, u, T, Y, steps=steps, storage=storage, ref_state=ref)
 
 
+def adjoint_flame(nx: int = 2048, storage: int = STORE_F64) -> Problem:
+    """The flame of the discrete-adjoint workload: the quasi-1D premixed flame of
+    ``flame1d`` on 2048 cells (9 species, 19 reactions, 64-cell hot slab), reversed over
+    4000 steps with a snapshot every 100 steps."""
+    prob = flame1d(nx=nx, storage=storage, steps=4000)
+    prob.name = f"adjoint_flame1d_{nx}"
+    return prob
+
+
 def flame_batch(n_flames: int = 256, seed: int = FLAME_SEED, len_range=(512, 8192), phi_range=(0.5, 3.0),
                 T_u: float = 300.0, T_hot: float = 2000.0, hot_cells: int = 64, zeta_ref: float = 0.003,
                 omega: float = 1.0, prandtl: float = 0.7, dt_phys: float = 3e-10,

@@ -198,7 +198,57 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lbm_step_graph(None, 2, None) == -1
     assert lib.lbm_flame_speeds(None, 900.0, None, None, None, None, None) == -1
     assert lib.lbm_flame_speeds_static(None, 900.0, None, None, None, None) == -1
-    assert lib.lbm_adjoint_step(None, None, None, None, None) == -2
+    assert lib.lbm_adjoint_step(None, None, None, None, None) == -1
+    assert lib.lbm_adjoint_macros(None, None, None, None, None, None, None, None, None) == -1
+    assert lib.lbm_adjoint_init(None, None, None, None, None, None, None, None, None, None, None) == -1
+    assert lib.lbm_state_save(None, None, None) == -1
+    assert lib.lbm_state_load(None, None, None) == -1
+    assert lib.lbm_state_size(None, None) == -1
+    assert lib.lbm_set_arrhenius(None, None, None) == -1
+
+
+def test_adjoint_workspace_and_scope(lib):
+    """The adjoint's work buffers enlarge the workspace; descriptors outside its scope
+    (16-bit storage, symmetry faces, batches, temperature-dependent transport) are
+    refused with LBM_ERR_UNSUPPORTED."""
+    prob = W.flame1d(nx=64, hot_cells=8)
+    d, keep = lbm.make_desc(prob)
+    code, plain, msg = _ws(lib, d)
+    assert code == 0, msg
+    d.adjoint = 1
+    code, with_adj, msg = _ws(lib, d)
+    assert code == 0, msg
+    S, N, M = prob.M + 1, prob.N, prob.M
+    assert with_adj - plain >= (2 * S * 27 + 6 * M + 9) * N * 8
+    for field, value in (("storage", W.STORE_F16_DEV), ("diff_T_exp", 0.5), ("visc_T_exp", 0.5)):
+        d2, keep2 = lbm.make_desc(prob, storage=value if field == "storage" else None, adjoint=True)
+        setattr(d2, field, value)
+        if field == "diff_T_exp":
+            d2.diff_T_ref = 300.0
+        if field == "visc_T_exp":
+            d2.visc_T_ref = 300.0
+        code, _, msg = _ws(lib, d2)
+        assert code == -2, (field, code, msg)
+    sym = W.sphere3d(shape=(6, 5, 4), radius=1.5, storage=W.STORE_F64)
+    sym.bc = (W.BC_SYMMETRY, W.BC_OPEN, W.BC_OPEN, W.BC_OPEN, W.BC_OPEN, W.BC_OPEN)
+    d3, keep3 = lbm.make_desc(sym, adjoint=True)
+    code, _, msg = _ws(lib, d3)
+    assert code == -2 and "symmetry" in msg
+    batch = W.flame_batch(lengths=[7, 5], phis=[1.0, 1.0], hot_cells=3, storage=W.STORE_F64)
+    d4, keep4 = lbm.make_desc(batch, adjoint=True)
+    code, _, msg = _ws(lib, d4)
+    assert code == -2 and "segments" in msg
+
+
+def test_large_slab_needs_no_24_bit_products(lib):
+    """A slab of more than 2^24 padded rows is a valid lattice: the step kernel forms row
+    and cell indices with full 32-bit products."""
+    prob = W.config1(nx=1, ny=4, nz=4)
+    d, keep = lbm.make_desc(prob)
+    d.ny, d.nz = 4100, 4100
+    d.bc = (C.c_int32 * 6)(W.BC_PERIODIC, W.BC_PERIODIC, W.BC_OPEN, W.BC_OPEN, W.BC_OPEN, W.BC_OPEN)
+    code, n, msg = _ws(lib, d)
+    assert code == 0, msg
 
 
 def test_segment_descriptors(lib):
