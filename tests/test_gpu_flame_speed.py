@@ -70,26 +70,49 @@ def test_flame_speed_matches_oracle(lbm_mod, oracle_speed, storage):
     assert rel <= 5e-3
 
 
-def test_full_size_flame_speed_fp32_against_fp64(lbm_mod):
-    """The 4096-cell flame over 20 000 steps: S_L from a least-squares line through the
-    front position every 100 steps over steps 10 000..20 000, FP32 storage against FP64
-    storage (both on the GPU; the FP64 path is the oracle's to 1e-12 at this size),
-    within 0.5%.  The oracle itself would take minutes for this run."""
-    speeds = {}
-    for storage in (W.STORE_F64, W.STORE_F32):
-        prob = W.flame1d(nx=4096)
-        s = lbm_mod.Solver(prob, storage=storage).init()
-        xs, ts = [], []
-        for n in range(100, 20001, 100):
-            s.step_graph(100)
-            if n >= 10000:
-                xs.append(front(s.macros()["T"], 300.0))
-                ts.append(n)
-        assert s.status() == 0
-        speeds[storage] = -np.polyfit(np.array(ts, float), np.array(xs), 1)[0]
-        s.close()
-    ref, got = speeds[W.STORE_F64], speeds[W.STORE_F32]
+def _golden_4096():
+    """The oracle's S_L and front positions of the 4096-cell flame over 20 000 steps,
+    written by tests/golden/make_flame_speed.py (oracle only)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "flame_speed_4096.txt")
+    speed, ts, xs = None, [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            key, val = line.split()
+            if key == "S_L":
+                speed = float(val)
+            else:
+                ts.append(int(key))
+                xs.append(float(val))
+    return speed, np.array(ts), np.array(xs)
+
+
+@pytest.mark.parametrize("storage", [W.STORE_F64, W.STORE_F32])
+def test_full_size_flame_speed_against_oracle_golden(lbm_mod, storage):
+    """The 4096-cell flame over 20 000 steps (steps replayed from a graph, 100 at a time):
+    S_L from a least-squares line through the front every 100 steps over steps
+    10 000..20 000, against the oracle's value stored in tests/golden, within 0.5%.  The
+    FP64 path's fronts also match the oracle's to 1e-6 cells."""
+    ref, ref_ts, ref_xs = _golden_4096()
+    prob = W.flame1d(nx=4096)
+    s = lbm_mod.Solver(prob, storage=storage).init()
+    xs, ts = [], []
+    for n in range(100, 20001, 100):
+        s.step_graph(100)
+        if n >= 10000:
+            xs.append(front(s.macros()["T"], 300.0))
+            ts.append(n)
+    assert s.status() == 0
+    s.close()
+    assert np.array_equal(np.array(ts), ref_ts)
+    got = -np.polyfit(np.array(ts, float), np.array(xs), 1)[0]
     rel = abs(got - ref) / ref
-    print(f"[flame1d 4096, 20k steps] S_L fp64 {ref:.6e} fp32 {got:.6e} cells/step, rel diff {rel:.2e}", flush=True)
+    shift = float(np.abs(np.array(xs) - ref_xs).max())
+    print(f"[flame1d 4096, 20k steps, storage={storage}] S_L gpu {got:.9e} oracle {ref:.9e} cells/step, "
+          f"rel diff {rel:.2e}, max front shift {shift:.2e} cells", flush=True)
     assert ref > 0.003
     assert rel <= 5e-3
+    if storage == W.STORE_F64:
+        assert shift <= 1e-6
