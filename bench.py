@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -48,37 +50,77 @@ def recorded_traffic(kernel):
     return rec
 
 
-def copy_ceiling_gbs(torch, dev, nbytes=4 << 30, reps=5):
-    """Read+write bandwidth of a plain device copy (measured ceiling)."""
+def copy_ceiling_gbs(torch, dev, lbm=None, nbytes=4 << 30, reps=5):
+    """Read+write bandwidth of a plain device copy: torch's copy (the runtime's copy
+    kernel) and, with the library, its hand-written streaming copy of 16-byte loads and
+    stores (lbm_stream_copy).  Returns (runtime copy, streaming kernel) in GB/s."""
+    import ctypes as C
     a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize(dev)
-    dt = (time.perf_counter() - t0) / reps
+    out = []
+    for kind in ("runtime", "stream"):
+        if kind == "stream" and lbm is None:
+            out.append(None)
+            continue
+        def once():
+            if kind == "runtime":
+                b.copy_(a)
+            else:
+                st = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+                rc = lbm.load().lbm_stream_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), nbytes, st)
+                if rc != 0:
+                    raise RuntimeError("lbm_stream_copy failed")
+        once()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize(dev)
+        out.append(2.0 * nbytes / ((time.perf_counter() - t0) / reps) / 1e9)
     del a, b
     torch.cuda.empty_cache()
-    return 2.0 * nbytes / dt / 1e9
+    return tuple(out)
 
 
-def cpu_baseline(seconds=12.0):
-    """FP64 CPU oracle on a 32^3 crop of the same workload, time-boxed."""
+def host_cpu():
+    """(CPU model, logical CPUs the host reports, threads the oracle may use: the box's
+    share of 16)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    n = os.cpu_count() or 1
+    return model, n, max(1, min(16, n))
+
+
+def _oracle_rate(prob, threads, seconds):
     from oracle import oracle as orc
-    from paper_2101_01702_amd import workloads as W
-    cores = max(1, min(16, os.cpu_count() or 1))
-    prob = W.sphere3d(shape=(32, 32, 32))
     sim = orc.OracleSim(prob).init()
-    sim.step(1, cores)
+    sim.step(1, threads)
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds or steps < 2:
-        sim.step(1, cores)
+        sim.step(1, threads)
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": round(prob.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"32^3 crop of the same spherical flame (M=9, R=19, FP64), {steps} steps, {dt:.1f} s"}
+    return prob.N * steps / dt / 1e6, steps, dt
+
+
+def cpu_baseline(prob=None, label="32^3 crop of the same spherical flame", seconds=8.0):
+    """FP64 CPU oracle on a bounded sample of the workload, time-boxed: on all the
+    threads of the machine's CPU share and on one thread."""
+    from paper_2101_01702_amd import workloads as W
+    model, nproc, cores = host_cpu()
+    prob = prob or W.sphere3d(shape=(32, 32, 32))
+    v_all, st_all, dt_all = _oracle_rate(prob, cores, seconds)
+    v_one, st_one, dt_one = _oracle_rate(prob, 1, seconds)
+    return {"value": round(v_all, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{label} (M=9, R=19, FP64): {st_all} steps in {dt_all:.1f} s on {cores} threads, "
+                      f"{st_one} steps in {dt_one:.1f} s on 1 thread",
+            "single_thread_value": round(v_one, 4), "nproc": nproc, "cpu_model": model}
 
 
 def error_vs_f64(lbm, W, storage, steps=100):
@@ -129,19 +171,61 @@ def error_vs_f64_full(lbm, W, storage, n, steps):
     return {"max_rel": max(errs.values()), "fields": errs, "steps": steps, "lattice": f"{n}^3"}
 
 
-def cpu_baseline_flame(prob, seconds=12.0):
+def cpu_baseline_flame(prob):
     """FP64 CPU oracle on one flame of the batch (the shortest), time-boxed."""
-    from oracle import oracle as orc
-    cores = max(1, min(16, os.cpu_count() or 1))
-    sim = orc.OracleSim(prob).init()
-    sim.step(1, cores)
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds or steps < 2:
-        sim.step(1, cores)
-        steps += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(prob.N * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"one flame of the batch ({prob.nx} cells, M=9, R=19, FP64), {steps} steps, {dt:.1f} s"}
+    return cpu_baseline(prob, f"one flame of the batch ({prob.nx} cells)")
+
+
+def adjoint_cost(torch, lbm, W, dev, storage, every=100):
+    """Cost of the discrete adjoint on its workload (the 2048-cell quasi-1D flame, 4000
+    steps, a snapshot every `every` steps): the forward alone (steps replayed from a
+    graph) against the whole gradient (forward with snapshots, then every segment
+    recomputed and reversed step by step), and one adjoint step against one forward
+    step."""
+    from paper_2101_01702_amd import adjoint as A
+    prob = W.adjoint_flame(storage=storage)
+    steps = 4000
+    sync = lambda: torch.cuda.synchronize(dev)
+    s = lbm.Solver(prob, storage=storage, device=dev, adjoint=True).init()
+    s.step_graph(steps)                      # records the graph
+    s.init()
+    sync()
+    t0 = time.perf_counter()
+    s.step_graph(steps)
+    sync()
+    fwd = time.perf_counter() - t0
+    theta = torch.tensor(A.theta_of(prob.mech), dtype=torch.float64, requires_grad=True)
+    T0 = torch.tensor(prob.T, dtype=torch.float64, requires_grad=True)
+    sync()
+    t0 = time.perf_counter()
+    J = A.FlameFront.apply(s, theta, T0, steps, every)
+    J.backward()
+    sync()
+    grad_wall = time.perf_counter() - t0
+    # one adjoint step against one forward step, both eager, over 200 steps of the flame
+    snap = s.state_save()
+    lam = torch.ones(s.S, 27, s.N, dtype=torch.float64, device=dev)
+    g = torch.zeros(prob.mech.R, 3, dtype=torch.float64, device=dev)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        s.step(1)
+    sync()
+    f1 = (time.perf_counter() - t0) / 200
+    t0 = time.perf_counter()
+    for _ in range(200):
+        s.adjoint_step(lam, state=snap, grad=g)
+    sync()
+    a1 = (time.perf_counter() - t0) / 200
+    ok = bool(np.isfinite(theta.grad.numpy()).all() and np.isfinite(T0.grad.numpy()).all())
+    anomaly = s.status()
+    s.close()
+    return {"workload": f"quasi-1D flame of {prob.N} cells, 9 species, 19 reactions, {steps} steps, snapshot every "
+                        f"{every}, {('f64', 'f32')[storage]} storage, FP64 adjoint",
+            "gradient_over_forward": round(grad_wall / fwd, 3), "forward_s": round(fwd, 4),
+            "gradient_s": round(grad_wall, 4), "adjoint_step_ms": round(a1 * 1e3, 4),
+            "forward_step_ms": round(f1 * 1e3, 4), "adjoint_step_over_forward_step": round(a1 / f1, 3),
+            "parameters": int(3 * prob.mech.R), "finite": ok, "anomaly_bits": anomaly}
 
 
 def bench_flame_batch(args, torch, lbm, W, dev):
@@ -208,10 +292,11 @@ def bench_flame_batch(args, torch, lbm, W, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": f"batch of {len(parts)} quasi-1D flames, {N} cells (512..8192 each), 9 species, "
-                               "19 reversible reactions, f32 population storage, FP64 node-local arithmetic",
+                               "19 reversible reactions, f32 population storage; FP64 temperature, thermo, rates and "
+                               "Stefan-Maxwell solve, FP32 inter-species term",
                    "flames": len(parts), "cells": N, "species": M, "reactions": 19, "storage": "f32",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_step", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -241,7 +326,10 @@ def main():
                     help="population storage (f16dev/bf16dev: 16-bit deviations from the reference state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--copy-only", action="store_true", help="run only the copy kernel (counter calibration)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint cost measurement (profiling the adjoint kernels)")
     ap.add_argument("--full-error-steps", type=int, default=0,
                     help="also measure the field error against FP64 storage at full size after this many steps")
     args = ap.parse_args()
@@ -258,7 +346,13 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.copy_only:
-        print(json.dumps({"copy_ceiling_GBps": round(copy_ceiling_gbs(torch, dev), 1), "bytes": 2 * (4 << 30)}))
+        cc = copy_ceiling_gbs(torch, dev, lbm)
+        print(json.dumps({"copy_ceiling_GBps": {"runtime_copy": round(cc[0], 1), "stream_kernel": round(cc[1], 1)},
+                          "bytes": 2 * (4 << 30)}))
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100),
+                          "adjoint_all_states": adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=1)}))
         return
     if args.workload == "flame_batch":
         bench_flame_batch(args, torch, lbm, W, dev)
@@ -315,10 +409,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": f"spherical flame {args.n}^3 D3Q27, 9 species, 19 reversible reactions, "
-                               f"{args.storage} population storage, FP64 node-local arithmetic",
+                               f"{args.storage} population storage; FP64 temperature, thermo, rates and "
+                               "Stefan-Maxwell solve, FP32 inter-species term",
                    "lattice": [args.n] * 3, "species": M, "reactions": 19, "storage": args.storage,
                    "parallelism": "single GPU"},
         "roofline": roofline,
@@ -330,7 +425,12 @@ def main():
         out["error_vs_f64"] = error_vs_f64(lbm, W, storage)
     if args.full_error_steps > 0 and storage != W.STORE_F64:
         out["error_vs_f64_full"] = error_vs_f64_full(lbm, W, storage, args.n, args.full_error_steps)
-    out["copy_ceiling_GBps"] = round(copy_ceiling_gbs(torch, dev), 1)
+    cc_runtime, cc_stream = copy_ceiling_gbs(torch, dev, lbm)
+    out["copy_ceiling_GBps"] = {"runtime_copy": round(cc_runtime, 1), "stream_kernel": round(cc_stream, 1)}
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100)
+        out["adjoint_all_states"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=1)
+        out["adjoint_forward_cost"] = out["adjoint"]["gradient_over_forward"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

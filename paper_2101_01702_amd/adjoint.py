@@ -8,9 +8,11 @@ of the front position of Sec. 5.1):
 a function of the Arrhenius parameters theta = (ln A_k, b_k, Ta_k) of every reaction and
 of the initial temperature field T_0 (with the other initial fields held).  ``FlameFront``
 is a torch.autograd.Function: its forward runs the n steps on the GPU, keeping a
-snapshot every K steps; its backward walks the segments from the last, recomputes the K
-states of each from its snapshot and applies the library's adjoint step to each in
-reverse order (lbm_adjoint_macros for the seed, lbm_adjoint_step per step,
+snapshot every K steps; its backward walks the segments from the last, recomputes the
+K - 1 states of each after its snapshot and applies the library's adjoint step to each in
+reverse order.  K = 1 keeps every state resident (about 1.1 kB per node and step in FP32
+storage with nine species: 9 GB for the 2048-cell flame's 4000 steps) and recomputes
+nothing (lbm_adjoint_macros for the seed, lbm_adjoint_step per step,
 lbm_adjoint_init for T_0).  Only argument marshalling happens here: every step and
 every adjoint step runs in the HIP library.
 """
@@ -58,12 +60,15 @@ class FlameFront:
                 w = torch.full((solver.N,), float(gJ) / (T_b - T_u), dtype=torch.float64, device=solver.device)
                 lam = solver.adjoint_macros(state=ctx.final, w_T=w)
                 grad = torch.zeros(max(R, 1), 3, dtype=torch.float64, device=solver.device)
+                ring = [solver.new_state_buffer() for _ in range(max(every - 1, 0))]
                 for snap, k in reversed(ctx.snaps):
-                    states = []
-                    solver.state_load(snap)
-                    for _ in range(k):
-                        states.append(solver.state_save())
-                        solver.step(1)
+                    # the segment's states: its snapshot, then k - 1 recomputed steps
+                    states = [snap]
+                    if k > 1:
+                        solver.state_load(snap)
+                        for j in range(k - 1):
+                            solver.step(1)
+                            states.append(solver.state_save(ring[j]))
                     for st in reversed(states):
                         solver.adjoint_step(lam, state=st, grad=grad)
                 g0 = solver.adjoint_init(lam, T=ctx.t0)

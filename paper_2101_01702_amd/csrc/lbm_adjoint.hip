@@ -70,26 +70,61 @@ __device__ __forceinline__ PhiD phi_d(int i, const double u[3], double z) {
 }
 
 // ---- NASA-7 (eq. specHa): h/RT, s/R, cp/R ------------------------------------------------
-__device__ __forceinline__ double a_hRT(const double *a, double T) {
+template <class P>
+__device__ __forceinline__ double a_hRT(P a, double T) {
   return a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * (a[4] * 0.2)))) + a[5] / T;
 }
-__device__ __forceinline__ double a_sR(const double *a, double T, double lnT) {
+template <class P>
+__device__ __forceinline__ double a_sR(P a, double T, double lnT) {
   return a[0] * lnT + T * (a[1] + T * (a[2] * 0.5 + T * (a[3] * (1.0 / 3.0) + T * (a[4] * 0.25)))) + a[6];
 }
-__device__ __forceinline__ double a_cpR(const double *a, double T) {
+template <class P>
+__device__ __forceinline__ double a_cpR(P a, double T) {
   return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
 }
 
-__device__ __forceinline__ double invD(const Tables &tb, int M, int a, int b) {
+template <class TB>
+__device__ __forceinline__ double invD(TB &tb, int M, int a, int b) {
   const int lo = a < b ? a : b, hi = a < b ? b : a;
   return tb.invDp[lo * M - lo * (lo + 1) / 2 + (hi - lo - 1)];
 }
 
-// butterfly sum over the 32 lanes of a node group; every lane gets the total
+// Sum over the 32 lanes of a node group; every lane gets the total.  Within each row of
+// 16 lanes by DPP moves (swap neighbours, swap pairs, then rotations by 4 and by 8), then
+// across the two rows by a swizzle that exchanges lanes l and l ^ 16.  The moves act on
+// the two 32-bit halves of the double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double swz_xor16(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(__double_as_longlong(v) & 0xffffffff), 0x401f);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(__double_as_longlong(v) >> 32), 0x401f);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int m = GL / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, GL);
+  v += dpp_mov<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x128>(v);   // row_ror:8
+  v += swz_xor16(v);        // bit-mask swizzle: and 0x1f, xor 0x10
   return v;
+}
+
+// LDS-qualified types for the node-level chains.  Those are out-of-line functions, where a
+// plain pointer argument has no known address space and every access through it would
+// take the flat path; the record and the workgroup's copy of the tables are passed as
+// LDS pointers instead.
+typedef __attribute__((address_space(3))) double lds_double;
+typedef const __attribute__((address_space(3))) Tables lds_tables;
+
+// the workgroup's copy of the tables (sizeof(Tables) is a multiple of 8)
+__device__ __forceinline__ void tables_to_lds(const Tables *src, Tables *dst) {
+  const double *s = reinterpret_cast<const double *>(src);
+  double *d = reinterpret_cast<double *>(dst);
+  for (int k = threadIdx.x; k < (int)(sizeof(Tables) / 8); k += blockDim.x) d[k] = s[k];
 }
 
 // ---- record of one node in LDS ---------------------------------------------------------
@@ -127,7 +162,11 @@ struct Rec {
   enum { W_LY, W_LZA, W_LHA, W_LRS, W_LC, W_LT, W_LRDOT, W_LJA, W_MU = W_LJA + 3, WPW = W_MU + 3 };
   static constexpr int WK = M_JA + 3 * M;
   static constexpr int wk(int a, int f) { return WK + a * WPW + f; }
-  static constexpr int WORDS = WK + M * WPW;
+  // scalar adjoints carried from the first part of the reverse chain to the last
+  enum { C_LRHO, C_LU, C_LZETA = C_LU + 3, C_LH, C_LPT, C_LRHOE, C_LQ, C_LPM = C_LQ + 3, C_LUMIX = C_LPM + 9, C_LT,
+         C_LA1, CPW = C_LA1 + 3 };
+  static constexpr int SC = WK + M * WPW;
+  static constexpr int WORDS = SC + CPW;
 };
 
 // ---- moments of the pulled populations on a lane's direction ---------------------------
@@ -164,197 +203,220 @@ __device__ __forceinline__ void group_moments(int i, bool valid, const double *f
   }
 }
 
-// ---- node-level forward (first lane of the group) ----------------------------------------
-// Macros (O1), temperature (O2), thermo, production rates (O3), Stefan-Maxwell (O4) and
-// the collision coefficients, into the record.
+// ---- node-level forward ---------------------------------------------------------------------
+// Called by every lane of a node's group (ok: the group holds a node), which all hold the
+// node's moments: lane a < M takes species a, sums over species are group sums, and the
+// Newton iteration for the temperature runs on every lane alike.  Macros (O1),
+// temperature (O2) and thermo into the record (node_forward); the production rates (O3)
+// one reaction per lane (fwd_rate) and one species per lane (fwd_rdot); Stefan-Maxwell
+// (O4) and the collision coefficients (fwd_sm).
 template <int M>
-__device__ __noinline__ void node_forward(const Tables &tb, const Mom<M> &m, double T0, volatile double *r, bool rates_and_sm) {
+__device__ __noinline__ void node_forward(lds_tables &tb, const Mom<M> &m, double T0, lds_double *r, int lane,
+                                         bool ok, bool rates_and_sm) {
   using RC = Rec<M>;
   const double rho = m.rho, inv_rho = 1.0 / rho;
   double u[3];
   for (int d = 0; d < 3; ++d) u[d] = m.j[d] * inv_rho;
-  r[RC::RHO] = rho;
-  r[RC::RHOE] = m.rhoE;
-  for (int d = 0; d < 3; ++d) {
-    r[RC::U + d] = u[d];
-    r[RC::QM + d] = m.q[d];
-    for (int e = 0; e < 3; ++e) r[RC::PT + 3 * d + e] = m.P[d][e];
+  if (ok && lane == 0) {
+    r[RC::RHO] = rho;
+    r[RC::RHOE] = m.rhoE;
+    for (int d = 0; d < 3; ++d) {
+      r[RC::U + d] = u[d];
+      r[RC::QM + d] = m.q[d];
+      for (int e = 0; e < 3; ++e) r[RC::PT + 3 * d + e] = m.P[d][e];
+    }
   }
   // species densities and momenta; the last species is slaved (eq. strongest)
   double rsum = 0.0, jsum[3] = {0.0, 0.0, 0.0};
   for (int a = 0; a < M - 1; ++a) {
-    r[RC::sp(a, RC::S_RS)] = m.ra[a];
     rsum += m.ra[a];
-    for (int d = 0; d < 3; ++d) {
-      r[RC::sp(a, RC::S_JA + d)] = m.ja[a][d];
-      jsum[d] += m.ja[a][d];
+    for (int d = 0; d < 3; ++d) jsum[d] += m.ja[a][d];
+  }
+  const int a = lane;
+  const bool sp = a < M;
+  double Y = 0.0;
+  if (sp) {
+    const double rs = a < M - 1 ? m.ra[a] : rho - rsum;
+    double ja[3];
+    for (int d = 0; d < 3; ++d) ja[d] = a < M - 1 ? m.ja[a][d] : m.j[d] - jsum[d];
+    Y = rs * inv_rho;
+    const bool tiny = fabs(rs) < 1e-300;
+    if (ok) {
+      r[RC::sp(a, RC::S_RS)] = rs;
+      r[RC::sp(a, RC::S_Y)] = Y;
+      r[RC::sp(a, RC::S_TINY)] = tiny ? 1.0 : 0.0;
+      for (int d = 0; d < 3; ++d) {
+        r[RC::sp(a, RC::S_JA + d)] = ja[d];
+        r[RC::sp(a, RC::S_RA + d)] = tiny ? 0.0 : ja[d] / rs - u[d];
+      }
     }
   }
-  r[RC::sp(M - 1, RC::S_RS)] = rho - rsum;
-  for (int d = 0; d < 3; ++d) r[RC::sp(M - 1, RC::S_JA + d)] = m.j[d] - jsum[d];
   uint32_t anom = 0;
   if (!(rho > 0.0) || !(rho - rsum > 0.0)) anom |= LBM_ANOM_NEG_DENSITY;
-  for (int a = 0; a < M; ++a) {
-    const double rs = r[RC::sp(a, RC::S_RS)];
-    r[RC::sp(a, RC::S_Y)] = rs * inv_rho;
-    const bool tiny = fabs(rs) < 1e-300;
-    r[RC::sp(a, RC::S_TINY)] = tiny ? 1.0 : 0.0;
-    for (int d = 0; d < 3; ++d) r[RC::sp(a, RC::S_RA + d)] = tiny ? 0.0 : r[RC::sp(a, RC::S_JA + d)] / rs - u[d];
-  }
   // temperature: sum_a Y_a U_a(T) = rhoE / rho - u^2 / 2 (Newton from the stored value)
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const double e = m.rhoE * inv_rho - 0.5 * usq;
-  double ec[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, dc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int a = 0; a < M; ++a) {
-    const double Y = r[RC::sp(a, RC::S_Y)];
-    for (int k = 0; k < 6; ++k) ec[k] += Y * tb.ucoef[a][k];
-    for (int k = 0; k < 5; ++k) dc[k] += Y * tb.cvcoef[a][k];
-  }
+  double ec[6], dc[5];
+  for (int k = 0; k < 6; ++k) ec[k] = gsum(sp ? Y * tb.ucoef[a][k] : 0.0);
+  for (int k = 0; k < 5; ++k) dc[k] = gsum(sp ? Y * tb.cvcoef[a][k] : 0.0);
   double T = T0;
-  int ok = 0;
+  int conv = 0;
   for (int it = 0; it < 50; ++it) {
     const double ev = ec[0] + T * (ec[1] + T * (ec[2] + T * (ec[3] + T * (ec[4] + T * ec[5])))) - e;
     const double dv = dc[0] + T * (dc[1] + T * (dc[2] + T * (dc[3] + T * dc[4])));
     const double dT = -ev / dv;
     T += dT;
     if (fabs(dT) <= 1e-12 * fabs(T)) {
-      ok = 1;
+      conv = 1;
       break;
     }
   }
-  if (!ok) anom |= LBM_ANOM_NEWTON;
+  if (!conv) anom |= LBM_ANOM_NEWTON;
   if (!isfinite(T) || !isfinite(rho)) anom |= LBM_ANOM_NONFINITE;
-  const double lnT = log(T), invT = 1.0 / T;
-  double zeta = 0.0, H = 0.0, Cv = 0.0;
-  for (int a = 0; a < M; ++a) {
-    const double Y = r[RC::sp(a, RC::S_Y)];
+  const double lnT = log(T);
+  double pz = 0.0, pH = 0.0, pC = 0.0;
+  if (sp) {
     const double za = tb.Ra[a] * T, h = a_hRT(tb.nasa[a], T), cp = a_cpR(tb.nasa[a], T);
-    r[RC::sp(a, RC::S_ZA)] = za;
-    r[RC::sp(a, RC::S_HRT)] = h;
-    r[RC::sp(a, RC::S_CPR)] = cp;
-    r[RC::sp(a, RC::S_HA)] = za * h;
-    r[RC::sp(a, RC::S_UA)] = za * (h - 1.0);
-    zeta += Y * za;
-    H += Y * za * h;
-    Cv += Y * tb.Ra[a] * (cp - 1.0);
+    if (ok) {
+      r[RC::sp(a, RC::S_ZA)] = za;
+      r[RC::sp(a, RC::S_HRT)] = h;
+      r[RC::sp(a, RC::S_CPR)] = cp;
+      r[RC::sp(a, RC::S_HA)] = za * h;
+      r[RC::sp(a, RC::S_UA)] = za * (h - 1.0);
+      // concentrations and Gibbs functions for the production rates (Sec. 4)
+      if (rates_and_sm) {
+        r[RC::sp(a, RC::S_C)] = r[RC::sp(a, RC::S_RS)] * tb.conc_scale[a];
+        r[RC::sp(a, RC::S_GIB)] = h - a_sR(tb.nasa[a], T, lnT);
+      }
+    }
+    pz = Y * za;
+    pH = Y * za * h;
+    pC = Y * tb.Ra[a] * (cp - 1.0);
   }
-  r[RC::T] = T;
-  r[RC::LNT] = lnT;
-  r[RC::ZETA] = zeta;
-  r[RC::PP] = rho * zeta;
-  r[RC::H] = H;
-  r[RC::CV] = Cv;
-  r[RC::ANOM] = double(anom);
-  if (!rates_and_sm) return;
+  const double zeta = gsum(pz), H = gsum(pH), Cv = gsum(pC);
+  if (ok && lane == 0) {
+    r[RC::T] = T;
+    r[RC::LNT] = lnT;
+    r[RC::ZETA] = zeta;
+    r[RC::PP] = rho * zeta;
+    r[RC::H] = H;
+    r[RC::CV] = Cv;
+    r[RC::ANOM] = double(anom);
+  }
+}
 
-  // production rates by mass action (Sec. 4)
-  for (int a = 0; a < M; ++a) {
-    r[RC::sp(a, RC::S_C)] = r[RC::sp(a, RC::S_RS)] * tb.conc_scale[a];
-    r[RC::sp(a, RC::S_GIB)] = r[RC::sp(a, RC::S_HRT)] - a_sR(tb.nasa[a], T, lnT);
-    r[RC::sp(a, RC::S_RDOT)] = 0.0;
-  }
+// one reaction's forward and reverse rates (mass action, Sec. 4) into the record
+template <int M>
+__device__ __forceinline__ void fwd_rate(lds_tables &tb, lds_double *r, int k) {
+  using RC = Rec<M>;
+  const double lnT = r[RC::LNT], invT = 1.0 / r[RC::T];
   // species index M of a padded reaction side stands for a factor 1
   auto conc = [&](int idx) -> double { return idx < M ? r[RC::sp(idx, RC::S_C)] : 1.0; };
-  const double ln_c0 = tb.ln_c0_const - lnT;
-  for (int k = 0; k < tb.R; ++k) {
-    const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
-    double fwd = exp(lnkf);
-    for (int q = 0; q < tb.nreac[k]; ++q) fwd *= conc(tb.reac_idx[k][q]);
-    double rev = 0.0;
-    if (tb.rev[k]) {
-      double dG = 0.0;
-      for (int a = 0; a < M; ++a) dG += tb.dnu_a[k][a] * r[RC::sp(a, RC::S_GIB)];
-      rev = exp(lnkf + dG - tb.dnu[k] * ln_c0);
-      for (int q = 0; q < tb.nprod[k]; ++q) rev *= conc(tb.prod_idx[k][q]);
-    }
-    r[RC::RX + 2 * k] = fwd;
-    r[RC::RX + 2 * k + 1] = rev;
-    for (int a = 0; a < M; ++a) r[RC::sp(a, RC::S_RDOT)] += tb.dnu_a[k][a] * (fwd - rev);
+  const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
+  double fwd = exp(lnkf);
+  for (int q = 0; q < tb.nreac[k]; ++q) fwd *= conc(tb.reac_idx[k][q]);
+  double rev = 0.0;
+  if (tb.rev[k]) {
+    double dG = 0.0;
+    for (int a = 0; a < M; ++a) dG += tb.dnu_a[k][a] * r[RC::sp(a, RC::S_GIB)];
+    rev = exp(lnkf + dG - tb.dnu[k] * (tb.ln_c0_const - lnT));
+    for (int q = 0; q < tb.nprod[k]; ++q) rev *= conc(tb.prod_idx[k][q]);
   }
-  for (int a = 0; a < M; ++a) r[RC::sp(a, RC::S_RDOT)] *= tb.rdot_scale[a];
+  r[RC::RX + 2 * k] = fwd;
+  r[RC::RX + 2 * k + 1] = rev;
+}
 
-  // Stefan-Maxwell (eqs. tauab, transform1): K_ab = zeta_a zeta_b / (zeta D_ab),
-  // t_a = sum_b Y_b K_ab, beta_a = t_a / (2 + t_a); A_aa = 1 + t_a / 2, A_ab = -K_ab Y_b / 2
-  const double inv_zeta = 1.0 / zeta;
-  for (int a = 0; a < M; ++a) r[RC::sp(a, RC::S_T)] = 0.0;
-  for (int a = 0; a < M; ++a) {
-    r[RC::K + a * M + a] = 0.0;
-    for (int b = a + 1; b < M; ++b) {
-      const double K = r[RC::sp(a, RC::S_ZA)] * r[RC::sp(b, RC::S_ZA)] * invD(tb, M, a, b) * inv_zeta;
+// one species' production rate from the reactions' rates in the record
+template <int M>
+__device__ __forceinline__ void fwd_rdot(lds_tables &tb, lds_double *r, int a) {
+  using RC = Rec<M>;
+  double s = 0.0;
+  for (int k = 0; k < tb.R; ++k) s += tb.dnu_a[k][a] * (r[RC::RX + 2 * k] - r[RC::RX + 2 * k + 1]);
+  r[RC::sp(a, RC::S_RDOT)] = s * tb.rdot_scale[a];
+}
+
+// Stefan-Maxwell relaxation (eqs. tauab, transform1) and the collision coefficients of
+// the species, by all lanes of the group (workgroup barriers between the stages):
+// K_ab = zeta_a zeta_b / (zeta D_ab), t_a = sum_b Y_b K_ab, beta_a = t_a / (2 + t_a),
+// A_aa = 1 + t_a / 2, A_ab = -K_ab Y_b / 2 (row a on lane a); the elimination one pivot
+// at a time (row q on lane q); the three right-hand sides on lanes 0..2.
+template <int M>
+__device__ __noinline__ void fwd_sm(lds_tables &tb, lds_double *r, int lane, bool ok) {
+  using RC = Rec<M>;
+  const int a = lane;
+  if (ok && a < M) {
+    const double inv_zeta = 1.0 / r[RC::ZETA], za = r[RC::sp(a, RC::S_ZA)];
+    double t = 0.0;
+    for (int b = 0; b < M; ++b) {
+      const double K = b == a ? 0.0 : za * r[RC::sp(b, RC::S_ZA)] * invD(tb, M, a, b) * inv_zeta;
       r[RC::K + a * M + b] = K;
-      r[RC::K + b * M + a] = K;
-      r[RC::sp(a, RC::S_T)] += r[RC::sp(b, RC::S_Y)] * K;
-      r[RC::sp(b, RC::S_T)] += r[RC::sp(a, RC::S_Y)] * K;
+      if (b != a) t += r[RC::sp(b, RC::S_Y)] * K;
     }
-  }
-  for (int a = 0; a < M; ++a) {
-    const double t = r[RC::sp(a, RC::S_T)];
+    r[RC::sp(a, RC::S_T)] = t;
     r[RC::sp(a, RC::S_BETA)] = t / (2.0 + t);
     for (int b = 0; b < M; ++b)
       r[RC::LU + a * M + b] = (a == b) ? 1.0 + 0.5 * t : -0.5 * r[RC::K + a * M + b] * r[RC::sp(b, RC::S_Y)];
   }
+  __syncthreads();
   // Gaussian elimination without pivoting (strictly row-diagonally dominant): the
   // multipliers below the diagonal, U on and above it
-  for (int k = 0; k < M; ++k)
-    for (int q = k + 1; q < M; ++q) {
-      const double l = r[RC::LU + q * M + k] / r[RC::LU + k * M + k];
-      r[RC::LU + q * M + k] = l;
-      for (int cc = k + 1; cc < M; ++cc) r[RC::LU + q * M + cc] -= l * r[RC::LU + k * M + cc];
+  for (int k = 0; k < M; ++k) {
+    if (ok && a > k && a < M) {
+      const double l = r[RC::LU + a * M + k] / r[RC::LU + k * M + k];
+      r[RC::LU + a * M + k] = l;
+      for (int cc = k + 1; cc < M; ++cc) r[RC::LU + a * M + cc] -= l * r[RC::LU + k * M + cc];
     }
+    __syncthreads();
+  }
   // du: L z = r_a - u (z in the du slots), then U du = z in place
-  for (int d = 0; d < 3; ++d) {
-    for (int a = 0; a < M; ++a) {
-      double v = r[RC::sp(a, RC::S_RA + d)];
-      for (int b = 0; b < a; ++b) v -= r[RC::LU + a * M + b] * r[RC::sp(b, RC::S_DU + d)];
-      r[RC::sp(a, RC::S_DU + d)] = v;
+  if (ok && lane < 3) {
+    const int d = lane;
+    for (int q = 0; q < M; ++q) {
+      double v = r[RC::sp(q, RC::S_RA + d)];
+      for (int b = 0; b < q; ++b) v -= r[RC::LU + q * M + b] * r[RC::sp(b, RC::S_DU + d)];
+      r[RC::sp(q, RC::S_DU + d)] = v;
     }
-    for (int a = M - 1; a >= 0; --a) {
-      double v = r[RC::sp(a, RC::S_DU + d)];
-      for (int b = a + 1; b < M; ++b) v -= r[RC::LU + a * M + b] * r[RC::sp(b, RC::S_DU + d)];
-      r[RC::sp(a, RC::S_DU + d)] = v / r[RC::LU + a * M + a];
+    for (int q = M - 1; q >= 0; --q) {
+      double v = r[RC::sp(q, RC::S_DU + d)];
+      for (int b = q + 1; b < M; ++b) v -= r[RC::LU + q * M + b] * r[RC::sp(b, RC::S_DU + d)];
+      r[RC::sp(q, RC::S_DU + d)] = v / r[RC::LU + q * M + q];
     }
   }
   // collision coefficients of the stored species: c_a = 2 beta_a rho_a + rho_dot_a (the
   // equilibrium and source share Phi(u, zeta_a)), s_a = (beta_a - 1) Y_a (eq. fStar)
-  for (int a = 0; a < M - 1; ++a) {
+  if (ok && a < M - 1) {
     const double beta = r[RC::sp(a, RC::S_BETA)];
     r[RC::sp(a, RC::S_CA)] = 2.0 * beta * r[RC::sp(a, RC::S_RS)] + r[RC::sp(a, RC::S_RDOT)];
     r[RC::sp(a, RC::S_SA)] = (beta - 1.0) * r[RC::sp(a, RC::S_Y)];
   }
 }
 
-// ---- the node-level adjoint chain (first lane of the group) -------------------------------
+// ---- the node-level adjoint chain ------------------------------------------------------------
 // Inputs in the record: the reduced adjoints of the per-direction terms, plus direct
 // adjoints of node quantities given by the caller (lT, lY, lP, lrho, lu, lphi).
 // Output: the adjoints of the moments in the record; the Arrhenius gradient in pg[3R].
+// Called by every lane of the node's group (ok: the group holds a node).  rev_a: the
+// node's scalar adjoints (the Grad forms of g and of its ghosts) on the first lane,
+// then the per-species terms with lane a on species a (the collision's coefficients,
+// the enthalpy flux, the Stefan-Maxwell solve); the production rates one reaction per
+// lane (rev_rate); rev_b on the first lane (thermo, temperature, the moments).  The
+// scalar adjoints are carried in the record; the lanes' parts of them are group sums.
+
+// the scalar part of rev_a (first lane)
 template <int M>
-__device__ __noinline__ void node_reverse(const Tables &tb, double omega, double omega1, volatile double *r, bool collision,
-                             double lT, const double *lY_in, double lP, double lrho_in, const double *lu_in,
-                             const double *lphi, volatile double *pg) {
+__device__ __noinline__ void rev_scalars(lds_tables &tb, double omega, double omega1, lds_double *r, bool collision,
+                                         double lT, double lP, double lrho_in, const double *lu_in) {
   using RC = Rec<M>;
-  const double rho = r[RC::RHO], inv_rho = 1.0 / rho, T = r[RC::T], lnT = r[RC::LNT], invT = 1.0 / T;
-  const double zeta = r[RC::ZETA], P = r[RC::PP], Cv = r[RC::CV];
+  const double rho = r[RC::RHO], P = r[RC::PP];
   double u[3];
   for (int d = 0; d < 3; ++d) u[d] = r[RC::U + d];
-  // adjoints of the node's scalars; per-species adjoints in the record's working arrays
   double lrho = lrho_in, lu[3], lzeta = 0.0, lH = 0.0, lPt = lP, lrhoE = 0.0, lq[3] = {0.0, 0.0, 0.0};
-  double lPm[3][3], lU = 0.0;
+  double lPm[3][3], lU = 0.0, lA1[3] = {0.0, 0.0, 0.0};
   for (int d = 0; d < 3; ++d) {
     lu[d] = lu_in ? lu_in[d] : 0.0;
     for (int e = 0; e < 3; ++e) lPm[d][e] = 0.0;
   }
-  for (int a = 0; a < M; ++a) {
-    r[RC::wk(a, RC::W_LY)] = lY_in ? lY_in[a] : 0.0;
-    r[RC::wk(a, RC::W_LZA)] = r[RC::asp(a, RC::A_ZETAB)];
-    r[RC::wk(a, RC::W_LHA)] = 0.0;
-    r[RC::wk(a, RC::W_LRS)] = r[RC::asp(a, RC::A_RHOB)];
-    r[RC::wk(a, RC::W_LC)] = 0.0;
-    r[RC::wk(a, RC::W_LT)] = 0.0;
-    r[RC::wk(a, RC::W_LRDOT)] = 0.0;
-    for (int d = 0; d < 3; ++d) r[RC::wk(a, RC::W_LJA + d)] = 0.0;
-  }
   auto Y = [&](int a) -> double { return r[RC::sp(a, RC::S_Y)]; };
-  auto rs = [&](int a) -> double { return r[RC::sp(a, RC::S_RS)]; };
 
   // The Grad forms: R = h2 P^eq + P v v, P^eq = P I + rho v v, q^eq = h2 rho v, h2 = H + v^2/2
   // at the velocity v (u, or 0 for a zero-velocity ghost, which has no u part).  Adds the
@@ -403,7 +465,6 @@ __device__ __noinline__ void node_reverse(const Tables &tb, double omega, double
         if (d == e) lrhoE -= 1.5 * om * lB;
       }
     const double kap = 3.0 * (om - om1);
-    double lA1[3];
     for (int d = 0; d < 3; ++d) {
       lA1[d] = r[RC::L_A1 + d];
       lqe[d] = 3.0 * om1 * lA1[d];
@@ -421,26 +482,7 @@ __device__ __noinline__ void node_reverse(const Tables &tb, double omega, double
         lu[cc] -= w * u[cc] * rho * u[d];
         lu[d] -= w * u[cc] * rho * u[cc];
       }
-    // hyd = 3 om1 rho sum_a H_a Y_a du_a
-    for (int a = 0; a < M; ++a) {
-      const double Ha = r[RC::sp(a, RC::S_HA)];
-      double s = 0.0;
-      for (int d = 0; d < 3; ++d) {
-        s += lA1[d] * r[RC::sp(a, RC::S_DU + d)];
-        r[RC::asp(a, RC::A_DU + d)] += 3.0 * om1 * rho * Ha * Y(a) * lA1[d];
-      }
-      lrho += 3.0 * om1 * Ha * Y(a) * s;
-      r[RC::wk(a, RC::W_LHA)] += 3.0 * om1 * rho * Y(a) * s;
-      r[RC::wk(a, RC::W_LY)] += 3.0 * om1 * rho * Ha * s;
-    }
     grad_eq_vjp(u, true, lqe, lR);
-    // Cg = sum_a w_a grad Y_a with w_a = (2 - om1)/2 P H_a
-    for (int a = 0; a < M; ++a) {
-      double cg = 0.0;
-      for (int d = 0; d < 3; ++d) cg += r[RC::L_CG + d] * r[RC::sp(a, RC::S_GY + d)];
-      lPt += 0.5 * (2.0 - om1) * r[RC::sp(a, RC::S_HA)] * cg;
-      r[RC::wk(a, RC::W_LHA)] += 0.5 * (2.0 - om1) * P * cg;
-    }
   }
   // ghost equilibria of g (Grad form at rhoE_g = rho (U + v^2/2), no relaxation factor)
   for (int z = 0; z < 2; ++z) {
@@ -467,9 +509,65 @@ __device__ __noinline__ void node_reverse(const Tables &tb, double omega, double
     grad_eq_vjp(v, z == 0, lqe, lR);
   }
 
-  if (collision) {
-    // species coefficients: c_a = 2 beta_a rho_a + rho_dot_a, s_a = (beta_a - 1) Y_a
-    for (int a = 0; a < M - 1; ++a) {
+  r[RC::SC + RC::C_LRHO] = lrho;
+  r[RC::SC + RC::C_LZETA] = lzeta;
+  r[RC::SC + RC::C_LH] = lH;
+  r[RC::SC + RC::C_LPT] = lPt;
+  r[RC::SC + RC::C_LRHOE] = lrhoE;
+  r[RC::SC + RC::C_LUMIX] = lU;
+  r[RC::SC + RC::C_LT] = lT;
+  for (int d = 0; d < 3; ++d) {
+    r[RC::SC + RC::C_LU + d] = lu[d];
+    r[RC::SC + RC::C_LQ + d] = lq[d];
+    r[RC::SC + RC::C_LA1 + d] = lA1[d];
+    for (int e = 0; e < 3; ++e) r[RC::SC + RC::C_LPM + 3 * d + e] = lPm[d][e];
+  }
+}
+
+template <int M>
+__device__ __noinline__ void rev_a(lds_tables &tb, double omega, double omega1, lds_double *r, bool collision,
+                                   double lT, const double *lY_in, int64_t lY_stride, double lP, double lrho_in,
+                                   const double *lu_in, int lane, bool ok) {
+  using RC = Rec<M>;
+  const int a = lane;
+  const bool sp = ok && a < M;
+  // per-species working arrays
+  if (sp) {
+    r[RC::wk(a, RC::W_LY)] = lY_in ? lY_in[a * lY_stride] : 0.0;
+    r[RC::wk(a, RC::W_LZA)] = r[RC::asp(a, RC::A_ZETAB)];
+    r[RC::wk(a, RC::W_LHA)] = 0.0;
+    r[RC::wk(a, RC::W_LRS)] = r[RC::asp(a, RC::A_RHOB)];
+    r[RC::wk(a, RC::W_LC)] = 0.0;
+    r[RC::wk(a, RC::W_LT)] = 0.0;
+    r[RC::wk(a, RC::W_LRDOT)] = 0.0;
+    for (int d = 0; d < 3; ++d) r[RC::wk(a, RC::W_LJA + d)] = 0.0;
+  }
+  if (ok && lane == 0) rev_scalars<M>(tb, omega, omega1, r, collision, lT, lP, lrho_in, lu_in);
+  __syncthreads();
+  if (!collision) return;   // uniform over the workgroup
+  const double rho = r[RC::RHO], P = r[RC::PP], zeta = r[RC::ZETA], om1 = omega1;
+  auto Y = [&](int q) -> double { return r[RC::sp(q, RC::S_Y)]; };
+  auto rs = [&](int q) -> double { return r[RC::sp(q, RC::S_RS)]; };
+  // enthalpy flux hyd = 3 om1 rho sum_a H_a Y_a du_a, the Cg weights
+  // w_a = (2 - om1)/2 P H_a, and the species coefficients c_a = 2 beta_a rho_a + rho_dot_a,
+  // s_a = (beta_a - 1) Y_a
+  double lrho_p = 0.0, lPt_p = 0.0;
+  if (sp) {
+    const double Ha = r[RC::sp(a, RC::S_HA)];
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double lA1 = r[RC::SC + RC::C_LA1 + d];
+      s += lA1 * r[RC::sp(a, RC::S_DU + d)];
+      r[RC::asp(a, RC::A_DU + d)] += 3.0 * om1 * rho * Ha * Y(a) * lA1;
+    }
+    lrho_p = 3.0 * om1 * Ha * Y(a) * s;
+    r[RC::wk(a, RC::W_LHA)] += 3.0 * om1 * rho * Y(a) * s;
+    r[RC::wk(a, RC::W_LY)] += 3.0 * om1 * rho * Ha * s;
+    double cg = 0.0;
+    for (int d = 0; d < 3; ++d) cg += r[RC::L_CG + d] * r[RC::sp(a, RC::S_GY + d)];
+    lPt_p = 0.5 * (2.0 - om1) * Ha * cg;
+    r[RC::wk(a, RC::W_LHA)] += 0.5 * (2.0 - om1) * P * cg;
+    if (a < M - 1) {
       const double beta = r[RC::sp(a, RC::S_BETA)];
       const double lc = r[RC::asp(a, RC::A_C)], ls = r[RC::asp(a, RC::A_S)];
       const double lbeta = r[RC::asp(a, RC::A_BETA)] + 2.0 * rs(a) * lc + Y(a) * ls;
@@ -479,105 +577,158 @@ __device__ __noinline__ void node_reverse(const Tables &tb, double omega, double
       const double ta = r[RC::sp(a, RC::S_T)];
       r[RC::wk(a, RC::W_LT)] += 2.0 * lbeta / ((2.0 + ta) * (2.0 + ta));
     }
-    // Stefan-Maxwell solve A du = r (three right-hand sides): A^T mu = lambda_du by the
-    // same factors (U^T then L^T), lambda_r = mu, lambda_A = -mu du^T
-    for (int d = 0; d < 3; ++d) {
-      for (int a = 0; a < M; ++a) {   // U^T w = lambda
-        double v = r[RC::asp(a, RC::A_DU + d)];
-        for (int b = 0; b < a; ++b) v -= r[RC::LU + b * M + a] * r[RC::wk(b, RC::W_MU + d)];
-        r[RC::wk(a, RC::W_MU + d)] = v / r[RC::LU + a * M + a];
-      }
-      for (int a = M - 1; a >= 0; --a) {   // L^T mu = w (unit diagonal)
-        double v = r[RC::wk(a, RC::W_MU + d)];
-        for (int b = a + 1; b < M; ++b) v -= r[RC::LU + b * M + a] * r[RC::wk(b, RC::W_MU + d)];
-        r[RC::wk(a, RC::W_MU + d)] = v;
-      }
-    }
-    for (int a = 0; a < M; ++a) {
-      // r_a = j_a / rho_a - u (0 when rho_a is negligible)
-      if (r[RC::sp(a, RC::S_TINY)] == 0.0) {
-        double mj = 0.0;
-        for (int d = 0; d < 3; ++d) {
-          const double mu = r[RC::wk(a, RC::W_MU + d)];
-          r[RC::wk(a, RC::W_LJA + d)] += mu / rs(a);
-          mj += mu * r[RC::sp(a, RC::S_JA + d)];
-          lu[d] -= mu;
-        }
-        r[RC::wk(a, RC::W_LRS)] -= mj / (rs(a) * rs(a));
-      }
-      for (int b = 0; b < M; ++b) {
-        double lA = 0.0;
-        for (int d = 0; d < 3; ++d) lA -= r[RC::wk(a, RC::W_MU + d)] * r[RC::sp(b, RC::S_DU + d)];
-        if (a == b) {
-          r[RC::wk(a, RC::W_LT)] += 0.5 * lA;
-        } else {
-          // A_ab = -K_ab Y_b / 2
-          r[RC::LK + a * M + b] += -0.5 * Y(b) * lA;
-          r[RC::wk(b, RC::W_LY)] += -0.5 * r[RC::K + a * M + b] * lA;
-        }
-      }
-    }
-    // t_a = sum_b Y_b K_ab
-    for (int a = 0; a < M; ++a)
-      for (int b = 0; b < M; ++b)
-        if (b != a) {
-          r[RC::wk(b, RC::W_LY)] += r[RC::wk(a, RC::W_LT)] * r[RC::K + a * M + b];
-          r[RC::LK + a * M + b] += r[RC::wk(a, RC::W_LT)] * Y(b);
-        }
-    // K_ab = zeta_a zeta_b / (zeta D_ab), symmetric
-    for (int a = 0; a < M; ++a)
-      for (int b = a + 1; b < M; ++b) {
-        const double lK = r[RC::LK + a * M + b] + r[RC::LK + b * M + a];
-        const double K = r[RC::K + a * M + b];
-        r[RC::wk(a, RC::W_LZA)] += lK * K / r[RC::sp(a, RC::S_ZA)];
-        r[RC::wk(b, RC::W_LZA)] += lK * K / r[RC::sp(b, RC::S_ZA)];
-        lzeta -= lK * K / zeta;
-      }
-    // production rates: rho_dot_a = m_a dt / rho_ref sum_k nu_ka q_k, q_k = fwd_k - rev_k,
-    // fwd = exp(ln k_f) prod c^nu', rev = exp(ln k_f - ln K_c) prod c^nu'',
-    // ln k_f = ln A + b ln T - Ta / T, d ln K_c / dT = (sum_a nu_ka h_a - nu_k) / T
-    auto conc = [&](int idx) -> double { return idx < M ? r[RC::sp(idx, RC::S_C)] : 1.0; };
-    for (int k = 0; k < tb.R; ++k) {
-      double lq_k = 0.0;
-      for (int a = 0; a < M - 1; ++a) lq_k += tb.rdot_scale[a] * tb.dnu_a[k][a] * r[RC::wk(a, RC::W_LRDOT)];
-      const double fwd = r[RC::RX + 2 * k], rev = r[RC::RX + 2 * k + 1], qk = fwd - rev;
-      const double g = lq_k * qk;   // adjoint of ln k_f
-      if (pg) {
-        pg[3 * k] = g;
-        pg[3 * k + 1] = g * lnT;
-        pg[3 * k + 2] = -g * invT;
-      }
-      lT += g * (tb.bexp[k] * invT + tb.Ta[k] * invT * invT);
-      const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
-      // d (prod c) / d c_a: the product with one factor removed, per factor
-      const double kf = exp(lnkf);
-      for (int q = 0; q < tb.nreac[k]; ++q) {
-        double p = kf;
-        for (int q2 = 0; q2 < tb.nreac[k]; ++q2)
-          if (q2 != q) p *= conc(tb.reac_idx[k][q2]);
-        const int a = tb.reac_idx[k][q];
-        if (a < M) r[RC::wk(a, RC::W_LC)] += lq_k * p;
-      }
-      if (tb.rev[k]) {
-        double dh = -tb.dnu[k], dG = 0.0;
-        for (int a = 0; a < M; ++a) {
-          dh += tb.dnu_a[k][a] * r[RC::sp(a, RC::S_HRT)];
-          dG += tb.dnu_a[k][a] * r[RC::sp(a, RC::S_GIB)];
-        }
-        lT += lq_k * rev * dh * invT;   // d q / d ln K_c = rev
-        const double kr = exp(lnkf + dG - tb.dnu[k] * (tb.ln_c0_const - lnT));
-        for (int q = 0; q < tb.nprod[k]; ++q) {
-          double p = kr;
-          for (int q2 = 0; q2 < tb.nprod[k]; ++q2)
-            if (q2 != q) p *= conc(tb.prod_idx[k][q2]);
-          const int a = tb.prod_idx[k][q];
-          if (a < M) r[RC::wk(a, RC::W_LC)] -= lq_k * p;
-        }
-      }
-    }
-    for (int a = 0; a < M; ++a) r[RC::wk(a, RC::W_LRS)] += r[RC::wk(a, RC::W_LC)] * tb.conc_scale[a];
   }
+  lrho_p = gsum(lrho_p);
+  lPt_p = gsum(lPt_p);
+  if (ok && lane == 0) {
+    r[RC::SC + RC::C_LRHO] += lrho_p;
+    r[RC::SC + RC::C_LPT] += lPt_p;
+  }
+  __syncthreads();
+  // Stefan-Maxwell solve A du = r (three right-hand sides): A^T mu = lambda_du by the
+  // same factors (U^T then L^T), one right-hand side per lane
+  if (ok && lane < 3) {
+    const int d = lane;
+    for (int q = 0; q < M; ++q) {   // U^T w = lambda
+      double v = r[RC::asp(q, RC::A_DU + d)];
+      for (int b = 0; b < q; ++b) v -= r[RC::LU + b * M + q] * r[RC::wk(b, RC::W_MU + d)];
+      r[RC::wk(q, RC::W_MU + d)] = v / r[RC::LU + q * M + q];
+    }
+    for (int q = M - 1; q >= 0; --q) {   // L^T mu = w (unit diagonal)
+      double v = r[RC::wk(q, RC::W_MU + d)];
+      for (int b = q + 1; b < M; ++b) v -= r[RC::LU + b * M + q] * r[RC::wk(b, RC::W_MU + d)];
+      r[RC::wk(q, RC::W_MU + d)] = v;
+    }
+  }
+  __syncthreads();
+  // lambda_r = mu with r_a = j_a / rho_a - u (0 when rho_a is negligible), on lane a;
+  // lambda_A = -mu du^T, column b of A on lane b
+  double lu_p[3] = {0.0, 0.0, 0.0};
+  if (sp) {
+    if (r[RC::sp(a, RC::S_TINY)] == 0.0) {
+      double mj = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double mu = r[RC::wk(a, RC::W_MU + d)];
+        r[RC::wk(a, RC::W_LJA + d)] += mu / rs(a);
+        mj += mu * r[RC::sp(a, RC::S_JA + d)];
+        lu_p[d] = -mu;
+      }
+      r[RC::wk(a, RC::W_LRS)] -= mj / (rs(a) * rs(a));
+    }
+    const int b = a;
+    for (int q = 0; q < M; ++q) {
+      double lA = 0.0;
+      for (int d = 0; d < 3; ++d) lA -= r[RC::wk(q, RC::W_MU + d)] * r[RC::sp(b, RC::S_DU + d)];
+      if (q == b) {
+        r[RC::wk(b, RC::W_LT)] += 0.5 * lA;
+      } else {
+        // A_qb = -K_qb Y_b / 2
+        r[RC::LK + q * M + b] += -0.5 * Y(b) * lA;
+        r[RC::wk(b, RC::W_LY)] += -0.5 * r[RC::K + q * M + b] * lA;
+      }
+    }
+  }
+  for (int d = 0; d < 3; ++d) lu_p[d] = gsum(lu_p[d]);
+  if (ok && lane == 0)
+    for (int d = 0; d < 3; ++d) r[RC::SC + RC::C_LU + d] += lu_p[d];
+  __syncthreads();
+  // t_q = sum_b Y_b K_qb: column b on lane b
+  if (sp) {
+    const int b = a;
+    for (int q = 0; q < M; ++q)
+      if (q != b) {
+        r[RC::wk(b, RC::W_LY)] += r[RC::wk(q, RC::W_LT)] * r[RC::K + q * M + b];
+        r[RC::LK + q * M + b] += r[RC::wk(q, RC::W_LT)] * Y(b);
+      }
+  }
+  __syncthreads();
+  // K_ab = zeta_a zeta_b / (zeta D_ab), symmetric: row a on lane a; each pair's zeta term
+  // on the lane of its first species
+  double lz_p = 0.0;
+  if (sp) {
+    const double za = r[RC::sp(a, RC::S_ZA)];
+    for (int b = 0; b < M; ++b) {
+      if (b == a) continue;
+      const double lK = r[RC::LK + a * M + b] + r[RC::LK + b * M + a];
+      const double K = r[RC::K + a * M + b];
+      r[RC::wk(a, RC::W_LZA)] += lK * K / za;
+      if (b > a) lz_p += lK * K / zeta;
+    }
+  }
+  lz_p = gsum(lz_p);
+  if (ok && lane == 0) r[RC::SC + RC::C_LZETA] -= lz_p;
+}
 
+// The adjoint of reaction k's rates (Sec. 4): its Arrhenius gradient into pg[3k..3k+2],
+// the adjoints of the concentrations it touches added into lc[M]; returns its part of the
+// temperature adjoint.
+template <int M>
+__device__ __forceinline__ double rev_rate(lds_tables &tb, lds_double *r, int k, lds_double *lc, lds_double *pg) {
+  using RC = Rec<M>;
+  const double T = r[RC::T], lnT = r[RC::LNT], invT = 1.0 / T;
+  double lT = 0.0;
+  // production rates: rho_dot_a = m_a dt / rho_ref sum_k nu_ka q_k, q_k = fwd_k - rev_k,
+  // fwd = exp(ln k_f) prod c^nu', rev = exp(ln k_f - ln K_c) prod c^nu'',
+  // ln k_f = ln A + b ln T - Ta / T, d ln K_c / dT = (sum_a nu_ka h_a - nu_k) / T
+  auto conc = [&](int idx) -> double { return idx < M ? r[RC::sp(idx, RC::S_C)] : 1.0; };
+  double lq_k = 0.0;
+  for (int a = 0; a < M - 1; ++a) lq_k += tb.rdot_scale[a] * tb.dnu_a[k][a] * r[RC::wk(a, RC::W_LRDOT)];
+  const double fwd = r[RC::RX + 2 * k], rev = r[RC::RX + 2 * k + 1], qk = fwd - rev;
+  const double g = lq_k * qk;   // adjoint of ln k_f
+  if (pg) {
+    pg[3 * k] = g;
+    pg[3 * k + 1] = g * lnT;
+    pg[3 * k + 2] = -g * invT;
+  }
+  lT += g * (tb.bexp[k] * invT + tb.Ta[k] * invT * invT);
+  const double lnkf = tb.lnA[k] + tb.bexp[k] * lnT - tb.Ta[k] * invT;
+  // d (prod c) / d c_a: the product with one factor removed, per factor
+  const double kf = exp(lnkf);
+  for (int q = 0; q < tb.nreac[k]; ++q) {
+    double p = kf;
+    for (int q2 = 0; q2 < tb.nreac[k]; ++q2)
+      if (q2 != q) p *= conc(tb.reac_idx[k][q2]);
+    const int a = tb.reac_idx[k][q];
+    if (a < M) lc[a] += lq_k * p;
+  }
+  if (tb.rev[k]) {
+    double dh = -tb.dnu[k], dG = 0.0;
+    for (int a = 0; a < M; ++a) {
+      dh += tb.dnu_a[k][a] * r[RC::sp(a, RC::S_HRT)];
+      dG += tb.dnu_a[k][a] * r[RC::sp(a, RC::S_GIB)];
+    }
+    lT += lq_k * rev * dh * invT;   // d q / d ln K_c = rev
+    const double kr = exp(lnkf + dG - tb.dnu[k] * (tb.ln_c0_const - lnT));
+    for (int q = 0; q < tb.nprod[k]; ++q) {
+      double p = kr;
+      for (int q2 = 0; q2 < tb.nprod[k]; ++q2)
+        if (q2 != q) p *= conc(tb.prod_idx[k][q2]);
+      const int a = tb.prod_idx[k][q];
+      if (a < M) lc[a] -= lq_k * p;
+    }
+  }
+  return lT;
+}
+
+template <int M>
+__device__ __noinline__ void rev_b(lds_tables &tb, lds_double *r, bool collision, const double *lphi) {
+  using RC = Rec<M>;
+  const double rho = r[RC::RHO], inv_rho = 1.0 / rho, T = r[RC::T], invT = 1.0 / T;
+  const double zeta = r[RC::ZETA], Cv = r[RC::CV];
+  double u[3];
+  for (int d = 0; d < 3; ++d) u[d] = r[RC::U + d];
+  double lrho = r[RC::SC + RC::C_LRHO], lzeta = r[RC::SC + RC::C_LZETA], lH = r[RC::SC + RC::C_LH];
+  double lPt = r[RC::SC + RC::C_LPT], lrhoE = r[RC::SC + RC::C_LRHOE], lU = r[RC::SC + RC::C_LUMIX];
+  double lT = r[RC::SC + RC::C_LT];
+  double lu[3], lq[3], lPm[3][3];
+  for (int d = 0; d < 3; ++d) {
+    lu[d] = r[RC::SC + RC::C_LU + d];
+    lq[d] = r[RC::SC + RC::C_LQ + d];
+    for (int e = 0; e < 3; ++e) lPm[d][e] = r[RC::SC + RC::C_LPM + 3 * d + e];
+  }
+  auto Y = [&](int a) -> double { return r[RC::sp(a, RC::S_Y)]; };
+  if (collision)
+    for (int a = 0; a < M; ++a) r[RC::wk(a, RC::W_LRS)] += r[RC::wk(a, RC::W_LC)] * tb.conc_scale[a];
   // non-local arguments: phi_d = rho u_d (1 - 3 zeta) - rho u_d^3 (eq. Xalpha)
   if (lphi)
     for (int d = 0; d < 3; ++d) {
@@ -635,9 +786,10 @@ __device__ __noinline__ void node_reverse(const Tables &tb, double omega, double
   }
 }
 
+
 // adjoint of the pulled population of direction i from the adjoints of the moments
 template <int M>
-__device__ __forceinline__ void moment_adjoint(int i, const volatile double *r, double *out) {
+__device__ __forceinline__ void moment_adjoint(int i, const double *r, double *out) {
   using RC = Rec<M>;
   const double c[3] = {double(acx(i)), double(acy(i)), double(acz(i))};
   double f = r[RC::M_RHO], g = r[RC::M_RHOE];
@@ -740,30 +892,28 @@ __device__ __forceinline__ bool ghost_adjoint(const ALat &L, int x, int y, int z
   return hit;
 }
 
-// the (node, c) pairs per axis whose gradient neighbour is z: wrap(y + c) on a periodic
-// axis, clamp(y + c) on an open one
+// The three (node, c) pairs per axis whose gradient neighbour is z: wrap(y + c) on a
+// periodic axis, clamp(y + c) on an open one.  Inside an open axis they are (z, 0),
+// (z - 1, +1) and (z + 1, -1); the first node has (0, -1) in place of (z - 1, +1), the
+// last (L - 1, +1) in place of (z + 1, -1) (both, on an axis of one node).
 struct APairs {
-  int y[9], c[9], n;
+  int y[3], c[3];
 };
 __device__ __forceinline__ APairs axis_pairs(int zc, int Lax, bool periodic) {
   APairs p;
-  p.n = 0;
+  p.y[0] = zc;
+  p.c[0] = 0;
   if (periodic) {
-    for (int c = -1; c <= 1; ++c) {
-      p.y[p.n] = wrapc(zc - c, Lax);
-      p.c[p.n++] = c;
-    }
+    p.y[1] = wrapc(zc - 1, Lax);
+    p.c[1] = 1;
+    p.y[2] = wrapc(zc + 1, Lax);
+    p.c[2] = -1;
   } else {
-    for (int y = zc - 1; y <= zc + 1; ++y) {
-      if (y < 0 || y >= Lax) continue;
-      for (int c = -1; c <= 1; ++c) {
-        const int v = y + c < 0 ? 0 : (y + c >= Lax ? Lax - 1 : y + c);
-        if (v == zc) {
-          p.y[p.n] = y;
-          p.c[p.n++] = c;
-        }
-      }
-    }
+    const bool lo = zc >= 1, hi = zc <= Lax - 2;
+    p.y[1] = lo ? zc - 1 : 0;
+    p.c[1] = lo ? 1 : -1;
+    p.y[2] = hi ? zc + 1 : zc;
+    p.c[2] = hi ? -1 : 1;
   }
   return p;
 }
@@ -780,114 +930,115 @@ struct AdjBuf {
   double *part;        // [3R][nblocks] Arrhenius gradient partials
 };
 
-// forward side fields: Y_a and the weights w_a = (2 - omega1)/2 P H_a of Cg
+// forward side fields: Y_a and the weights w_a = (2 - omega1)/2 P H_a of Cg.  A node's
+// directions on the lanes of a 32-lane group (moments by group sums), its species on
+// lanes 0..M-1.
 template <int M>
-__global__ __launch_bounds__(128) void k_adj_fwd(ALat L, const Tables *tbp, AdjBuf ab, double omega1) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= L.N) return;
+__global__ __launch_bounds__(ADJ_BLOCK) void k_adj_fwd(ALat L, const Tables *tbp, AdjBuf ab, double omega1) {
+  constexpr int S = M + 1;
   const Tables &tb = *tbp;
+  const int slot = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int64_t n = (int64_t)blockIdx.x * NPB + slot;
+  const bool node_ok = n < L.N;
+  const int64_t nn = node_ok ? n : 0;
+  const bool valid = node_ok && lane < Q;
+  const int i = lane < Q ? lane : 13;
   const int64_t N = L.N;
+  double f[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) f[s] = valid ? ab.P[((int64_t)s * Q + i) * N + nn] : 0.0;
   Mom<M> m;
-  m.rho = m.rhoE = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    m.j[d] = m.q[d] = 0.0;
-    for (int e = 0; e < 3; ++e) m.P[d][e] = 0.0;
-  }
-  for (int a = 0; a < M - 1; ++a) {
-    m.ra[a] = 0.0;
-    for (int d = 0; d < 3; ++d) m.ja[a][d] = 0.0;
-  }
-  for (int i = 0; i < Q; ++i) {
-    const double f = ab.P[((int64_t)(M - 1) * Q + i) * N + n];
-    const double c[3] = {double(acx(i)), double(acy(i)), double(acz(i))};
-    m.rho += f;
-    for (int d = 0; d < 3; ++d) m.j[d] += c[d] * f;
-    m.rhoE += ab.P[((int64_t)M * Q + i) * N + n];
-    for (int a = 0; a < M - 1; ++a) m.ra[a] += ab.P[((int64_t)a * Q + i) * N + n];
-  }
-  double rsum = 0.0, Y[M];
-  for (int a = 0; a < M - 1; ++a) {
-    Y[a] = m.ra[a] / m.rho;
-    rsum += m.ra[a];
-  }
-  Y[M - 1] = (m.rho - rsum) / m.rho;
+  group_moments<M>(i, valid, f, m);
+  // species on lanes a < M; the Newton iteration on every lane alike, on the group sums
+  // of the internal-energy and heat-capacity polynomials
+  double rsum = 0.0;
+  for (int a = 0; a < M - 1; ++a) rsum += m.ra[a];
+  const int a = lane;
+  const bool sp = a < M;
+  const double Y = sp ? (a < M - 1 ? m.ra[a] : m.rho - rsum) / m.rho : 0.0;
   const double usq = (m.j[0] * m.j[0] + m.j[1] * m.j[1] + m.j[2] * m.j[2]) / (m.rho * m.rho);
   const double e = m.rhoE / m.rho - 0.5 * usq;
-  double T = ab.T0[n];
+  double ec[6], dc[5];
+  for (int k = 0; k < 6; ++k) ec[k] = gsum(sp ? Y * tb.ucoef[a][k] : 0.0);
+  for (int k = 0; k < 5; ++k) dc[k] = gsum(sp ? Y * tb.cvcoef[a][k] : 0.0);
+  double T = ab.T0[nn];
   for (int it = 0; it < 50; ++it) {
-    double ev = -e, dv = 0.0;
-    for (int a = 0; a < M; ++a) {
-      const double *uc = tb.ucoef[a], *cv = tb.cvcoef[a];
-      ev += Y[a] * (uc[0] + T * (uc[1] + T * (uc[2] + T * (uc[3] + T * (uc[4] + T * uc[5])))));
-      dv += Y[a] * (cv[0] + T * (cv[1] + T * (cv[2] + T * (cv[3] + T * cv[4]))));
-    }
+    const double ev = ec[0] + T * (ec[1] + T * (ec[2] + T * (ec[3] + T * (ec[4] + T * ec[5])))) - e;
+    const double dv = dc[0] + T * (dc[1] + T * (dc[2] + T * (dc[3] + T * dc[4])));
     const double dT = -ev / dv;
     T += dT;
     if (fabs(dT) <= 1e-12 * fabs(T)) break;
   }
-  double zeta = 0.0;
-  for (int a = 0; a < M; ++a) zeta += Y[a] * tb.Ra[a] * T;
+  const double zeta = gsum(sp ? Y * tb.Ra[a] * T : 0.0);
   const double Pp = m.rho * zeta;
-  for (int a = 0; a < M; ++a) {
-    ab.fY[a * N + n] = Y[a];
-    ab.fw[a * N + n] = 0.5 * (2.0 - omega1) * Pp * tb.Ra[a] * T * a_hRT(tb.nasa[a], T);
+  if (node_ok && sp) {
+    ab.fY[a * N + nn] = Y;
+    ab.fw[a * N + nn] = 0.5 * (2.0 - omega1) * Pp * tb.Ra[a] * T * a_hRT(tb.nasa[a], T);
   }
 }
 
 // adjoints of the stencil outputs at each node: X (from the axis directions of f) and
-// Cg (from g), the latter spread over the species as lambda_gY_a = w_a lambda_Cg
+// Cg (from g), the latter spread over the species as lambda_gY_a = w_a lambda_Cg.  A
+// node's directions on the lanes of a 32-lane group, summed over the group.
 template <int M>
-__global__ __launch_bounds__(128) void k_adj_x(ALat L, AdjBuf ab) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= L.N) return;
+__global__ __launch_bounds__(ADJ_BLOCK) void k_adj_x(ALat L, AdjBuf ab) {
+  const int slot = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int64_t n = (int64_t)blockIdx.x * NPB + slot;
+  const bool node_ok = n < L.N;
+  const int64_t nn = node_ok ? n : 0;
+  const bool valid = node_ok && lane < Q;
+  const int i = lane < Q ? lane : 13;
   const int64_t N = L.N;
-  const int x = (int)(n % L.nx), y = (int)((n / L.nx) % L.ny), z = (int)(n / ((int64_t)L.nx * L.ny));
-  double lX[3] = {0.0, 0.0, 0.0}, lC[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < Q; ++i) {
-    const int64_t pn = push_node(L, x, y, z, i);
-    if (pn < 0) continue;
-    const int c[3] = {acx(i), acy(i), acz(i)};
-    const double Lf = ab.Ln[((int64_t)(M - 1) * Q + i) * N + pn];
-    const double Lg = ab.Ln[((int64_t)M * Q + i) * N + pn];
-    const int c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-    for (int d = 0; d < 3; ++d) {
-      if (c2 == 1) lX[d] += 0.5 * c[d] * Lf;
-      lC[d] += 3.0 * awgt(i) * c[d] * Lg;
-    }
+  const int x = (int)(nn % L.nx), y = (int)((nn / L.nx) % L.ny), z = (int)(nn / ((int64_t)L.nx * L.ny));
+  const int64_t pn = valid ? push_node(L, x, y, z, i) : -1;
+  const double Lf = pn >= 0 ? ab.Ln[((int64_t)(M - 1) * Q + i) * N + pn] : 0.0;
+  const double Lg = pn >= 0 ? ab.Ln[((int64_t)M * Q + i) * N + pn] : 0.0;
+  const int c[3] = {acx(i), acy(i), acz(i)};
+  const bool axis = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] == 1;
+  double lX[3], lC[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lX[d] = gsum(axis ? 0.5 * c[d] * Lf : 0.0);
+    lC[d] = gsum(3.0 * awgt(i) * c[d] * Lg);
   }
-  for (int d = 0; d < 3; ++d) ab.lX[d * N + n] = lX[d];
-  for (int a = 0; a < M; ++a)
-    for (int d = 0; d < 3; ++d) ab.lgY[(a * 3 + d) * N + n] = ab.fw[a * N + n] * lC[d];
+  if (!node_ok) return;
+  if (lane < 3) {
+    const int d = lane;
+    ab.lX[d * N + nn] = d == 0 ? lX[0] : (d == 1 ? lX[1] : lX[2]);
+  }
+  if (lane < M) {
+    const int a = lane;
+    const double w = ab.fw[a * N + nn];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ab.lgY[(a * 3 + d) * N + nn] = w * lC[d];
+  }
 }
 
 // transposed isotropic gradient: out(z) = sum over (y, i) with nb(y, i) = z of
-// 3 w_i c_i,alpha in(y), per component (vec) or for a vector input per species
-__device__ __forceinline__ void transposed_grad(const ALat &L, int64_t n, const double *in, int ncomp,
-                                                int64_t comp_stride, bool diag_only, double *out) {
+// 3 w_i c_i,alpha in(y).  DIAG: a vector input, out_alpha from in_alpha (out[3]); else
+// one species' vector input, out = sum_alpha of the components (out[1]).  The 27 source
+// nodes are fixed, so their loads are independent of each other.
+template <bool DIAG>
+__device__ __forceinline__ void transposed_grad(const ALat &L, int64_t n, const double *in, int64_t comp_stride,
+                                                double *out) {
   const int x = (int)(n % L.nx), y = (int)((n / L.nx) % L.ny), z = (int)(n / ((int64_t)L.nx * L.ny));
   const APairs px = axis_pairs(x, L.nx, L.per[0]), py = axis_pairs(y, L.ny, L.per[1]),
                pz = axis_pairs(z, L.nz, L.per[2]);
-  for (int k = 0; k < ncomp; ++k) out[k] = 0.0;
-  for (int a = 0; a < px.n; ++a)
-    for (int b = 0; b < py.n; ++b)
-      for (int cc = 0; cc < pz.n; ++cc) {
+  double o[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
         const int cv[3] = {px.c[a], py.c[b], pz.c[cc]};
         const double w3 = 3.0 * aw1(cv[0]) * aw1(cv[1]) * aw1(cv[2]);
         const int64_t src = ((int64_t)pz.y[cc] * L.ny + py.y[b]) * L.nx + px.y[a];
-        if (diag_only) {
-          // ncomp = 3: out_alpha = sum 3 w c_alpha in_alpha
-          for (int d = 0; d < 3; ++d)
-            if (cv[d] != 0) out[d] += w3 * cv[d] * in[d * comp_stride + src];
-        } else {
-          // ncomp species: out_s = sum 3 w c . in_s (in_s has 3 components)
-          for (int s = 0; s < ncomp; ++s) {
-            double v = 0.0;
-            for (int d = 0; d < 3; ++d)
-              if (cv[d] != 0) v += cv[d] * in[(s * 3 + d) * comp_stride + src];
-            out[s] += w3 * v;
-          }
-        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) o[DIAG ? d : 0] += w3 * double(cv[d]) * in[d * comp_stride + src];
       }
+#pragma unroll
+  for (int d = 0; d < (DIAG ? 3 : 1); ++d) out[d] = o[d];
 }
 
 // lambda_psi = -G^T lambda_X (X_alpha = -grad_alpha psi_alpha)
@@ -895,20 +1046,26 @@ __global__ __launch_bounds__(128) void k_adj_psi(ALat L, AdjBuf ab) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= L.N) return;
   double o[3];
-  transposed_grad(L, n, ab.lX, 3, L.N, true, o);
+  transposed_grad<true>(L, n, ab.lX, L.N, o);
   for (int d = 0; d < 3; ++d) ab.lpsi[d * L.N + n] = -o[d];
 }
 
-// lambda_phi = (1/omega - 1/2) G^T lambda_psi; lambda_Y_a = G^T lambda_gY_a
+// lambda_phi = (1/omega - 1/2) G^T lambda_psi; lambda_Y_a = G^T lambda_gY_a.  One thread
+// per (node, output): output a < M is species a, output M the three components of phi.
 template <int M>
 __global__ __launch_bounds__(128) void k_adj_phi(ALat L, AdjBuf ab, double coef) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= L.N) return;
-  double o[M > 3 ? M : 3];
-  transposed_grad(L, n, ab.lpsi, 3, L.N, true, o);
-  for (int d = 0; d < 3; ++d) ab.lphi[d * L.N + n] = coef * o[d];
-  transposed_grad(L, n, ab.lgY, M, L.N, false, o);
-  for (int a = 0; a < M; ++a) ab.lYs[a * L.N + n] = o[a];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.N * (M + 1)) return;
+  const int comp = (int)(t / L.N);
+  const int64_t n = t - (int64_t)comp * L.N;
+  double o[3];
+  if (comp == M) {
+    transposed_grad<true>(L, n, ab.lpsi, L.N, o);
+    for (int d = 0; d < 3; ++d) ab.lphi[d * L.N + n] = coef * o[d];
+  } else {
+    transposed_grad<false>(L, n, ab.lgY + (int64_t)comp * 3 * L.N, L.N, o);
+    ab.lYs[comp * L.N + n] = o[0];
+  }
 }
 
 // The reverse of the collision, ghosts and streaming of one step at each node (see the
@@ -920,7 +1077,11 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_step(ALat L, const Tables *tb
   using RC = Rec<M>;
   __shared__ double recs[NPB][RC::WORDS];
   __shared__ double pgs[NPB][3 * MAXR];
+  __shared__ double lcs[NPB][GL][M];   // per lane: its reactions' concentration adjoints
+  __shared__ Tables tbs;
   const Tables &tb = *tbp;
+  tables_to_lds(tbp, &tbs);
+  lds_tables &tl = *(lds_tables *)&tbs;
   const int slot = threadIdx.x / GL, lane = threadIdx.x % GL;
   const int64_t n = (int64_t)blockIdx.x * NPB + slot;
   const bool node_ok = n < L.N;
@@ -928,11 +1089,14 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_step(ALat L, const Tables *tb
   const bool valid = node_ok && lane < Q;
   const int i = lane < Q ? lane : 13;
   const int64_t N = L.N;
-  volatile double *r = recs[slot];
+  double *r = recs[slot];
+  lds_double *rl = (lds_double *)recs[slot];
   const int x = (int)(nn % L.nx), y = (int)((nn / L.nx) % L.ny), z = (int)(nn / ((int64_t)L.nx * L.ny));
   // clear the reduced-adjoint part of the record
   for (int k = RC::L0 + lane; k < RC::MO; k += GL) r[k] = 0.0;
   for (int k = lane; k < 3 * MAXR; k += GL) pgs[slot][k] = 0.0;
+  for (int a = 0; a < M; ++a) lcs[slot][lane][a] = 0.0;
+  __syncthreads();
 
   // adjoints arriving at this node's post-collision populations (push)
   double Lp[S];
@@ -954,7 +1118,7 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_step(ALat L, const Tables *tb
     }
     Mom<M> m;
     group_moments<M>(i, valid, f, m);
-    if (lane == 0 && node_ok) node_forward<M>(tb, m, ab.T0[nn], r, true);
+    node_forward<M>(tl, m, ab.T0[nn], rl, lane, node_ok, true);
   }
   // grad Y_a at the node from the neighbours' mass fractions (forward O6 stencil)
   {
@@ -975,6 +1139,15 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_step(ALat L, const Tables *tb
       }
     }
   }
+  __syncthreads();
+  // production rates: one reaction per lane, then one species per lane; then the
+  // Stefan-Maxwell step on the first lane
+  if (node_ok)
+    for (int k = lane; k < tl.R; k += GL) fwd_rate<M>(tl, rl, k);
+  __syncthreads();
+  if (node_ok && lane < M) fwd_rdot<M>(tl, rl, lane);
+  __syncthreads();
+  fwd_sm<M>(tl, rl, lane, node_ok);
   __syncthreads();
 
   // adjoints arriving at the ghost equilibria of this node
@@ -1124,13 +1297,30 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_step(ALat L, const Tables *tb
     }
   }
   __syncthreads();
+  rev_a<M>(tl, omega, omega1, rl, true, 0.0, ab.lYs + nn, N, 0.0, 0.0, nullptr, lane, node_ok);
+  __syncthreads();
+  // the rates' adjoints, one reaction per lane; the concentration adjoints summed per
+  // species over the lanes' rows, the temperature adjoint over the group
+  {
+    double lTr = 0.0;
+    if (node_ok)
+      for (int k = lane; k < tl.R; k += GL)
+        lTr += rev_rate<M>(tl, rl, k, (lds_double *)lcs[slot][lane], (lds_double *)pgs[slot]);
+    lTr = gsum(lTr);
+    __syncthreads();
+    if (node_ok && lane < M) {
+      double sc = 0.0;
+      for (int q = 0; q < GL; ++q) sc += lcs[slot][q][lane];
+      r[RC::wk(lane, RC::W_LC)] = sc;
+    }
+    if (node_ok && lane == 0) r[RC::SC + RC::C_LT] += lTr;
+  }
+  __syncthreads();
   if (lane == 0 && node_ok) {
-    double lphi[3], lY[M];
+    double lphi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) lphi[d] = ab.lphi[d * N + nn];
-#pragma unroll
-    for (int a = 0; a < M; ++a) lY[a] = ab.lYs[a * N + nn];
-    node_reverse<M>(tb, omega, omega1, r, true, 0.0, lY, 0.0, 0.0, nullptr, lphi, (volatile double *)pgs[slot]);
+    rev_b<M>(tl, rl, true, lphi);
   }
   __syncthreads();
   if (valid) {
@@ -1152,13 +1342,21 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_step(ALat L, const Tables *tb
   }
 }
 
-// sum of the workgroup partials into the caller's gradient (+=), one thread per entry
-__global__ void k_adj_param_sum(const double *part, int64_t nparts, int n, double *grad) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+// sum of the workgroup partials into the caller's gradient (+=): one workgroup per
+// entry, strided partial sums per thread, then a tree over the workgroup (a fixed order)
+constexpr int PSUM_BLOCK = 256;
+__global__ __launch_bounds__(PSUM_BLOCK) void k_adj_param_sum(const double *part, int64_t nparts, double *grad) {
+  __shared__ double red[PSUM_BLOCK];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int64_t j = 0; j < nparts; ++j) s += part[(int64_t)k * nparts + j];
-  grad[k] += s;
+  for (int64_t j = threadIdx.x; j < nparts; j += PSUM_BLOCK) s += part[(int64_t)k * nparts + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = PSUM_BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[k] += red[0];
 }
 
 // Adjoint of the macroscopic fields (lbm_macros) of a state: lambda = sum over nodes of
@@ -1171,7 +1369,9 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_macros(ALat L, const Tables *
   constexpr int S = M + 1;
   using RC = Rec<M>;
   __shared__ double recs[NPB][RC::WORDS];
-  const Tables &tb = *tbp;
+  __shared__ Tables tbs;
+  tables_to_lds(tbp, &tbs);
+  lds_tables &tl = *(lds_tables *)&tbs;
   const int slot = threadIdx.x / GL, lane = threadIdx.x % GL;
   const int64_t n = (int64_t)blockIdx.x * NPB + slot;
   const bool node_ok = n < L.N;
@@ -1179,21 +1379,23 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_macros(ALat L, const Tables *
   const bool valid = node_ok && lane < Q;
   const int i = lane < Q ? lane : 13;
   const int64_t N = L.N;
-  volatile double *r = recs[slot];
+  double *r = recs[slot];
+  lds_double *rl = (lds_double *)recs[slot];
   for (int k = RC::L0 + lane; k < RC::MO; k += GL) r[k] = 0.0;
+  __syncthreads();
   double f[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) f[s] = valid ? P[((int64_t)s * Q + i) * N + nn] : 0.0;
   Mom<M> m;
   group_moments<M>(i, valid, f, m);
-  if (lane == 0 && node_ok) node_forward<M>(tb, m, T0[nn], r, false);
+  node_forward<M>(tl, m, T0[nn], rl, lane, node_ok, false);
   __syncthreads();
-  if (lane == 0 && node_ok) {
-    double lY[M], lu[3];
-    for (int a = 0; a < M; ++a) lY[a] = w_Y ? w_Y[a * N + nn] : 0.0;
+  {
+    double lu[3];
     for (int d = 0; d < 3; ++d) lu[d] = w_u ? w_u[d * N + nn] : 0.0;
-    node_reverse<M>(tb, 0.0, 0.0, r, false, w_T ? w_T[nn] : 0.0, lY, w_P ? w_P[nn] : 0.0,
-                    w_rho ? w_rho[nn] : 0.0, lu, nullptr, nullptr);
+    rev_a<M>(tl, 0.0, 0.0, rl, false, w_T ? w_T[nn] : 0.0, w_Y ? w_Y + nn : nullptr, N, w_P ? w_P[nn] : 0.0,
+             w_rho ? w_rho[nn] : 0.0, lu, lane, node_ok);
+    if (lane == 0 && node_ok) rev_b<M>(tl, rl, false, nullptr);
   }
   __syncthreads();
   if (valid) {
@@ -1339,15 +1541,15 @@ hipError_t adj_step_m(const Geom &g, const Tables *tb, const AdjBufHost &h, doub
                       double *adj, double *grad, hipStream_t st) {
   const ALat L = make_alat(g);
   AdjBuf ab{h.P, h.Ln, h.T0, h.fY, h.fw, h.lX, h.lgY, h.lpsi, h.lphi, h.lYs, h.part};
-  hipLaunchKernelGGL((k_adj_fwd<M>), dim3(ablocks(g.N, 128)), dim3(128), 0, st, L, tb, ab, omega1);
-  hipLaunchKernelGGL((k_adj_x<M>), dim3(ablocks(g.N, 128)), dim3(128), 0, st, L, ab);
-  hipLaunchKernelGGL(k_adj_psi, dim3(ablocks(g.N, 128)), dim3(128), 0, st, L, ab);
-  hipLaunchKernelGGL((k_adj_phi<M>), dim3(ablocks(g.N, 128)), dim3(128), 0, st, L, ab, 1.0 / omega - 0.5);
+  hipLaunchKernelGGL((k_adj_fwd<M>), dim3(ablocks(g.N, NPB)), dim3(ADJ_BLOCK), 0, st, L, tb, ab, omega1);
+  hipLaunchKernelGGL((k_adj_x<M>), dim3(ablocks(g.N, NPB)), dim3(ADJ_BLOCK), 0, st, L, ab);
+  hipLaunchKernelGGL(k_adj_psi, dim3(ablocks(g.N, 64)), dim3(64), 0, st, L, ab);
+  hipLaunchKernelGGL((k_adj_phi<M>), dim3(ablocks(g.N * (M + 1), 128)), dim3(128), 0, st, L, ab, 1.0 / omega - 0.5);
   const unsigned nb = ablocks(g.N, NPB);
   hipLaunchKernelGGL((k_adj_step<M>), dim3(nb), dim3(ADJ_BLOCK), 0, st, L, tb, ab, omega, omega1, adj);
   if (grad && R > 0)
-    hipLaunchKernelGGL(k_adj_param_sum, dim3(ablocks(3 * R, 64)), dim3(64), 0, st, (const double *)h.part,
-                       (int64_t)nb, 3 * R, grad);
+    hipLaunchKernelGGL(k_adj_param_sum, dim3(3 * R), dim3(PSUM_BLOCK), 0, st, (const double *)h.part, (int64_t)nb,
+                       grad);
   return hipGetLastError();
 }
 

@@ -1831,7 +1831,7 @@ __global__ __launch_bounds__(128) void k_macros(Geom g, Buffers b, CollideConsts
 
 // pre-collision populations at listed nodes
 template <int M, typename ST, typename RT>
-__global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, CollideConsts kc, int cur,
+__global__ __launch_bounds__(64) void k_export(Geom g, Buffers b, CollideConsts kc, int cur,
                                                 const int64_t *nodes, int64_t nn, double *out, double *T_out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nn) return;
@@ -1845,23 +1845,24 @@ __global__ __launch_bounds__(128) void k_export(Geom g, Buffers b, CollideConsts
   const AxisSrc ax = axis_src_x(g, x);
   const AxisSrc ay = axis_src(y, g.ny, g.per[1]);
   const AxisSrc az = axis_src(z, g.nz, g.per[2]);
-  for (int kyz = 0; kyz < 9; ++kyz) {
-    const int ky = kyz % 3, kz = kyz / 3;
-    const int cy = ky - 1, cz = kz - 1;
-    static_for<3>([&](auto Kx) {
-      constexpr int kx = decltype(Kx)::value;
-      constexpr int cx = kx - 1;
-      const int i = kx + 3 * kyz;
-      const Src r = make_src(g, ax, ay, az, kx, ky, kz);
-      out[((int64_t)(M - 1) * Q + i) * nn + k] =
-          pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
-      out[((int64_t)M * Q + i) * nn + k] =
-          pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
-      for (int a = 0; a < M - 1; ++a)
-        out[((int64_t)a * Q + i) * nn + k] = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
-    });
-  }
-  if (T_out) T_out[k] = b.T[n];
+  // one direction per grid row: 27 times the threads of a node loop
+  const int kyz = blockIdx.y / 3, kx_run = blockIdx.y % 3;
+  const int ky = kyz % 3, kz = kyz / 3;
+  const int cy = ky - 1, cz = kz - 1;
+  static_for<3>([&](auto Kx) {
+    constexpr int kx = decltype(Kx)::value;
+    constexpr int cx = kx - 1;
+    if (kx != kx_run) return;
+    const int i = kx + 3 * kyz;
+    const Src r = make_src(g, ax, ay, az, kx, ky, kz);
+    out[((int64_t)(M - 1) * Q + i) * nn + k] =
+        pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
+    out[((int64_t)M * Q + i) * nn + k] =
+        pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
+    for (int a = 0; a < M - 1; ++a)
+      out[((int64_t)a * Q + i) * nn + k] = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
+  });
+  if (T_out && blockIdx.y == 0) T_out[k] = b.T[n];
 }
 
 // ---- diagnostics (Sec. 5.2) -----------------------------------------------------------
@@ -2327,7 +2328,7 @@ struct RunExport {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, const int64_t *nodes,
                         int64_t nn, double *out, double *T_out, hipStream_t st) {
     if (nn == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_export<M, ST, RT>), dim3(blocks_for(nn, 128)), dim3(128), 0, st, g, b, kc, cur, nodes,
+    hipLaunchKernelGGL((k_export<M, ST, RT>), dim3(blocks_for(nn, 64), 27), dim3(64), 0, st, g, b, kc, cur, nodes,
                        nn, out, T_out);
     return hipGetLastError();
   }
