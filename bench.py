@@ -415,6 +415,7 @@ def main():
                                f"{args.storage} population storage; FP64 temperature, thermo, rates and "
                                "Stefan-Maxwell solve, FP32 inter-species term",
                    "lattice": [args.n] * 3, "species": M, "reactions": 19, "storage": args.storage,
+                   "state": "non-igniting: the 1500 K kernel of radius 12 cools over the timed steps",
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "kernel_ms_per_step": {k: round(v / args.steps, 4) for k, v in kernel_ms.items()},

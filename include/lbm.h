@@ -171,9 +171,12 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
  * device workspace (256-byte aligned, >= lbm_workspace_size bytes, must outlive
  * the handle).  The current HIP device must be the workspace's device.  The
  * upload is synchronous.  It then times the three tile shapes of the correction
- * stencil that suit the lattice (four launches each, on the default stream) and keeps
- * the fastest; LBM_CORR_TILE=k in the environment (0-2 for lattices with a
- * cross-section, 3-5 for lattices one node thick in y and z) picks shape k instead.
+ * stencil that suit the lattice (four launches each, on a non-blocking stream that the
+ * call creates, waits for and destroys: lbm_create has no stream argument because it
+ * returns only when the handle is ready, and the private stream keeps the timing apart
+ * from the caller's streams) and keeps the fastest; LBM_CORR_TILE=k in the environment
+ * (0-2 for lattices with a cross-section, 3-5 for lattices one node thick in y and z)
+ * picks shape k instead.
  * Every shape gives the same bits.  The timing overwrites the side channel and the
  * deferred corrections in the workspace, so a state left there by another handle is
  * not kept: start from lbm_init_fields. */

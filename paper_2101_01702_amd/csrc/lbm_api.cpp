@@ -401,10 +401,11 @@ struct lbm_ctx {
 namespace {
 
 // Tile shape of the correction stencil for this lattice: each valid shape is timed over
-// three launches (after one untimed) on the default stream, with the stencil's inputs
-// cleared, and the fastest kept.  LBM_CORR_TILE=k in the environment picks shape k when
-// it is valid for the lattice.  The stencil's output (the corrections) is cleared again
-// by lbm_init_fields.
+// three launches (after one untimed) on a non-blocking stream of its own, created and
+// destroyed here (so the timing neither waits for nor holds up work the caller has on
+// other streams), with the stencil's inputs cleared, and the fastest kept.
+// LBM_CORR_TILE=k in the environment picks shape k when it is valid for the lattice.
+// The stencil's output (the corrections) is cleared again by lbm_init_fields.
 hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
   int cand[3];
   const int nc = corr_tile_candidates(h->g, cand);
@@ -418,7 +419,9 @@ hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
       }
   }
   const Layout &L = h->L;
-  hipError_t e = launch_zero(ws + L.side_Y, (int64_t)((L.corr - L.side_Y) / 4), nullptr);
+  hipStream_t st = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = launch_zero(ws + L.side_Y, (int64_t)((L.corr - L.side_Y) / 4), st);
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (e == hipSuccess) e = hipEventCreate(&ev[0]);
   if (e == hipSuccess) e = hipEventCreate(&ev[1]);
@@ -426,10 +429,10 @@ hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
   int choice = cand[0];
   for (int i = 0; i < nc && e == hipSuccess; ++i) {
     h->g.corr_tile = cand[i];
-    e = launch_corr_only(h->g, h->b, h->d.storage, nullptr);
-    if (e == hipSuccess) e = hipEventRecord(ev[0], nullptr);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_corr_only(h->g, h->b, h->d.storage, nullptr);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], nullptr);
+    e = launch_corr_only(h->g, h->b, h->d.storage, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_corr_only(h->g, h->b, h->d.storage, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
     float t = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
@@ -438,8 +441,13 @@ hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
       choice = cand[i];
     }
   }
+  if (st) {
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = es;
+  }
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
+  if (st) (void)hipStreamDestroy(st);
   h->g.corr_tile = choice;
   return e;
 }

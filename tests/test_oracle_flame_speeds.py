@@ -43,9 +43,9 @@ def _run(prob, settle, lib=None):
     return fs, g, u, dTdt, pw
 
 
-def _composition_step(prob, phi_hot):
+def _composition_step(prob, phi_hot, width):
     x = np.arange(prob.nx, dtype=np.float64)
-    s = W.tanh_profile(x - (prob.nx / 2 - 0.5), 6.0)
+    s = W.tanh_profile(x - (prob.nx / 2 - 0.5), width)
     X = W.premixed_h2air_X(prob.mech, 1.0)[:, None] * (1 - s) + W.premixed_h2air_X(prob.mech, phi_hot)[:, None] * s
     prob.Y = W.mole_to_mass(X, prob.mech.molar_mass)
     prob.rho = W.lattice_density(np.full(prob.nx, W.P_ATM), prob.T, W.mean_molar_mass(X, prob.mech.molar_mass),
@@ -53,11 +53,18 @@ def _composition_step(prob, phi_hot):
     return prob
 
 
+# The balance holds up to the truncation of the lattice's second-order stencils, which
+# falls with the square of the profile width: over a 6-cell edge the conduction case
+# misses by 3.0%, over 12 cells by 1.1%, over 24 cells by 0.3% (a 4th-order time
+# difference changes none of these).  The two diffusion cases use 24-cell profiles and a
+# 1% bar.  The burning flame's own thickness (about ten cells across T = 0.2 of the
+# peak gradient, set by the conduction, not by D: diffusivities x2 and x4 leave it at
+# 6.5%) keeps its S_d at 7.3%: bar 10%.
 CASES = {
-    "conduction": (lambda: W.flame1d(nx=128, hot_cells=64, T_hot=420.0, edge=6.0), 300, 0.3, 0.06),
-    "enthalpy diffusion": (lambda: _composition_step(W.flame1d(nx=128, hot_cells=64, T_hot=420.0, edge=6.0), 2.5),
-                           300, 0.3, 0.06),
-    "heat release": (lambda: W.flame1d(nx=512, hot_cells=64), 1500, 0.2, 0.12),
+    "conduction": (lambda: W.flame1d(nx=256, hot_cells=128, T_hot=420.0, edge=24.0), 300, 0.3, 0.01),
+    "enthalpy diffusion": (lambda: _composition_step(W.flame1d(nx=256, hot_cells=128, T_hot=420.0, edge=24.0), 2.5,
+                                                     24.0), 300, 0.3, 0.01),
+    "heat release": (lambda: W.flame1d(nx=512, hot_cells=64), 1500, 0.2, 0.10),
 }
 
 
@@ -110,7 +117,8 @@ def test_front_velocity_matches_absolute_speed_on_the_isoline():
     parity measures it) against the isoline mean of S_a from eq. sd at the same time,
     over the quasi-1D flame's propagation (steps 1500..3500): the isotherm moves at its
     absolute speed, so the two agree to the interpolation of the front between nodes
-    (measured within 4%; bar 6%)."""
+    (measured within 4%; bar 6%): the front position is linear between two nodes of a
+    profile that is not, and the 50-step difference of two such positions carries it."""
     def front(T, T_u=300.0):
         k = int(np.nonzero(T >= 3.0 * T_u)[0][0])
         return k - 1 + (3.0 * T_u - T[k - 1]) / (T[k] - T[k - 1])
