@@ -934,7 +934,10 @@ struct AdjBuf {
 // directions on the lanes of a 32-lane group (moments by group sums), its species on
 // lanes 0..M-1.
 template <int M>
-__global__ __launch_bounds__(ADJ_BLOCK) void k_adj_fwd(ALat L, const Tables *tbp, AdjBuf ab, double omega1) {
+// It also copies the incoming adjoint of its node into the work buffer Ln (lam_in is
+// overwritten with lambda_n by k_adj_step, while Ln is read at the neighbours).
+__global__ __launch_bounds__(ADJ_BLOCK) void k_adj_fwd(ALat L, const Tables *tbp, AdjBuf ab, double omega1,
+                                                       const double *lam_in, double *Ln) {
   constexpr int S = M + 1;
   const Tables &tb = *tbp;
   const int slot = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -944,9 +947,15 @@ __global__ __launch_bounds__(ADJ_BLOCK) void k_adj_fwd(ALat L, const Tables *tbp
   const bool valid = node_ok && lane < Q;
   const int i = lane < Q ? lane : 13;
   const int64_t N = L.N;
-  double f[S];
+  double f[S], lam[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) f[s] = valid ? ab.P[((int64_t)s * Q + i) * N + nn] : 0.0;
+  for (int s = 0; s < S; ++s) {
+    f[s] = valid ? ab.P[((int64_t)s * Q + i) * N + nn] : 0.0;
+    lam[s] = valid ? lam_in[((int64_t)s * Q + i) * N + nn] : 0.0;
+  }
+  if (valid)
+#pragma unroll
+    for (int s = 0; s < S; ++s) Ln[((int64_t)s * Q + i) * N + nn] = lam[s];
   Mom<M> m;
   group_moments<M>(i, valid, f, m);
   // species on lanes a < M; the Newton iteration on every lane alike, on the group sums
@@ -1541,7 +1550,8 @@ hipError_t adj_step_m(const Geom &g, const Tables *tb, const AdjBufHost &h, doub
                       double *adj, double *grad, hipStream_t st) {
   const ALat L = make_alat(g);
   AdjBuf ab{h.P, h.Ln, h.T0, h.fY, h.fw, h.lX, h.lgY, h.lpsi, h.lphi, h.lYs, h.part};
-  hipLaunchKernelGGL((k_adj_fwd<M>), dim3(ablocks(g.N, NPB)), dim3(ADJ_BLOCK), 0, st, L, tb, ab, omega1);
+  hipLaunchKernelGGL((k_adj_fwd<M>), dim3(ablocks(g.N, NPB)), dim3(ADJ_BLOCK), 0, st, L, tb, ab, omega1,
+                     (const double *)adj, h.Ln);
   hipLaunchKernelGGL((k_adj_x<M>), dim3(ablocks(g.N, NPB)), dim3(ADJ_BLOCK), 0, st, L, ab);
   hipLaunchKernelGGL(k_adj_psi, dim3(ablocks(g.N, 64)), dim3(64), 0, st, L, ab);
   hipLaunchKernelGGL((k_adj_phi<M>), dim3(ablocks(g.N * (M + 1), 128)), dim3(128), 0, st, L, ab, 1.0 / omega - 0.5);

@@ -924,8 +924,7 @@ lbm_status lbm_adjoint_step(lbm_handle h, const void *d_state, void *d_adj, doub
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double *T0 = nullptr;
   hipError_t e = adjoint_forward_state(h, d_state, st, &T0);
-  const size_t pop_words = (size_t)(h->d.n_species + 1) * Q * (size_t)h->g.N;
-  if (e == hipSuccess) e = hipMemcpyAsync(h->adj.Ln, d_adj, pop_words * 8, hipMemcpyDeviceToDevice, st);
+  // the incoming adjoint is copied to the work buffer Ln by the first kernel of the step
   if (e == hipSuccess) {
     AdjBufHost a = h->adj;
     a.T0 = T0;

@@ -249,12 +249,16 @@ __device__ __forceinline__ double pull_f(const ST *__restrict__ base, const Src 
                                          int cz, int s, int i, const CollideConsts &kc) {
   double v = pop_val(ld(base, r.ps), s, i, kc);
   {
+    // the correction loads are unconditional and the terms selected: a branch around a
+    // load would wait for every load in flight at its join
     const uint32_t ns = r.ps;   // padded planes: zero at open ghosts, mirrored at symmetry ghosts
     if constexpr (CX != 0) {
-      if (cy == 0 && cz == 0) v += double(CT(0.5 * CX * double(ld(cr.X, ns))));
+      const double x0 = double(ld(cr.X, ns));
+      v += (cy == 0 && cz == 0) ? double(CT(0.5 * CX * x0)) : 0.0;
     } else {
-      if (cy != 0 && cz == 0) v += double(CT(0.5 * cy * double(ld(cr.X + cr.NPAD, ns))));
-      if (cy == 0 && cz != 0) v += double(CT(0.5 * cz * double(ld(cr.X + 2 * cr.NPAD, ns))));
+      const double x1 = double(ld(cr.X + cr.NPAD, ns)), x2 = double(ld(cr.X + 2 * cr.NPAD, ns));
+      v += (cy != 0 && cz == 0) ? double(CT(0.5 * cy * x1)) : 0.0;
+      v += (cy == 0 && cz != 0) ? double(CT(0.5 * cz * x2)) : 0.0;
     }
   }
   return v;
@@ -270,8 +274,9 @@ __device__ __forceinline__ double pull_g(const ST *__restrict__ base, const Src 
     const uint32_t ns = r.ps;   // padded planes: zero at open ghosts, mirrored at symmetry ghosts
     double d = 0.0;
     if constexpr (CX != 0) d += CX * double(ld(cr.Cg, ns));
-    if (cy != 0) d += cy * double(ld(cr.Cg + cr.NPAD, ns));
-    if (cz != 0) d += cz * double(ld(cr.Cg + 2 * cr.NPAD, ns));
+    const double c1 = double(ld(cr.Cg + cr.NPAD, ns)), c2 = double(ld(cr.Cg + 2 * cr.NPAD, ns));
+    d += cy != 0 ? cy * c1 : 0.0;
+    d += cz != 0 ? cz * c2 : 0.0;
     v += double(CT(w3 * d));
   }
   return v;
@@ -1720,7 +1725,10 @@ __device__ __forceinline__ GhostSrc ghost_src(const Geom &g, const GhostCell &c)
 // faces only, it is the mirror image: the post-collision population of the mirrored
 // direction at the mirrored node (the quarter-domain flame of Sec. 5.2); beyond a
 // symmetry and an open face, the equilibrium of the mirrored direction.
-template <int M, typename ST, typename RT>
+// SPLIT: one thread per (ghost cell, direction), the direction from the grid's y index
+// (lattices with few ghost cells, where one thread per cell would run the 27 directions
+// one after the other); otherwise one thread per cell.  Both give the same bits.
+template <int M, typename ST, typename RT, bool SPLIT>
 __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts kc, int cur, int64_t nx_slab,
                                                int64_t ny_slab, int64_t nz_slab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1732,6 +1740,18 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts 
   const int64_t na = ((int64_t)gs.a3[2] * g.ny + gs.a3[1]) * g.nx + gs.a3[0];
   const int64_t p = c.p, pa = gs.pa;
   ST *dst = static_cast<ST *>(b.pop[cur ^ 1]);
+  if (SPLIT) {
+    // leave before the equilibrium when no node pulls this direction from the cell
+    const int i = blockIdx.y;
+    const int cv[3] = {cx_of(i), cy_of(i), cz_of(i)};
+    bool need = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int t2 = c.gc[d] + cv[d];
+      need = need && (g.per[d] || (t2 >= 0 && t2 < nn[d]));
+    }
+    if (!need) return;
+  }
   EqState<M> e;
   if (gs.open) {
     const RT *srho = static_cast<const RT *>(b.side_rho);
@@ -1748,8 +1768,9 @@ __global__ __launch_bounds__(128) void k_ghost(Geom g, Buffers b, CollideConsts 
   // only the directions along which a node of the lattice (of the segment, for x) pulls
   // from this ghost cell (a face cell serves 9, an edge cell 3, a corner cell 1); a
   // runtime loop keeps the kernel small
+  const int i_lo = SPLIT ? (int)blockIdx.y : 0, i_hi = SPLIT ? (int)blockIdx.y + 1 : 27;
 #pragma unroll 1
-  for (int i = 0; i < 27; ++i) {
+  for (int i = i_lo; i < i_hi; ++i) {
     const int cv[3] = {cx_of(i), cy_of(i), cz_of(i)};
     bool need = true;
 #pragma unroll
@@ -1855,12 +1876,15 @@ __global__ __launch_bounds__(64) void k_export(Geom g, Buffers b, CollideConsts 
     if (kx != kx_run) return;
     const int i = kx + 3 * kyz;
     const Src r = make_src(g, ax, ay, az, kx, ky, kz);
-    out[((int64_t)(M - 1) * Q + i) * nn + k] =
-        pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
-    out[((int64_t)M * Q + i) * nn + k] =
-        pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
-    for (int a = 0; a < M - 1; ++a)
-      out[((int64_t)a * Q + i) * nn + k] = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
+    // every set's value first, then the stores: a store between two loads would wait
+    // for the first load, one round trip per set
+    double v[M + 1];
+    v[M - 1] = pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
+    v[M] = pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
+#pragma unroll
+    for (int a = 0; a < M - 1; ++a) v[a] = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
+#pragma unroll
+    for (int s2 = 0; s2 <= M; ++s2) out[((int64_t)s2 * Q + i) * nn + k] = v[s2];
   });
   if (T_out && blockIdx.y == 0) T_out[k] = b.T[n];
 }
@@ -2253,8 +2277,14 @@ struct RunGhost {
     const int64_t sz = g.pz ? 2LL * g.nx * g.ny : 0;
     const int64_t tot = sx + sy + sz;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_ghost<M, ST, RT>), dim3(blocks_for(tot, 128)), dim3(128), 0, st, g, b, kc, cur, sx, sy,
-                       sz);
+    // below 32768 ghost cells (quasi-1D flames and their batches, small lattices) a
+    // thread per cell and direction; above, a thread per cell
+    if (tot < 32768)
+      hipLaunchKernelGGL((k_ghost<M, ST, RT, true>), dim3(blocks_for(tot, 128), 27), dim3(128), 0, st, g, b, kc, cur,
+                         sx, sy, sz);
+    else
+      hipLaunchKernelGGL((k_ghost<M, ST, RT, false>), dim3(blocks_for(tot, 128)), dim3(128), 0, st, g, b, kc, cur,
+                         sx, sy, sz);
     return hipGetLastError();
   }
 };
