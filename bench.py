@@ -82,6 +82,29 @@ def copy_ceiling_gbs(torch, dev, lbm=None, nbytes=4 << 30, reps=5):
     return tuple(out)
 
 
+def mix_ceiling_gbs(torch, dev, nbytes=4 << 30, reps=5):
+    """Bandwidth of plain streaming kernels with other read:write mixes than a copy's
+    1:1: an elementwise c = a + b (2:1, about the step kernel's own mix of counted reads
+    and writes) over buffers of nbytes/2 each, and a sum over nbytes (read only).
+    Returns (read 2 : write 1, read only) in GB/s of bytes moved."""
+    a = torch.ones(nbytes // 8, dtype=torch.float32, device=dev)
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    r = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    out = []
+    for moved, once in ((1.5 * nbytes, lambda: torch.add(a, b, out=c)), (1.0 * nbytes, lambda: r.sum())):
+        once()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize(dev)
+        out.append(moved / ((time.perf_counter() - t0) / reps) / 1e9)
+    del a, b, c, r
+    torch.cuda.empty_cache()
+    return tuple(out)
+
+
 def host_cpu():
     """(CPU model, logical CPUs the host reports, threads the oracle may use: the box's
     share of 16)."""
@@ -347,7 +370,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_only:
         cc = copy_ceiling_gbs(torch, dev, lbm)
-        print(json.dumps({"copy_ceiling_GBps": {"runtime_copy": round(cc[0], 1), "stream_kernel": round(cc[1], 1)},
+        mc = mix_ceiling_gbs(torch, dev)
+        print(json.dumps({"copy_ceiling_GBps": {"runtime_copy": round(cc[0], 1), "stream_kernel": round(cc[1], 1),
+                                                "read2_write1": round(mc[0], 1), "read_only": round(mc[1], 1)},
                           "bytes": 2 * (4 << 30)}))
         return
     if args.adjoint_only:
@@ -427,7 +452,9 @@ def main():
     if args.full_error_steps > 0 and storage != W.STORE_F64:
         out["error_vs_f64_full"] = error_vs_f64_full(lbm, W, storage, args.n, args.full_error_steps)
     cc_runtime, cc_stream = copy_ceiling_gbs(torch, dev, lbm)
-    out["copy_ceiling_GBps"] = {"runtime_copy": round(cc_runtime, 1), "stream_kernel": round(cc_stream, 1)}
+    mc = mix_ceiling_gbs(torch, dev)
+    out["copy_ceiling_GBps"] = {"runtime_copy": round(cc_runtime, 1), "stream_kernel": round(cc_stream, 1),
+                                "read2_write1": round(mc[0], 1), "read_only": round(mc[1], 1)}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100)
         out["adjoint_all_states"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=1)

@@ -327,6 +327,13 @@ lbm_status lbm_adjoint_init(lbm_handle h, const double *d_rho, const double *d_u
  * LBM_ERR_DEVICE_ANOMALY when any bit was set. */
 lbm_status lbm_status_sync(lbm_handle h, void *stream, uint32_t *anomaly_bits);
 
+/* Growth law of the expanding flame (Sec. 5.2): the least-squares line through
+ * (ln t_k, ln R_k), k < n, of mean radii R_k (from lbm_flame_speeds' isosurface sums)
+ * sampled at times t_k, as R = a t^alpha.  Host arrays; host arithmetic only (no device
+ * work).  LBM_ERR_ARG for n < 2, a null pointer, a t_k or R_k that is not positive and
+ * finite, or all t_k equal. */
+lbm_status lbm_growth_fit(const double *t, const double *R, int64_t n, double *a, double *alpha);
+
 /* Measurement aid: copy `bytes` (a multiple of 16, 16-byte aligned buffers) with a plain
  * streaming kernel of 16-byte loads and stores, the read + write bandwidth ceiling of a
  * streaming kernel on the device the stream belongs to. */

@@ -89,10 +89,12 @@ __device__ __forceinline__ double invD(TB &tb, int M, int a, int b) {
   return tb.invDp[lo * M - lo * (lo + 1) / 2 + (hi - lo - 1)];
 }
 
-// Sum over the 32 lanes of a node group; every lane gets the total.  Within each row of
-// 16 lanes by DPP moves (swap neighbours, swap pairs, then rotations by 4 and by 8), then
-// across the two rows by a swizzle that exchanges lanes l and l ^ 16.  The moves act on
-// the two 32-bit halves of the double.
+// Sum over the 32 lanes of a node group; every lane gets the same total, bit for bit.
+// Within each row of 16 lanes by DPP moves that pair lanes symmetrically (swap
+// neighbours, swap pairs, mirror each half row, mirror the row: each lane adds the value
+// of a partner that adds its value back, so both form the same sum), then across the two
+// rows by a swizzle that exchanges lanes l and l ^ 16.  The moves act on the two 32-bit
+// halves of the double.
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(v) & 0xffffffff), CTRL, 0xf, 0xf, false);
@@ -107,8 +109,8 @@ __device__ __forceinline__ double swz_xor16(double v) {
 __device__ __forceinline__ double gsum(double v) {
   v += dpp_mov<0xb1>(v);    // quad_perm [1, 0, 3, 2]
   v += dpp_mov<0x4e>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_mov<0x124>(v);   // row_ror:4
-  v += dpp_mov<0x128>(v);   // row_ror:8
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
   v += swz_xor16(v);        // bit-mask swizzle: and 0x1f, xor 0x10
   return v;
 }

@@ -988,6 +988,31 @@ lbm_status lbm_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *s
   return LBM_OK;
 }
 
+lbm_status lbm_growth_fit(const double *t, const double *R, int64_t n, double *a, double *alpha) {
+  if (!t || !R || !a || !alpha) return arg_fail(nullptr, "pointers must not be NULL");
+  if (n < 2) return arg_fail(nullptr, "the fit needs at least two samples");
+  // centred sums: slope = sum (x - mx)(y - my) / sum (x - mx)^2, x = ln t, y = ln R
+  double mx = 0.0, my = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    if (!(t[k] > 0.0) || !(R[k] > 0.0) || !std::isfinite(t[k]) || !std::isfinite(R[k]))
+      return arg_fail(nullptr, "times and radii must be positive and finite");
+    mx += std::log(t[k]);
+    my += std::log(R[k]);
+  }
+  mx /= (double)n;
+  my /= (double)n;
+  double sxx = 0.0, sxy = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double dx = std::log(t[k]) - mx, dy = std::log(R[k]) - my;
+    sxx += dx * dx;
+    sxy += dx * dy;
+  }
+  if (!(sxx > 0.0)) return arg_fail(nullptr, "the sample times must not all be equal");
+  *alpha = sxy / sxx;
+  *a = std::exp(my - *alpha * mx);
+  return LBM_OK;
+}
+
 const char *lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : g_last_error.c_str(); }
 
 }  // extern "C"

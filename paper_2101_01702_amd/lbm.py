@@ -58,7 +58,7 @@ EXPORTS = ("lbm_workspace_size", "lbm_create", "lbm_destroy", "lbm_init_fields",
            "lbm_step_timed", "lbm_step_graph", "lbm_macros", "lbm_populations", "lbm_diagnostics",
            "lbm_flame_speeds", "lbm_flame_speeds_static", "lbm_state_size", "lbm_state_save",
            "lbm_state_load", "lbm_set_arrhenius", "lbm_adjoint_step", "lbm_adjoint_macros", "lbm_adjoint_init",
-           "lbm_stream_copy",
+           "lbm_stream_copy", "lbm_growth_fit",
            "lbm_status_sync", "lbm_last_error")
 DIAG_TOTALS = 4   # heat release rate, nodes with T >= T_iso, mass, total energy
 FLAME_WORK = 17   # FP64 work fields per node of lbm_flame_speeds
@@ -96,6 +96,7 @@ def load(path: Optional[str] = None):
     lib.lbm_adjoint_macros.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.lbm_adjoint_init.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.lbm_growth_fit.argtypes = [_dp, _dp, C.c_int64, _dp, _dp]
     lib.lbm_status_sync.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = C.c_char_p
@@ -405,11 +406,14 @@ class Solver:
 
 def growth_exponent(t: Sequence[float], r: Sequence[float]):
     """Least-squares fit of R = a t^alpha to samples of a mean radius (the growth law of
-    the expanding flame, Sec. 5.2): returns (a, alpha) from a line through ln R against
-    ln t."""
-    lt = np.log(np.asarray(t, dtype=np.float64))
-    lr = np.log(np.asarray(r, dtype=np.float64))
-    if lt.size < 2:
-        raise ValueError("the fit needs at least two samples")
-    alpha, ln_a = np.polyfit(lt, lr, 1)
-    return float(np.exp(ln_a)), float(alpha)
+    the expanding flame, Sec. 5.2), by lbm_growth_fit: returns (a, alpha)."""
+    lib = load()
+    tt = np.ascontiguousarray(t, dtype=np.float64).reshape(-1)
+    rr = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+    if tt.size != rr.size:
+        raise ValueError("t and r must have the same length")
+    a, alpha = C.c_double(0.0), C.c_double(0.0)
+    st = lib.lbm_growth_fit(tt.ctypes.data_as(_dp), rr.ctypes.data_as(_dp), tt.size, C.byref(a), C.byref(alpha))
+    if st != LBM_OK:
+        raise ValueError(lib.lbm_last_error(None).decode())
+    return float(a.value), float(alpha.value)

@@ -326,3 +326,14 @@ def test_growth_exponent_fit():
     assert abs(alpha - 1.16) < 1e-12 and abs(a - 0.37) < 1e-12
     with pytest.raises(ValueError):
         lbm.growth_exponent([1.0], [2.0])
+    with pytest.raises(ValueError):
+        lbm.growth_exponent([1.0, 2.0], [1.0, -1.0])
+    with pytest.raises(ValueError):
+        lbm.growth_exponent([3.0, 3.0], [1.0, 2.0])
+    # against the plain least-squares line through the logs of seeded noisy samples
+    rng = np.random.default_rng(5)
+    tn = np.sort(rng.uniform(100.0, 5000.0, 12))
+    rn = 0.5 * tn ** 0.9 * np.exp(rng.normal(0.0, 0.05, 12))
+    a, alpha = lbm.growth_exponent(tn, rn)
+    ref_alpha, ref_ln_a = np.polyfit(np.log(tn), np.log(rn), 1)
+    assert abs(alpha - ref_alpha) < 1e-12 and abs(np.log(a) - ref_ln_a) < 1e-12
