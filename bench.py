@@ -30,12 +30,16 @@ sys.path.insert(0, ROOT)
 METRIC = "reactive MLUPS & % of HBM peak at stated error vs FP64; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_sphere3d_256.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2101_01702_amd", "csrc", "lbm_device.hip")
+# the step kernel's source and the host code that lays out its buffers (plane padding)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2101_01702_amd", "csrc", f) for f in ("lbm_device.hip", "lbm_api.cpp")]
 
 
 def kernel_source_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(kernel):

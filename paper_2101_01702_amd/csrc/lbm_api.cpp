@@ -55,7 +55,13 @@ Geom make_geom(const lbm_desc &d) {
   g.vt = d.visc_T_exp != 0.0 ? 1 : 0;
   g.N = (int64_t)d.nx * d.ny * d.nz;
   g.XG = (int64_t)g.NX * g.NY * g.NZ;
-  g.NPAD = g.XG + (g.xg ? 2LL * g.nseg * g.NY * g.NZ : 0);
+  // Planes are padded to a multiple of 64 cells, so that every plane starts on a 256-byte
+  // boundary; from 65536 cells on, to a multiple of 1024 cells plus 64 more, so that
+  // each plane also starts 256 bytes (modulo 4 KiB) after the previous one.  Packed
+  // planes started a few words off a cache line, so that each wave's stretch of a row
+  // touched one more line: the 256^3 step ran 5-10% slower.
+  const int64_t used = g.XG + (g.xg ? 2LL * g.nseg * g.NY * g.NZ : 0);
+  g.NPAD = used >= 65536 ? (used + 1023) / 1024 * 1024 + 64 : (used + 63) / 64 * 64;
   return g;
 }
 

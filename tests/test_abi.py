@@ -253,20 +253,21 @@ def test_large_slab_needs_no_24_bit_products(lib):
 
 def test_segment_descriptors(lib):
     """A batch of lattices along x: lengths >= 1 summing to nx, non-periodic x faces;
-    two x ghost cells per segment and row, plus the segment table."""
-    prob = W.flame_batch(lengths=[7, 1, 12], phis=[1.0, 1.0, 1.0], hot_cells=4, storage=W.STORE_F64)
+    two x ghost cells per segment and row, plus the segment table.  Planes are padded to
+    multiples of 64 cells: 62 cells with 2 ghosts fill one such block, with 6 ghosts two."""
+    prob = W.flame_batch(lengths=[30, 1, 31], phis=[1.0, 1.0, 1.0], hot_cells=4, storage=W.STORE_F64)
     d, keep = lbm.make_desc(prob)
     assert d.n_segments == 3
     code, n3, msg = _ws(lib, d)
     assert code == 0, msg
-    one = W.flame_batch(lengths=[20], phis=[1.0], hot_cells=4, storage=W.STORE_F64)
+    one = W.flame_batch(lengths=[62], phis=[1.0], hot_cells=4, storage=W.STORE_F64)
     d1, k1 = lbm.make_desc(one)
     assert d1.n_segments == 0
     code, n1, msg = _ws(lib, d1)
     assert code == 0, msg
     S = prob.M + 1
-    assert n3 - n1 >= 2 * S * 27 * 4 * 8            # 2 x 2 more ghost cells per plane, two copies
-    for lens, needle in (([7, 1, 11], "sum"), ([7, 0, 13], "segment_lengths[1]")):
+    assert n3 - n1 >= 2 * S * 27 * 64 * 8           # one more 64-cell block per plane, two copies
+    for lens, needle in (([30, 1, 30], "sum"), ([30, 0, 32], "segment_lengths[1]")):
         arr = np.array(lens, np.int32)
         d.segment_lengths = arr.ctypes.data_as(C.POINTER(C.c_int32))
         code, _, msg = _ws(lib, d)
@@ -283,7 +284,7 @@ def test_segment_descriptors(lib):
     code, _, msg = _ws(lib, d)
     assert code == -1 and "periodic" in msg
     d, keep = lbm.make_desc(prob)
-    d.n_segments = 21
+    d.n_segments = prob.nx + 1
     code, _, msg = _ws(lib, d)
     assert code == -1 and "exceeds" in msg
 
