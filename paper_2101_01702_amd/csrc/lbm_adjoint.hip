@@ -18,10 +18,11 @@
 // Layout of the work: a node's 27 directions sit on 27 lanes of a 32-lane group (8 nodes
 // per 256-thread workgroup).  Each lane reverses its direction's part of the collision
 // (the equilibria, the inter-species term and the energy population of that direction)
-// and the per-node sums over directions are butterfly reductions across the group.  The
-// node-level chain (temperature, thermo, rates, the Stefan-Maxwell solve) runs on the
-// group's first lane over a record of the node in LDS.  The stencils of X and grad Y are
-// reversed as gathers with the transposed stencil.
+// and the per-node sums over directions are group sums.  The node-level chain
+// (temperature, thermo, rates, the Stefan-Maxwell solve) works on a record of the node in
+// LDS, spread over the group: species on lanes 0..M-1, reactions on lanes 0..R-1, the
+// scalar parts on the first lane.  The stencils of X and grad Y are reversed as gathers
+// with the transposed stencil.
 #include "lbm_internal.h"
 
 namespace lbm {

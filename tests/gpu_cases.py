@@ -99,7 +99,7 @@ TOL64_U = 1e-10
 TOL32 = 1e-5
 # FP32 storage does not reach 1e-5 on every field: the velocity of nearly quiescent
 # lattices against the floor 1e-3 sqrt(zeta_ref) (rounding of the populations, absolute:
-# measured up to 9e-5) and the trace-radical mass fractions of igniting flames (H, OH:
+# measured up to 1.1e-4) and the trace-radical mass fractions of igniting flames (H, OH:
 # max Y_a ~ 6e-5 to 9e-5; measured 1.2e-5 to 2.5e-5).  Rounding the oracle's own state to
 # FP32 after every step gives the same mass-fraction figure (1.5e-5 on the 512-cell flame):
 # the storage rounding of every set (f alone 9e-6, g alone 6e-6, the species alone

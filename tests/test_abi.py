@@ -338,3 +338,12 @@ def test_growth_exponent_fit():
     a, alpha = lbm.growth_exponent(tn, rn)
     ref_alpha, ref_ln_a = np.polyfit(np.log(tn), np.log(rn), 1)
     assert abs(alpha - ref_alpha) < 1e-12 and abs(np.log(a) - ref_ln_a) < 1e-12
+
+
+def test_stream_copy_rejects_unaligned_arguments(lib):
+    """Size and pointers must be multiples of 16 bytes; the check comes before any device
+    work (the pointers here are never dereferenced)."""
+    assert lib.lbm_stream_copy(C.c_void_p(4096), C.c_void_p(8192), 24, None) == -1
+    assert b"16" in lib.lbm_last_error(None)
+    assert lib.lbm_stream_copy(C.c_void_p(4100), C.c_void_p(8192), 32, None) == -1
+    assert lib.lbm_stream_copy(None, C.c_void_p(8192), 32, None) == -1
