@@ -127,6 +127,25 @@ def test_sphere3d_ragged_fp32(lbm_mod):
     _assert_fields(mac, sim.macros(), prob, TOL32, "sphere3d 13x10x9 fp32")
 
 
+# --- the circular flame extruded along z (open x and y faces, periodic z) --------------
+def test_cylinder3d_fp64(lbm_mod):
+    prob = W.cylinder3d(n=32, nz=2, radius=10.0, storage=W.STORE_F64)
+    s, mac, bits = _gpu_run(lbm_mod, prob, 100, W.STORE_F64)
+    sim, anom = oracle_run(prob, 100)
+    assert bits == 0 and anom == 0
+    _assert_fields(mac, sim.macros(), prob, TOL64, "cylinder3d 32x32x2 fp64 100")
+    pop, _ = s.populations(np.arange(prob.N))
+    assert max(pop_errors(pop, sim.state()[0])) <= TOL64
+
+
+def test_cylinder3d_fp32_1000_steps(lbm_mod):
+    prob = W.cylinder3d(n=32, nz=2, radius=10.0, storage=W.STORE_F32)
+    s, mac, bits = _gpu_run(lbm_mod, prob, 1000, W.STORE_F32)
+    sim, anom = oracle_run(prob, 1000)
+    assert bits == 0 and anom == 0
+    _assert_fields(mac, sim.macros(), prob, TOL32, "cylinder3d 32x32x2 fp32 1000")
+
+
 # --- edge cases ------------------------------------------------------------------------
 @pytest.mark.parametrize("shape,bc", [
     ((1, 1, 7), (0, 0, 0, 0, 1, 2)),     # z-only column, zero-velocity top face
