@@ -409,11 +409,12 @@ namespace {
 // Tile shape of the correction stencil for this lattice: each valid shape is timed over
 // three launches (after one untimed) on a non-blocking stream of its own, created and
 // destroyed here (so the timing neither waits for nor holds up work the caller has on
-// other streams), with the stencil's inputs cleared, and the fastest kept.
+// other streams), with the stencil's inputs (and the temperature) cleared, and the
+// fastest kept.  A shape that takes psi from k_psi is timed with k_psi before it.
 // LBM_CORR_TILE=k in the environment picks shape k when it is valid for the lattice.
 // The stencil's output (the corrections) is cleared again by lbm_init_fields.
 hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
-  int cand[3];
+  int cand[LBM_CORR_TILES_MAX];
   const int nc = corr_tile_candidates(h->g, cand);
   h->g.corr_tile = cand[0];
   if (const char *env = std::getenv("LBM_CORR_TILE")) {
@@ -427,7 +428,7 @@ hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
   const Layout &L = h->L;
   hipStream_t st = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = launch_zero(ws + L.side_Y, (int64_t)((L.corr - L.side_Y) / 4), st);
+  if (e == hipSuccess) e = launch_zero(ws + L.T, (int64_t)((L.corr - L.T) / 4), st);
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (e == hipSuccess) e = hipEventCreate(&ev[0]);
   if (e == hipSuccess) e = hipEventCreate(&ev[1]);
@@ -435,9 +436,14 @@ hipError_t tune_corr_tile(lbm_ctx *h, char *ws) {
   int choice = cand[0];
   for (int i = 0; i < nc && e == hipSuccess; ++i) {
     h->g.corr_tile = cand[i];
-    e = launch_corr_only(h->g, h->b, h->d.storage, st);
+    auto once = [&] {
+      hipError_t r = hipSuccess;
+      if (!corr_forms_psi(cand[i])) r = launch_psi(h->g, h->b, h->d.storage, st);
+      return r == hipSuccess ? launch_corr_only(h->g, h->b, h->d.storage, st) : r;
+    };
+    e = once();
     if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_corr_only(h->g, h->b, h->d.storage, st);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = once();
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
     float t = 0.f;
@@ -697,7 +703,8 @@ static lbm_status run_steps(lbm_handle h, int32_t n_steps, hipStream_t st, float
     const int cur = h->cur;
     e = timed(0, [&] { return launch_step(h->g, h->b, h->kc, store, cur, st); });
     if (e == hipSuccess) e = timed(3, [&] { return launch_ghost(h->g, h->b, h->kc, store, cur, st); });
-    if (e == hipSuccess) e = timed(1, [&] { return launch_psi(h->g, h->b, store, st); });
+    if (e == hipSuccess && !corr_forms_psi(h->g.corr_tile))
+      e = timed(1, [&] { return launch_psi(h->g, h->b, store, st); });
     if (e == hipSuccess) e = timed(2, [&] { return launch_corr(h->g, h->b, store, st); });
     if (e == hipSuccess) h->cur ^= 1;
   }

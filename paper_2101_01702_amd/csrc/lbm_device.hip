@@ -1376,7 +1376,30 @@ __global__ __launch_bounds__(ISL_BLOCK, LBM_STEP_WAVES_PER_SIMD) void k_step(Geo
 }
 
 // ---- psi_alpha = (1/omega - 1/2) d_alpha phi_alpha (isotropic gradient) ------------
-template <typename RT>
+// One node's sums for psi, term by term in the order of the directions, from the phi
+// components of its neighbours (get(I, d): component d of the neighbour along
+// direction I).  sg holds the sign of the mirror image of phi_alpha beyond a symmetry
+// face (phi_alpha is odd in u_alpha); SYM = false when no face of the lattice is one:
+// every sign is then 1, and leaving the factor out changes no bit.
+template <bool SYM, typename G>
+__device__ __forceinline__ void psi_terms(G &&get, const double (&sg)[3][3], double (&acc)[3]) {
+  static_for<27>([&](auto Ic) {
+    constexpr int I = decltype(Ic)::value;
+    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+    constexpr double w = 3.0 * wgt(I);
+    if constexpr (SYM) {
+      if constexpr (cx != 0) acc[0] += (cx * w) * (sg[0][cx + 1] * get(Ic, 0));
+      if constexpr (cy != 0) acc[1] += (cy * w) * (sg[1][cy + 1] * get(Ic, 1));
+      if constexpr (cz != 0) acc[2] += (cz * w) * (sg[2][cz + 1] * get(Ic, 2));
+    } else {
+      if constexpr (cx != 0) acc[0] += (cx * w) * get(Ic, 0);
+      if constexpr (cy != 0) acc[1] += (cy * w) * get(Ic, 1);
+      if constexpr (cz != 0) acc[2] += (cz * w) * get(Ic, 2);
+    }
+  });
+}
+
+template <typename RT, bool SYM>
 __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
   const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
   if (n >= g.N) return;
@@ -1395,26 +1418,22 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
     ys[k] = nb_coord(y, k - 1, g.ny, g.per[1]);
     zs[k] = nb_coord(z, k - 1, g.nz, g.per[2]);
   }
-  // phi_alpha is odd in u_alpha: its mirror image beyond a symmetry face normal to
-  // alpha has the opposite sign
   double sg[3][3];
-  const int xyz[3] = {x, y, z}, lo3[3] = {xsg.x0, 0, 0}, hi3[3] = {xsg.x1, g.ny - 1, g.nz - 1};
+  if constexpr (SYM) {
+    const int xyz[3] = {x, y, z}, lo3[3] = {xsg.x0, 0, 0}, hi3[3] = {xsg.x1, g.ny - 1, g.nz - 1};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    sg[a][0] = (xyz[a] == lo3[a] && g.bc[2 * a] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
-    sg[a][1] = 1.0;
-    sg[a][2] = (xyz[a] == hi3[a] && g.bc[2 * a + 1] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+    for (int a = 0; a < 3; ++a) {
+      sg[a][0] = (xyz[a] == lo3[a] && g.bc[2 * a] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+      sg[a][1] = 1.0;
+      sg[a][2] = (xyz[a] == hi3[a] && g.bc[2 * a + 1] == LBM_BC_SYMMETRY) ? -1.0 : 1.0;
+    }
   }
   double acc[3] = {0, 0, 0};
-  static_for<27>([&](auto Ic) {
+  psi_terms<SYM>([&](auto Ic, int d) {
     constexpr int I = decltype(Ic)::value;
-    constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
-    const int64_t nn = ((int64_t)zs[cz + 1] * g.ny + ys[cy + 1]) * g.nx + xs[cx + 1];
-    constexpr double w = 3.0 * wgt(I);
-    if constexpr (cx != 0) acc[0] += (cx * w) * (sg[0][cx + 1] * double(phi[0 * N + nn]));
-    if constexpr (cy != 0) acc[1] += (cy * w) * (sg[1][cy + 1] * double(phi[1 * N + nn]));
-    if constexpr (cz != 0) acc[2] += (cz * w) * (sg[2][cz + 1] * double(phi[2 * N + nn]));
-  });
+    const int64_t nn = ((int64_t)zs[cz_of(I) + 1] * g.ny + ys[cy_of(I) + 1]) * g.nx + xs[cx_of(I) + 1];
+    return double(phi[d * N + nn]);
+  }, sg, acc);
   RT *psi = static_cast<RT *>(b.psi);
 #pragma unroll
   for (int d = 0; d < 3; ++d) psi[d * N + n] = RT(coef * acc[d]);
@@ -1526,6 +1545,279 @@ __global__ __launch_bounds__(CorrTile<K>::THREADS) void k_corr(Geom g, Buffers b
   for (int d = 0; d < 3; ++d) {
     corr[d * NPAD + pn] = CT(X[d]);
     corr[(3 + d) * NPAD + pn] = CT(C[d]);
+  }
+}
+
+// ---- psi and the corrections in one pass, marching along z ---------------------------
+// The values of k_psi followed by k_corr, bit for bit, without psi's round trip through
+// HBM and without its launch.  A workgroup takes a column of X x Y nodes over a range of
+// ZC planes and walks it along z.  Three planes of phi (X+4 by Y+4 cells: the psi tile
+// and its own one-cell halo), of psi and of Y_a (X+2 by Y+2 cells) rotate through LDS.
+// At plane z the workgroup stores phi of plane z+2, then stores Y_a of z+1 and forms psi
+// of z+1 from phi, then sums X and Cg of plane z from psi and Y_a; the loads of the next
+// plane are issued before the sums of the current one, and two barriers a plane order
+// the slots' reuse.
+// A cell of a tile holds the field at the node the gradient stencil takes (wrapped on
+// periodic axes, clamped on open ones), as in k_corr.  psi of a cell is formed at that
+// node from the phi tile: on a periodic axis its neighbours are the next cells of the
+// tile, on an open axis the clamped neighbours of the node, which the tile also covers.
+// In z a psi plane beyond an open face is never formed: the stencil takes the face plane.
+template <int TXv, int TYv, int ZCv>
+struct MarchTileT {
+  static constexpr int X = TXv, Y = TYv, ZC = ZCv, THREADS = X * Y;
+  static constexpr int PX = X + 4, PCELLS = PX * (Y + 4);   // phi tile
+  static constexpr int SX = X + 2, SCELLS = SX * (Y + 2);   // psi and Y_a tiles
+  static constexpr int PPT = (PCELLS + THREADS - 1) / THREADS, SPT = (SCELLS + THREADS - 1) / THREADS;
+  static_assert(SCELLS >= THREADS, "every thread holds a cell of each tile");
+};
+// shapes 6 and 7 (corr_tile_candidates): chunks of 32 and 16 planes; narrower in y for
+// FP64 fields, whose tiles take twice the LDS
+template <int K, typename RT>
+struct MarchTile;
+template <typename RT> struct MarchTile<6, RT> : MarchTileT<32, sizeof(RT) == 8 ? 4 : 8, 32> {};
+template <typename RT> struct MarchTile<7, RT> : MarchTileT<32, sizeof(RT) == 8 ? 4 : 8, 16> {};
+
+template <int K, typename RT>
+inline int64_t march_tiles(const Geom &g) {
+  using T = MarchTile<K, RT>;
+  return (int64_t)((g.nx + T::X - 1) / T::X) * ((g.ny + T::Y - 1) / T::Y) * ((g.nz + T::ZC - 1) / T::ZC);
+}
+
+// LDS slot of plane q (q >= -2)
+__device__ __forceinline__ int mslot(int q) { return (q + 3) % 3; }
+
+// A psi cell of the tile: the phi-tile columns of its x neighbours, the offsets of the
+// rows of its y neighbours, and the signs of the mirror images at symmetry faces (bit 0
+// x-, 1 x+, 2 y-, 3 y+); the same for every plane
+struct MarchCell {
+  int ox[3], oy[3], sym;
+};
+template <typename T>
+__device__ __forceinline__ MarchCell march_cell(const Geom &g, int c, int x0, int y0) {
+  const int hx = c % T::SX, hy = c / T::SX;
+  const int x = halo_coord(x0 - 1 + hx, g.nx, g.per[0]), y = halo_coord(y0 - 1 + hy, g.ny, g.per[1]);
+  const XSeg xsg = x_segment(g, x);
+  MarchCell m;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    m.ox[k] = g.per[0] ? hx + k : min(max(x + k - 1, xsg.x0), xsg.x1) - (x0 - 2);
+    m.oy[k] = (g.per[1] ? hy + k : nb_coord(y, k - 1, g.ny, false) - (y0 - 2)) * T::PX;
+  }
+  m.sym = (x == xsg.x0 && g.bc[0] == LBM_BC_SYMMETRY ? 1 : 0) | (x == xsg.x1 && g.bc[1] == LBM_BC_SYMMETRY ? 2 : 0) |
+          (y == 0 && g.bc[2] == LBM_BC_SYMMETRY ? 4 : 0) | (y == g.ny - 1 && g.bc[3] == LBM_BC_SYMMETRY ? 8 : 0);
+  return m;
+}
+
+template <int M, typename RT, typename CT, int K, bool SYM>
+__global__ __launch_bounds__((MarchTile<K, RT>::THREADS)) void k_corr_march(Geom g, Buffers b) {
+  using T = MarchTile<K, RT>;
+  constexpr int NT = T::THREADS, PC = T::PCELLS, SC = T::SCELLS, PPT = T::PPT, SPT = T::SPT;
+  __shared__ RT sphi[3][3 * PC];   // plane q in slot mslot(q); component d at d * PC + cell
+  __shared__ RT spsi[3][3 * SC];
+  __shared__ RT sY[3][M * SC];
+  const int tiles_x = (g.nx + T::X - 1) / T::X, tiles_y = (g.ny + T::Y - 1) / T::Y;
+  const int64_t t = xcd_tile();
+  const int x0 = (int)(t % tiles_x) * T::X, y0 = (int)((t / tiles_x) % tiles_y) * T::Y;
+  const int zb = (int)(t / ((int64_t)tiles_x * tiles_y)) * T::ZC, ze = min(zb + T::ZC, g.nz);
+  const int tid = threadIdx.x;
+  const RT *phi = static_cast<const RT *>(b.side_phi);
+  const RT *Yf = static_cast<const RT *>(b.side_Y);
+  const RT *wf = static_cast<const RT *>(b.side_w);
+  const int64_t N = g.N, NXY = (int64_t)g.nx * g.ny;
+  // a cell j > 0 of this thread exists when c(j) is within its tile (cell 0 always does)
+  auto has = [&](int j, int cells) { return j == 0 || tid + j * NT < cells; };
+  // in-plane index of the node each tile cell of this thread holds
+  int pxy[PPT], sxy[SPT];
+  MarchCell mc[SPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int c = min(tid + j * NT, PC - 1);
+    pxy[j] = halo_coord(y0 - 2 + c / T::PX, g.ny, g.per[1]) * g.nx + halo_coord(x0 - 2 + c % T::PX, g.nx, g.per[0]);
+  }
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int c = min(tid + j * NT, SC - 1);
+    sxy[j] = halo_coord(y0 - 1 + c / T::SX, g.ny, g.per[1]) * g.nx + halo_coord(x0 - 1 + c % T::SX, g.nx, g.per[0]);
+    mc[j] = march_cell<T>(g, c, x0, y0);
+  }
+  const int lx = tid % T::X, ly = tid / T::X, x = x0 + lx, y = y0 + ly;
+  const bool inb = x < g.nx && y < g.ny;
+  const int nxy = inb ? y * g.nx + x : 0;
+  const int c0 = (ly + 1) * T::SX + (lx + 1);
+  const XSeg xsg = x_segment(g, inb ? x : 0);
+  const int dxm = (!g.per[0] && x == xsg.x0) ? 0 : -1, dxp = (!g.per[0] && x == xsg.x1) ? 0 : 1;
+  const bool vt = g.vt != 0;
+  double coef0 = 0.0;
+  if (!vt) {
+    double om, om1;
+    relax_rates(*b.tab, 1.0, om, om1);
+    coef0 = 1.0 / om - 0.5;
+  }
+  // a psi or Y_a plane exists within the lattice, or by wrapping
+  auto live = [&](int q) { return g.per[2] || (q >= 0 && q < g.nz); };
+  auto plane = [&](int q) { return (int64_t)halo_coord(q, g.nz, g.per[2]) * NXY; };
+  auto load_phi = [&](int q, RT (&v)[PPT][3]) {
+    const int64_t o = plane(q);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[j][d] = phi[d * N + o + pxy[j]];
+  };
+  auto store_phi = [&](int q, const RT (&v)[PPT][3]) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+      if (has(j, PC)) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sphi[mslot(q)][d * PC + tid + j * NT] = v[j][d];
+      }
+  };
+  auto load_Y = [&](int q, RT (&v)[SPT][M]) {
+    const int64_t o = plane(q);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j)
+#pragma unroll
+      for (int a = 0; a < M; ++a) v[j][a] = Yf[a * N + o + sxy[j]];
+  };
+  auto store_Y = [&](int q, const RT (&v)[SPT][M]) {
+#pragma unroll
+    for (int j = 0; j < SPT; ++j)
+      if (has(j, SC)) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) sY[mslot(q)][a * SC + tid + j * NT] = v[j][a];
+      }
+  };
+  // stored temperature at the psi cells (read only for temperature-dependent rates)
+  auto load_T = [&](int q, double (&v)[SPT]) {
+    if (!vt) return;
+    const int64_t o = plane(q);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) v[j] = b.T[o + sxy[j]];
+  };
+  // psi of plane q at this thread's cells (the arithmetic of k_psi)
+  auto form_psi = [&](int q, const double (&tq)[SPT]) {
+    if (!live(q)) return;
+    int zs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zs[k] = mslot(g.per[2] ? q + k - 1 : nb_coord(q, k - 1, g.nz, false));
+    const int z = g.per[2] ? halo_coord(q, g.nz, true) : q;
+    const bool zlo = z == 0 && g.bc[4] == LBM_BC_SYMMETRY, zhi = z == g.nz - 1 && g.bc[5] == LBM_BC_SYMMETRY;
+    RT *ps = spsi[mslot(q)];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      if (!has(j, SC)) continue;
+      const MarchCell &m = mc[j];
+      double coef = coef0;
+      if (vt) {
+        double om, om1;
+        relax_rates(*b.tab, tq[j], om, om1);
+        coef = 1.0 / om - 0.5;
+      }
+      double sg[3][3];
+      if constexpr (SYM) {
+        sg[0][0] = (m.sym & 1) ? -1.0 : 1.0;
+        sg[0][2] = (m.sym & 2) ? -1.0 : 1.0;
+        sg[1][0] = (m.sym & 4) ? -1.0 : 1.0;
+        sg[1][2] = (m.sym & 8) ? -1.0 : 1.0;
+        sg[2][0] = zlo ? -1.0 : 1.0;
+        sg[2][2] = zhi ? -1.0 : 1.0;
+        sg[0][1] = sg[1][1] = sg[2][1] = 1.0;
+      }
+      double acc[3] = {0, 0, 0};
+      psi_terms<SYM>([&](auto Ic, int d) {
+        constexpr int I = decltype(Ic)::value;
+        return double(sphi[zs[cz_of(I) + 1]][d * PC + m.oy[cy_of(I) + 1] + m.ox[cx_of(I) + 1]]);
+      }, sg, acc);
+      const int c = tid + j * NT;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) ps[d * SC + c] = RT(coef * acc[d]);
+    }
+  };
+  auto load_w = [&](int q, RT (&v)[M]) {
+    if (!inb) return;
+#pragma unroll
+    for (int a = 0; a < M; ++a) v[a] = wf[a * N + (int64_t)q * NXY + nxy];
+  };
+
+  RT ph[PPT][3], yv[SPT][M], wv[M];
+  double tv[SPT] = {};
+  // prologue: phi of planes zb-2 .. zb+1, psi and Y_a of planes zb-1 and zb
+  load_phi(zb - 2, ph);
+  store_phi(zb - 2, ph);
+  load_phi(zb - 1, ph);
+  store_phi(zb - 1, ph);
+  load_phi(zb, ph);
+  store_phi(zb, ph);
+  load_Y(zb - 1, yv);
+  if (live(zb - 1)) store_Y(zb - 1, yv);
+  load_Y(zb, yv);
+  store_Y(zb, yv);
+  load_T(zb - 1, tv);
+  __syncthreads();
+  form_psi(zb - 1, tv);
+  load_phi(zb + 1, ph);
+  load_T(zb, tv);
+  __syncthreads();
+  store_phi(zb + 1, ph);
+  __syncthreads();
+  form_psi(zb, tv);
+  load_phi(zb + 2, ph);
+  load_Y(zb + 1, yv);
+  load_T(zb + 1, tv);
+  load_w(zb, wv);
+  __syncthreads();
+
+  CT *corr = static_cast<CT *>(b.corr);
+  const int64_t NPAD = g.NPAD;
+  for (int z = zb; z < ze; ++z) {
+    store_phi(z + 2, ph);
+    __syncthreads();
+    if (live(z + 1)) store_Y(z + 1, yv);
+    double tq[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) tq[j] = tv[j];
+    RT wz[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) wz[a] = wv[a];
+    if (z + 1 < ze) {   // the next plane's loads, in flight during the sums
+      load_phi(z + 3, ph);
+      load_Y(z + 2, yv);
+      load_T(z + 2, tv);
+      load_w(z + 1, wv);
+    }
+    form_psi(z + 1, tq);
+    __syncthreads();
+    if (!inb) continue;
+    int zs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zs[k] = mslot(g.per[2] ? z + k - 1 : nb_coord(z, k - 1, g.nz, false));
+    double wa[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) wa[a] = double(wz[a]);
+    double X[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+    static_for<27>([&](auto Ic) {
+      constexpr int I = decltype(Ic)::value;
+      constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
+      if constexpr (I != 13) {
+        const int nc = c0 + cy * T::SX + (cx < 0 ? dxm : (cx > 0 ? dxp : 0));
+        const RT *ps = spsi[zs[cz + 1]], *yy = sY[zs[cz + 1]];
+        constexpr double w = 3.0 * wgt(I);
+        if constexpr (cx != 0) X[0] -= (cx * w) * double(ps[0 * SC + nc]);
+        if constexpr (cy != 0) X[1] -= (cy * w) * double(ps[1 * SC + nc]);
+        if constexpr (cz != 0) X[2] -= (cz * w) * double(ps[2 * SC + nc]);
+        double hy = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) hy += wa[a] * double(yy[a * SC + nc]);
+        if constexpr (cx != 0) C[0] += (cx * w) * hy;
+        if constexpr (cy != 0) C[1] += (cy * w) * hy;
+        if constexpr (cz != 0) C[2] += (cz * w) * hy;
+      }
+    });
+    const int64_t pn = ((int64_t)(z + g.pz) * g.NY + (y + g.py)) * g.NX + x;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      corr[d * NPAD + pn] = CT(X[d]);
+      corr[(3 + d) * NPAD + pn] = CT(C[d]);
+    }
   }
 }
 
@@ -2228,6 +2520,11 @@ hipError_t dispatch(int M, int store, Args &&...args) {
 #undef LBM_CASE
 }
 
+inline bool any_symmetry(const Geom &g) {
+  for (int k = 0; k < 6; ++k)
+    if (g.bc[k] == LBM_BC_SYMMETRY) return true;
+  return false;
+}
 template <int M, typename ST, typename RT>
 struct RunStep {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, hipStream_t st) {
@@ -2255,6 +2552,17 @@ struct RunCorr {
     break;
       LBM_CORR_CASE(0) LBM_CORR_CASE(1) LBM_CORR_CASE(2) LBM_CORR_CASE(3) LBM_CORR_CASE(4) LBM_CORR_CASE(5)
 #undef LBM_CORR_CASE
+#define LBM_MARCH_CASE(K)                                                                              \
+  case K:                                                                                              \
+    if (any_symmetry(g))                                                                               \
+      hipLaunchKernelGGL((k_corr_march<M, RT, RT, K, true>), dim3((unsigned)march_tiles<K, RT>(g)),     \
+                         dim3(MarchTile<K, RT>::THREADS), 0, st, g, b);                                \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_corr_march<M, RT, RT, K, false>), dim3((unsigned)march_tiles<K, RT>(g)),    \
+                         dim3(MarchTile<K, RT>::THREADS), 0, st, g, b);                                \
+    break;
+      LBM_MARCH_CASE(6) LBM_MARCH_CASE(7)
+#undef LBM_MARCH_CASE
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2303,11 +2611,6 @@ struct RunDiag {
     return e;
   }
 };
-inline bool any_symmetry(const Geom &g) {
-  for (int k = 0; k < 6; ++k)
-    if (g.bc[k] == LBM_BC_SYMMETRY) return true;
-  return false;
-}
 template <int M, typename ST, typename RT>
 struct RunFlame {
   static hipError_t run(const Geom &g, const Buffers &b, const CollideConsts &kc, int cur, double T_iso,
@@ -2371,22 +2674,39 @@ hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc,
   return dispatch<RunStep>(g.M, store, g, b, kc, cur, st);
 }
 
+template <typename RT>
+void launch_psi_rt(const Geom &g, const Buffers &b, hipStream_t st) {
+  if (any_symmetry(g))
+    hipLaunchKernelGGL((k_psi<RT, true>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+  else
+    hipLaunchKernelGGL((k_psi<RT, false>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+}
+
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st) {
   if (store == LBM_STORE_F64)
-    hipLaunchKernelGGL((k_psi<Fmt<double>::Side>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    launch_psi_rt<Fmt<double>::Side>(g, b, st);
   else if (store == LBM_STORE_F32)
-    hipLaunchKernelGGL((k_psi<Fmt<float>::Side>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    launch_psi_rt<Fmt<float>::Side>(g, b, st);
   else
-    hipLaunchKernelGGL((k_psi<float>), dim3(blocks_for(g.N, 256)), dim3(256), 0, st, g, b);
+    launch_psi_rt<float>(g, b, st);
   return hipGetLastError();
 }
 
 int corr_tile_candidates(const Geom &g, int *out) {
   // the thin tiles take the node's own row for every y and z neighbour: one node thick only
   const bool thin = g.ny == 1 && g.nz == 1;
-  for (int k = 0; k < 3; ++k) out[k] = thin ? 3 + k : k;
-  return 3;
+  if (thin) {
+    for (int k = 0; k < 3; ++k) out[k] = 3 + k;
+    return 3;
+  }
+  // the tiles of k_corr after k_psi, then the z-marching shapes that form psi themselves
+  for (int k = 0; k < 3; ++k) out[k] = k;
+  out[3] = 6;
+  out[4] = 7;
+  return 5;
 }
+
+bool corr_forms_psi(int tile) { return tile >= 6; }
 
 hipError_t launch_corr_only(const Geom &g, const Buffers &b, int store, hipStream_t st) {
   return dispatch<RunCorr>(g.M, store, g, b, st);

@@ -119,9 +119,12 @@ hipError_t launch_step(const Geom &g, const Buffers &b, const CollideConsts &kc,
                        hipStream_t st);
 hipError_t launch_psi(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_corr(const Geom &g, const Buffers &b, int store, hipStream_t st);
-// the correction-stencil tile shapes valid for the lattice (3 of them), and one launch of
-// the stencil alone with g.corr_tile (for timing them)
+// the correction-stencil tile shapes valid for the lattice (their count, at most
+// LBM_CORR_TILES_MAX), whether a shape forms psi itself (then k_psi is not launched
+// before it), and one launch of the stencil alone with g.corr_tile (for timing them)
+constexpr int LBM_CORR_TILES_MAX = 8;
 int corr_tile_candidates(const Geom &g, int *out);
+bool corr_forms_psi(int tile);
 hipError_t launch_corr_only(const Geom &g, const Buffers &b, int store, hipStream_t st);
 hipError_t launch_ghost(const Geom &g, const Buffers &b, const CollideConsts &kc, int store, int cur,
                         hipStream_t st);
