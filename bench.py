@@ -231,17 +231,23 @@ def cpu_baseline_flame(prob):
     return cpu_baseline(prob, f"one flame of the batch ({prob.nx} cells)")
 
 
-def adjoint_cost(torch, lbm, W, dev, storage, every=100):
+def adjoint_cost(torch, lbm, W, dev, storage, every=None):
     """Cost of the discrete adjoint on its workload (the 2048-cell quasi-1D flame, 4000
-    steps, a snapshot every `every` steps): the forward alone (steps replayed from a
-    graph) against the whole gradient (forward with snapshots, then every segment
-    recomputed and reversed step by step), and one adjoint step against one forward
-    step."""
+    steps, a snapshot every `every` steps; None: the spacing FlameFront takes by
+    default, the smallest whose snapshots fit in half of the free device memory): the
+    forward alone (steps replayed from a graph) against the whole gradient (forward
+    with snapshots, then every segment recomputed and reversed step by step), and one
+    adjoint step against one forward step."""
     from paper_2101_01702_amd import adjoint as A
     prob = W.adjoint_flame(storage=storage)
     steps = 4000
     sync = lambda: torch.cuda.synchronize(dev)
     s = lbm.Solver(prob, storage=storage, device=dev, adjoint=True).init()
+    policy = "fixed"
+    if every is None:
+        free, _ = torch.cuda.mem_get_info(dev)
+        every = A.snapshot_spacing(steps, s.state_size(), 0.5 * free)
+        policy = f"the smallest that fits half of the {free / 2**30:.0f} GiB free"
     s.step_graph(steps)                      # records the graph
     s.init()
     sync()
@@ -277,6 +283,8 @@ def adjoint_cost(torch, lbm, W, dev, storage, every=100):
     s.close()
     return {"workload": f"quasi-1D flame of {prob.N} cells, 9 species, 19 reactions, {steps} steps, snapshot every "
                         f"{every}, {('f64', 'f32')[storage]} storage, FP64 adjoint",
+            "snapshot_every": int(every), "snapshot_policy": policy,
+            "snapshot_bytes": int(s.state_size()),
             "gradient_over_forward": round(grad_wall / fwd, 3), "forward_s": round(fwd, 4),
             "gradient_s": round(grad_wall, 4), "adjoint_step_ms": round(a1 * 1e3, 4),
             "forward_step_ms": round(f1 * 1e3, 4), "adjoint_step_over_forward_step": round(a1 / f1, 3),
@@ -408,8 +416,8 @@ def main():
                           "bytes": 2 * (4 << 30)}))
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100),
-                          "adjoint_all_states": adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=1)}))
+        print(json.dumps({"adjoint": adjoint_cost(torch, lbm, W, dev, W.STORE_F32),
+                          "adjoint_every_100": adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100)}))
         return
     if args.workload == "flame_batch":
         bench_flame_batch(args, torch, lbm, W, dev)
@@ -489,8 +497,8 @@ def main():
     out["copy_ceiling_GBps"] = {"runtime_copy": round(cc_runtime, 1), "stream_kernel": round(cc_stream, 1),
                                 "read2_write1": round(mc[0], 1), "read_only": round(mc[1], 1)}
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100)
-        out["adjoint_all_states"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=1)
+        out["adjoint"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32)
+        out["adjoint_every_100"] = adjoint_cost(torch, lbm, W, dev, W.STORE_F32, every=100)
         out["adjoint_forward_cost"] = out["adjoint"]["gradient_over_forward"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -13,8 +13,11 @@ K - 1 states of each after its snapshot and applies the library's adjoint step t
 reverse order.  K = 1 keeps every state resident (about 1.1 kB per node and step in FP32
 storage with nine species: 9 GB for the 2048-cell flame's 4000 steps) and recomputes
 nothing (lbm_adjoint_macros for the seed, lbm_adjoint_step per step,
-lbm_adjoint_init for T_0).  Only argument marshalling happens here: every step and
-every adjoint step runs in the HIP library.
+lbm_adjoint_init for T_0).  By default K is the smallest spacing whose snapshots (and
+the ring of recomputed states) fit in half of the device memory free at the call
+(``snapshot_spacing``): on a GPU of 288 GB that keeps every state of such runs, and
+recomputation only starts where memory runs short.  Only argument marshalling happens
+here: every step and every adjoint step runs in the HIP library.
 """
 from __future__ import annotations
 
@@ -26,12 +29,28 @@ def _torch():
     return torch
 
 
+def snapshot_spacing(n_steps: int, state_bytes: int, budget_bytes: float) -> int:
+    """Smallest K >= 1 for which ceil(n / K) snapshots and a ring of K - 1 recomputed
+    states, each of state_bytes, fit in budget_bytes (n_steps when none does)."""
+    n = max(int(n_steps), 1)
+    for k in range(1, n + 1):
+        if (-(-n // k) + k - 1) * state_bytes <= budget_bytes:
+            return k
+    return n
+
+
 class FlameFront:
     """Autograd function J(theta, T_0) over a Solver created with adjoint=True."""
 
     @staticmethod
-    def apply(solver, theta, T0, n_steps: int, every: int = 100, T_u: float = 300.0, T_b: float = 2000.0):
+    def apply(solver, theta, T0, n_steps: int, every=None, T_u: float = 300.0, T_b: float = 2000.0):
         torch = _torch()
+        if every is None:
+            free, _ = torch.cuda.mem_get_info(solver.device)
+            every = snapshot_spacing(n_steps, solver.state_size(), 0.5 * free)
+        every = int(every)
+        if every < 1:
+            raise ValueError("every must be >= 1")
 
         class _Fn(torch.autograd.Function):
             @staticmethod
