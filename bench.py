@@ -280,11 +280,12 @@ def adjoint_cost(torch, lbm, W, dev, storage, every=None):
     a1 = (time.perf_counter() - t0) / 200
     ok = bool(np.isfinite(theta.grad.numpy()).all() and np.isfinite(T0.grad.numpy()).all())
     anomaly = s.status()
+    snap_bytes = s.state_size()
     s.close()
     return {"workload": f"quasi-1D flame of {prob.N} cells, 9 species, 19 reactions, {steps} steps, snapshot every "
                         f"{every}, {('f64', 'f32')[storage]} storage, FP64 adjoint",
             "snapshot_every": int(every), "snapshot_policy": policy,
-            "snapshot_bytes": int(s.state_size()),
+            "snapshot_bytes": int(snap_bytes),
             "gradient_over_forward": round(grad_wall / fwd, 3), "forward_s": round(fwd, 4),
             "gradient_s": round(grad_wall, 4), "adjoint_step_ms": round(a1 * 1e3, 4),
             "forward_step_ms": round(f1 * 1e3, 4), "adjoint_step_over_forward_step": round(a1 / f1, 3),
