@@ -170,16 +170,18 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
 /* Validate the descriptor, copy it, and upload its tables into the caller's
  * device workspace (256-byte aligned, >= lbm_workspace_size bytes, must outlive
  * the handle).  The current HIP device must be the workspace's device.  The
- * upload is synchronous.  It then times the three tile shapes of the correction
- * stencil that suit the lattice (four launches each, on a non-blocking stream that the
- * call creates, waits for and destroys: lbm_create has no stream argument because it
- * returns only when the handle is ready, and the private stream keeps the timing apart
- * from the caller's streams) and keeps the fastest; LBM_CORR_TILE=k in the environment
- * (0-2 for lattices with a cross-section, 3-5 for lattices one node thick in y and z)
- * picks shape k instead.
- * Every shape gives the same bits.  The timing overwrites the side channel and the
- * deferred corrections in the workspace, so a state left there by another handle is
- * not kept: start from lbm_init_fields. */
+ * upload is synchronous.  It then times the shapes of the correction stencil (psi
+ * and the deferred corrections of eqs. Xalpha and corrFourier) that suit the lattice
+ * (four launches each, on a non-blocking stream that the call creates, waits for and
+ * destroys: lbm_create has no stream argument because it returns only when the handle
+ * is ready, and the private stream keeps the timing apart from the caller's streams)
+ * and keeps the fastest; LBM_CORR_TILE=k in the environment picks shape k instead:
+ * 0-2 (psi, then the corrections on tiles of 32x4x4, 64x2x2, 16x4x8 nodes) and 6-7
+ * (both in one pass along z, in chunks of 32 or 16 planes) for lattices with a
+ * cross-section, 3-5 for lattices one node thick in y and z.
+ * Every shape gives the same bits.  The timing overwrites the temperature, the side
+ * channel and the deferred corrections in the workspace, so a state left there by
+ * another handle is not kept: start from lbm_init_fields. */
 lbm_status lbm_create(const lbm_desc *desc, void *d_workspace, size_t bytes, lbm_handle *out);
 
 /* Release the host handle (the workspace is untouched). */
