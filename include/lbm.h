@@ -176,8 +176,8 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
  * destroys: lbm_create has no stream argument because it returns only when the handle
  * is ready, and the private stream keeps the timing apart from the caller's streams)
  * and keeps the fastest; LBM_CORR_TILE=k in the environment picks shape k instead:
- * 0-2 (psi, then the corrections on tiles of 32x4x4, 64x2x2, 16x4x8 nodes) and 6-7
- * (both in one pass along z, in chunks of 32 or 16 planes) for lattices with a
+ * 0-2 (psi, then the corrections on tiles of 32x4x4, 64x2x2, 16x4x8 nodes) and 6
+ * (both in one pass along z, in chunks of 32 planes) for lattices with a
  * cross-section, 3-5 for lattices one node thick in y and z.
  * Every shape gives the same bits.  The timing overwrites the temperature, the side
  * channel and the deferred corrections in the workspace, so a state left there by

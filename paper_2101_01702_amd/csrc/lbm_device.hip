@@ -1570,12 +1570,11 @@ struct MarchTileT {
   static constexpr int PPT = (PCELLS + THREADS - 1) / THREADS, SPT = (SCELLS + THREADS - 1) / THREADS;
   static_assert(SCELLS >= THREADS, "every thread holds a cell of each tile");
 };
-// shapes 6 and 7 (corr_tile_candidates): chunks of 32 and 16 planes; narrower in y for
-// FP64 fields, whose tiles take twice the LDS
+// shape 6 (corr_tile_candidates): chunks of 32 planes (16 measured no faster); narrower
+// in y for FP64 fields, whose tiles take twice the LDS
 template <int K, typename RT>
 struct MarchTile;
 template <typename RT> struct MarchTile<6, RT> : MarchTileT<32, sizeof(RT) == 8 ? 4 : 8, 32> {};
-template <typename RT> struct MarchTile<7, RT> : MarchTileT<32, sizeof(RT) == 8 ? 4 : 8, 16> {};
 
 template <int K, typename RT>
 inline int64_t march_tiles(const Geom &g) {
@@ -2561,7 +2560,7 @@ struct RunCorr {
       hipLaunchKernelGGL((k_corr_march<M, RT, RT, K, false>), dim3((unsigned)march_tiles<K, RT>(g)),    \
                          dim3(MarchTile<K, RT>::THREADS), 0, st, g, b);                                \
     break;
-      LBM_MARCH_CASE(6) LBM_MARCH_CASE(7)
+      LBM_MARCH_CASE(6)
 #undef LBM_MARCH_CASE
       default: return hipErrorInvalidValue;
     }
@@ -2702,8 +2701,7 @@ int corr_tile_candidates(const Geom &g, int *out) {
   // the tiles of k_corr after k_psi, then the z-marching shapes that form psi themselves
   for (int k = 0; k < 3; ++k) out[k] = k;
   out[3] = 6;
-  out[4] = 7;
-  return 5;
+  return 4;
 }
 
 bool corr_forms_psi(int tile) { return tile >= 6; }
