@@ -204,13 +204,19 @@ __device__ __forceinline__ double pop_val(ST raw, int s, int i, const K &kc) {
   else
     return double(raw);
 }
-// stored form of the population value v of set s along direction i
+// stored form of the population value v of set s along direction i: rounded to FP32,
+// then to the 16-bit format.  The FP32 value is made opaque so that the two roundings
+// stay two hardware conversions; folded into one double -> half conversion, the
+// compiler emulates it in integer instructions (about 30 per value).
 template <typename ST, typename K>
 __device__ __forceinline__ ST pop_enc(double v, int s, int i, const K &kc) {
-  if constexpr (Fmt<ST>::dev)
-    return ST(float((v - double(kc.ref[s][i])) * double(kc.isc[s])));
-  else
+  if constexpr (Fmt<ST>::dev) {
+    float t = float((v - double(kc.ref[s][i])) * double(kc.isc[s]));
+    opaque(t);
+    return ST(t);
+  } else {
     return ST(v);
+  }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with its own
