@@ -2155,7 +2155,9 @@ __global__ __launch_bounds__(64) void k_export(Geom g, Buffers b, CollideConsts 
   if (k >= nn) return;
   const int64_t n = nodes[k];
   if (n < 0 || n >= g.N) return;
-  const int x = (int)(n % g.nx), y = (int)((n / g.nx) % g.ny), z = (int)(n / ((int64_t)g.nx * g.ny));
+  // a lattice has fewer than 2^30 nodes: 32-bit division
+  const uint32_t un = (uint32_t)n, unx = (uint32_t)g.nx, uny = (uint32_t)g.ny;
+  const int x = (int)(un % unx), y = (int)((un / unx) % uny), z = (int)(un / (unx * uny));
   const int64_t NPAD = g.NPAD;
   using Side = typename Fmt<ST>::Side;
   const ST *pop = static_cast<const ST *>(b.pop[cur]);
@@ -2167,22 +2169,27 @@ __global__ __launch_bounds__(64) void k_export(Geom g, Buffers b, CollideConsts 
   const int kyz = blockIdx.y / 3, kx_run = blockIdx.y % 3;
   const int ky = kyz % 3, kz = kyz / 3;
   const int cy = ky - 1, cz = kz - 1;
+  const int i = kx_run + 3 * kyz;
+  const Src r = make_src(g, ax, ay, az, kx_run, ky, kz);
+  // every set's value first, then the stores: a store between two loads would wait for
+  // the first load, one round trip per set.  The species loads go out ahead of the
+  // branch on the direction's x component, in which f and g are pulled with their
+  // corrections, so that all the loads of the direction are in flight together.
+  ST sp[M - 1];
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) sp[a] = ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps);
+  double v[M + 1];
   static_for<3>([&](auto Kx) {
     constexpr int kx = decltype(Kx)::value;
     constexpr int cx = kx - 1;
     if (kx != kx_run) return;
-    const int i = kx + 3 * kyz;
-    const Src r = make_src(g, ax, ay, az, kx, ky, kz);
-    // every set's value first, then the stores: a store between two loads would wait
-    // for the first load, one round trip per set
-    double v[M + 1];
     v[M - 1] = pull_f<cx, ST, Side>(pop + ((int64_t)(M - 1) * Q + i) * NPAD, r, cr, cy, cz, M - 1, i, kc);
     v[M] = pull_g<cx, ST, Side>(pop + ((int64_t)M * Q + i) * NPAD, r, cr, cy, cz, M, i, kc);
-#pragma unroll
-    for (int a = 0; a < M - 1; ++a) v[a] = pop_val(ld(pop + ((int64_t)a * Q + i) * NPAD, r.ps), a, i, kc);
-#pragma unroll
-    for (int s2 = 0; s2 <= M; ++s2) out[((int64_t)s2 * Q + i) * nn + k] = v[s2];
   });
+#pragma unroll
+  for (int a = 0; a < M - 1; ++a) v[a] = pop_val(sp[a], a, i, kc);
+#pragma unroll
+  for (int s2 = 0; s2 <= M; ++s2) out[((int64_t)s2 * Q + i) * nn + k] = v[s2];
   if (T_out && blockIdx.y == 0) T_out[k] = b.T[n];
 }
 
