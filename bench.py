@@ -203,12 +203,16 @@ def burning_flame(torch, lbm, W, dev, storage, label, n, warm=200, steps=20):
 
 def error_vs_f64_full(lbm, W, storage, n, steps):
     """The same field error at full size: the benchmarked storage against FP64 storage
-    on the n^3 flame after `steps` steps (both runs on the GPU)."""
+    on the n^3 flame after `steps` steps (both runs on the GPU), with the velocity floor
+    1e-3 sqrt(zeta_ref) of error_vs_f64."""
     import numpy as np
     import torch
     out = {}
+    zeta = None
     for st in (W.STORE_F64, storage):
         prob = W.sphere3d(n=n, storage=st)
+        if zeta is None:   # the unburnt lattice RT, as in error_vs_f64
+            zeta = prob.kappa * W.R_U * prob.T.min() / (1e-3 / (prob.Y[:, 0] / prob.mech.molar_mass).sum())
         s = lbm.Solver(prob, storage=st).init()
         del prob.rho, prob.u, prob.T, prob.Y
         s.step(steps)
@@ -217,7 +221,7 @@ def error_vs_f64_full(lbm, W, storage, n, steps):
         del s
         torch.cuda.empty_cache()
     a, b = out[storage], out[W.STORE_F64]
-    zeta_floor = math.sqrt(0.003)   # sqrt of the unburnt lattice RT, as in error_vs_f64
+    zeta_floor = 1e-3 * math.sqrt(zeta)
     errs = {k: float(np.abs(a[k] - b[k]).max() / np.abs(b[k]).max()) for k in ("rho", "T", "P")}
     errs["u"] = float(max(np.abs(a["u"][d] - b["u"][d]).max() / max(np.abs(b["u"][d]).max(), zeta_floor)
                           for d in range(3)))
