@@ -201,6 +201,30 @@ def burning_flame(torch, lbm, W, dev, storage, label, n, warm=200, steps=20):
             "error_vs_f64": error_vs_f64(lbm, W, storage, steps=500, prob=crop, lattice="96x96x4 crop of the burning flame")}
 
 
+def circular_flame_2d(torch, lbm, W, dev, storage, label, n=1200, warm=200, steps=50):
+    """The expanding circular flame of Sec. 5.2 on the paper's grid size, n x n x 1 (open
+    x and y faces, a 2000 K disc of radius 32 in the premixture), timed over `steps`
+    steps after `warm` steps of burning."""
+    prob = W.cylinder3d(n=n, nz=1, storage=storage)
+    s = lbm.Solver(prob, storage=storage, device=dev).init()
+    s.step(warm)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    _, tot = s.diagnostics(1200.0)
+    Tmax = float(s.macros(to_numpy=False)["T"].max())
+    anomaly = s.status()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return {"workload": f"circular flame (Sec. 5.2), {n}x{n} (the paper's grid), open x/y faces, 2000 K disc of "
+                        f"radius 32, {label} population storage",
+            "value": round(prob.N * steps / dt / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 3),
+            "after_steps": warm, "T_max": round(Tmax, 1), "burnt_cells": int(tot[1]), "anomaly_bits": anomaly}
+
+
 def error_vs_f64_full(lbm, W, storage, n, steps):
     """The same field error at full size: the benchmarked storage against FP64 storage
     on the n^3 flame after `steps` steps (both runs on the GPU), with the velocity floor
@@ -495,6 +519,7 @@ def main():
     if not args.no_error_check:
         out["error_vs_f64"] = error_vs_f64(lbm, W, storage)
         out["burning_flame"] = burning_flame(torch, lbm, W, dev, storage, args.storage, args.n)
+        out["circular_flame_2d"] = circular_flame_2d(torch, lbm, W, dev, storage, args.storage)
     if args.full_error_steps > 0 and storage != W.STORE_F64:
         out["error_vs_f64_full"] = error_vs_f64_full(lbm, W, storage, args.n, args.full_error_steps)
     cc_runtime, cc_stream = copy_ceiling_gbs(torch, dev, lbm)
