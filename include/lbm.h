@@ -178,7 +178,8 @@ lbm_status lbm_workspace_size(const lbm_desc *desc, size_t *bytes);
  * and keeps the fastest; LBM_CORR_TILE=k in the environment picks shape k instead:
  * 0-2 (psi, then the corrections on tiles of 32x4x4, 64x2x2, 16x4x8 nodes) and 6
  * (both in one pass along z, in chunks of 32 planes) for lattices with a
- * cross-section, 3-5 for lattices one node thick in y and z.
+ * cross-section, with 9 (a tile of 32x8x1) when they are one node thick in z, and 3-5
+ * for lattices one node thick in y and z.
  * Every shape gives the same bits.  The timing overwrites the temperature, the side
  * channel and the deferred corrections in the workspace, so a state left there by
  * another handle is not kept: start from lbm_init_fields. */

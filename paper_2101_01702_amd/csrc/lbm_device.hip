@@ -1454,11 +1454,12 @@ __global__ __launch_bounds__(256) void k_psi(Geom g, Buffers b) {
 // A lattice one node thick in y and z (quasi-1D flames and their batches) takes a tile
 // of 256 x 1 x 1 with no y or z halo: its y and z neighbours are the node's own row
 // (wrapped on periodic axes, clamped on open ones), so 32 x 4 x 4 tiles would leave 15
-// of 16 threads idle.
+// of 16 threads idle.  A lattice one node thick in z alone (2D flames) can take a tile
+// of 32 x 8 x 1 with no z halo, for the same reason.
 template <int TX, int TY, int TZ, bool TH>
 struct CorrTileT {
-  static constexpr bool THIN = TH;
-  static constexpr int X = TX, Y = TY, Z = TZ, HX = X + 2, HY = TH ? 1 : Y + 2, HZ = TH ? 1 : Z + 2;
+  static constexpr bool THIN = TH, FLAT = !TH && TZ == 1;
+  static constexpr int X = TX, Y = TY, Z = TZ, HX = X + 2, HY = TH ? 1 : Y + 2, HZ = (TH || FLAT) ? 1 : Z + 2;
   static constexpr int THREADS = X * Y * Z, CELLS = HX * HY * HZ;
 };
 // the tile shapes a lattice chooses from (corr_tile_candidates): 0-2 for lattices with a
@@ -1471,6 +1472,7 @@ template <> struct CorrTile<2> : CorrTileT<16, 4, 8, false> {};
 template <> struct CorrTile<3> : CorrTileT<256, 1, 1, true> {};
 template <> struct CorrTile<4> : CorrTileT<128, 1, 1, true> {};
 template <> struct CorrTile<5> : CorrTileT<512, 1, 1, true> {};
+template <> struct CorrTile<9> : CorrTileT<32, 8, 1, false> {};
 
 __device__ __forceinline__ int halo_coord(int v, int n, bool periodic) {
   if (periodic) {
@@ -1489,7 +1491,7 @@ inline int64_t corr_tiles(const Geom &g) {
 template <int M, typename RT, typename CT, int K>
 __global__ __launch_bounds__(CorrTile<K>::THREADS) void k_corr(Geom g, Buffers b) {
   using T = CorrTile<K>;
-  constexpr bool THIN = T::THIN;
+  constexpr bool THIN = T::THIN, FLAT = T::FLAT;
   constexpr int CH_X = T::HX, CH_Y = T::HY, CH_CELLS = T::CELLS;
   __shared__ RT sh[(M + 3) * CH_CELLS];   // field f of halo cell c at f * CH_CELLS + c
   const int tiles_x = (g.nx + T::X - 1) / T::X, tiles_y = (g.ny + T::Y - 1) / T::Y;
@@ -1504,7 +1506,7 @@ __global__ __launch_bounds__(CorrTile<K>::THREADS) void k_corr(Geom g, Buffers b
     const int hx = c % CH_X, hy = (c / CH_X) % CH_Y, hz = c / (CH_X * CH_Y);
     const int gx = halo_coord(x0 + hx - 1, g.nx, g.per[0]);
     const int gy = THIN ? 0 : halo_coord(y0 + hy - 1, g.ny, g.per[1]);
-    const int gz = THIN ? 0 : halo_coord(z0 + hz - 1, g.nz, g.per[2]);
+    const int gz = (THIN || FLAT) ? 0 : halo_coord(z0 + hz - 1, g.nz, g.per[2]);
     const int64_t nn = ((int64_t)gz * g.ny + gy) * g.nx + gx;
 #pragma unroll
     for (int f = 0; f < 3; ++f) sh[f * CH_CELLS + c] = psi[f * N + nn];
@@ -1516,7 +1518,7 @@ __global__ __launch_bounds__(CorrTile<K>::THREADS) void k_corr(Geom g, Buffers b
   const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
   if (x >= g.nx || y >= g.ny || z >= g.nz) return;
   const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
-  const int c0 = THIN ? lx + 1 : ((lz + 1) * CH_Y + (ly + 1)) * CH_X + (lx + 1);
+  const int c0 = THIN ? lx + 1 : ((FLAT ? 0 : (lz + 1) * CH_Y) + (ly + 1)) * CH_X + (lx + 1);
   // x neighbours stay within the node's segment: at its ends the stencil takes the node
   // itself (the halo cell beyond the lattice's ends holds the same value)
   const XSeg xsg = x_segment(g, x);
@@ -1530,7 +1532,7 @@ __global__ __launch_bounds__(CorrTile<K>::THREADS) void k_corr(Geom g, Buffers b
     constexpr int I = decltype(Ic)::value;
     constexpr int cx = cx_of(I), cy = cy_of(I), cz = cz_of(I);
     if constexpr (I != 13) {
-      const int nc = c0 + (THIN ? 0 : (cz * CH_Y + cy) * CH_X) + (cx < 0 ? dxm : (cx > 0 ? dxp : 0));
+      const int nc = c0 + (THIN ? 0 : ((FLAT ? 0 : cz * CH_Y) + cy) * CH_X) + (cx < 0 ? dxm : (cx > 0 ? dxp : 0));
       constexpr double w = 3.0 * wgt(I);
       if constexpr (cx != 0) X[0] -= (cx * w) * double(sh[0 * CH_CELLS + nc]);
       if constexpr (cy != 0) X[1] -= (cy * w) * double(sh[1 * CH_CELLS + nc]);
@@ -2563,6 +2565,7 @@ struct RunCorr {
                        st, g, b);                                                                     \
     break;
       LBM_CORR_CASE(0) LBM_CORR_CASE(1) LBM_CORR_CASE(2) LBM_CORR_CASE(3) LBM_CORR_CASE(4) LBM_CORR_CASE(5)
+      LBM_CORR_CASE(9)
 #undef LBM_CORR_CASE
 #define LBM_MARCH_CASE(K)                                                                              \
   case K:                                                                                              \
@@ -2711,13 +2714,18 @@ int corr_tile_candidates(const Geom &g, int *out) {
     for (int k = 0; k < 3; ++k) out[k] = 3 + k;
     return 3;
   }
-  // the tiles of k_corr after k_psi, then the z-marching shapes that form psi themselves
+  // the tiles of k_corr after k_psi, then the z-marching shape that forms psi itself,
+  // and on a lattice one node thick in z the flat tile
   for (int k = 0; k < 3; ++k) out[k] = k;
   out[3] = 6;
+  if (g.nz == 1) {
+    out[4] = 9;
+    return 5;
+  }
   return 4;
 }
 
-bool corr_forms_psi(int tile) { return tile >= 6; }
+bool corr_forms_psi(int tile) { return tile == 6; }
 
 hipError_t launch_corr_only(const Geom &g, const Buffers &b, int store, hipStream_t st) {
   return dispatch<RunCorr>(g.M, store, g, b, st);

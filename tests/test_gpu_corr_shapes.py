@@ -1,6 +1,7 @@
 """The tile shapes of the correction stencil (eqs. X and the energy-flux correction, with
 psi of the isotropy correction), which lbm_create times and from which it keeps the
-fastest: k_corr after k_psi in three tiles (0-2), and k_corr_march (6),
+fastest: k_corr after k_psi in three tiles (0-2), or in a flat one (9) on lattices one
+node thick in z, and k_corr_march (6),
 which forms psi itself from phi while it walks a column of the lattice along z, so
 that psi never goes through HBM.  Every shape reads the same values and sums them in
 the same order: a run gives the same bits whichever shape it takes.  Covered: chunks
@@ -23,6 +24,7 @@ pytestmark = pytest.mark.gpu
 S, O, P, U0 = W.BC_SYMMETRY, W.BC_OPEN, W.BC_PERIODIC, W.BC_OPEN_U0
 SPLIT = (0, 1, 2)        # k_psi, then k_corr
 MARCH = (6,)             # k_corr_march
+FLAT = (9,)              # k_psi, then k_corr on a 32 x 8 x 1 tile (lattices one node thick in z)
 
 
 @pytest.fixture(scope="module")
@@ -82,7 +84,7 @@ def _same(a, b, what):
 def test_marching_shapes_give_the_same_bits_fp64(lbm_mod, name, monkeypatch):
     prob = lattice(name)
     ref = _run(lbm_mod, prob, W.STORE_F64, 0, 20, monkeypatch)
-    for tile in SPLIT[1:] + MARCH:
+    for tile in SPLIT[1:] + MARCH + (FLAT if prob.nz == 1 else ()):
         _same(_run(lbm_mod, prob, W.STORE_F64, tile, 20, monkeypatch), ref, (name, tile))
 
 
@@ -103,7 +105,7 @@ def test_marching_shapes_on_random_lattices(lbm_mod, monkeypatch):
         if prob.ny == 1 and prob.nz == 1:
             continue
         ref = _run(lbm_mod, prob, W.STORE_F64, 0, 10, monkeypatch)
-        for tile in MARCH:
+        for tile in MARCH + (FLAT if prob.nz == 1 else ()):
             _same(_run(lbm_mod, prob, W.STORE_F64, tile, 10, monkeypatch), ref, (prob.name, tile))
         n += 1
     assert n >= 30
