@@ -146,6 +146,23 @@ def test_cylinder3d_fp32_1000_steps(lbm_mod):
     _assert_fields(mac, sim.macros(), prob, TOL32, "cylinder3d 32x32x2 fp32 1000")
 
 
+@pytest.mark.parametrize("tile", [None, 9])
+def test_circle2d_fp64(lbm_mod, tile, monkeypatch):
+    """The expanding circular flame of Sec. 5.2 on one plane (40 x 40 x 1, open x and y
+    faces, a 2000 K disc of radius 10): FP64 to 1e-12 on fields and every population
+    after 100 steps, with the correction stencil's timed shape and with the flat
+    32 x 8 x 1 tile forced."""
+    if tile is not None:
+        monkeypatch.setenv("LBM_CORR_TILE", str(tile))
+    prob = W.cylinder3d(n=40, nz=1, radius=10.0, storage=W.STORE_F64)
+    s, mac, bits = _gpu_run(lbm_mod, prob, 100, W.STORE_F64)
+    sim, anom = oracle_run(prob, 100)
+    assert bits == 0 and anom == 0
+    _assert_fields(mac, sim.macros(), prob, TOL64, f"circle2d 40x40x1 fp64 100 tile {tile}")
+    pop, _ = s.populations(np.arange(prob.N))
+    assert max(pop_errors(pop, sim.state()[0])) <= TOL64
+
+
 # --- edge cases ------------------------------------------------------------------------
 @pytest.mark.parametrize("shape,bc", [
     ((1, 1, 7), (0, 0, 0, 0, 1, 2)),     # z-only column, zero-velocity top face
