@@ -201,11 +201,20 @@ def burning_flame(torch, lbm, W, dev, storage, label, n, warm=200, steps=20):
             "error_vs_f64": error_vs_f64(lbm, W, storage, steps=500, prob=crop, lattice="96x96x4 crop of the burning flame")}
 
 
-def circular_flame_2d(torch, lbm, W, dev, storage, label, n=1200, warm=200, steps=50):
+def circular_flame_2d(torch, lbm, W, dev, storage, label, n=1200, warm=200, steps=50, until=3000, every=250,
+                      T_iso=1200.0, fit_from=1000):
     """The expanding circular flame of Sec. 5.2 on the paper's grid size, n x n x 1 (open
     x and y faces, a 2000 K disc of radius 32 in the premixture), timed over `steps`
-    steps after `warm` steps of burning."""
+    steps after `warm` steps of burning; then run on to `until` steps, with the mean
+    radius of the T_iso isotherm (eq. rmean) every `every` steps, and, from step
+    `fit_from` on (after the kernel's first contraction), the growth exponent of
+    R = a t^alpha (Sec. 5.2) and the rate dR/dt of a straight line.  The centre is the
+    centroid of the initial hot disc."""
+    import numpy as np
     prob = W.cylinder3d(n=n, nz=1, storage=storage)
+    hot = prob.T - prob.T.min()
+    idx = np.arange(prob.N)
+    centre = (float((idx % n * hot).sum() / hot.sum()), float((idx // n * hot).sum() / hot.sum()), 0.0)
     s = lbm.Solver(prob, storage=storage, device=dev).init()
     s.step(warm)
     torch.cuda.synchronize(dev)
@@ -213,16 +222,28 @@ def circular_flame_2d(torch, lbm, W, dev, storage, label, n=1200, warm=200, step
     s.step(steps)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
-    _, tot = s.diagnostics(1200.0)
+    _, tot = s.diagnostics(T_iso)
     Tmax = float(s.macros(to_numpy=False)["T"].max())
+    done, ts, rs = warm + steps, [], []
+    for target in range(every * ((done + every - 1) // every), until + 1, every):
+        s.step(target - done)
+        done = target
+        ts.append(target)
+        rs.append(round(s.mean_radius(T_iso, centre=centre), 3))
     anomaly = s.status()
     s.close()
     del s
     torch.cuda.empty_cache()
+    fit = [(t, r) for t, r in zip(ts, rs) if t >= fit_from]
+    _, alpha = lbm.growth_exponent([t for t, _ in fit], [r for _, r in fit])
+    rate = float(np.polyfit([t for t, _ in fit], [r for _, r in fit], 1)[0])
     return {"workload": f"circular flame (Sec. 5.2), {n}x{n} (the paper's grid), open x/y faces, 2000 K disc of "
                         f"radius 32, {label} population storage",
             "value": round(prob.N * steps / dt / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 3),
-            "after_steps": warm, "T_max": round(Tmax, 1), "burnt_cells": int(tot[1]), "anomaly_bits": anomaly}
+            "after_steps": warm, "T_max": round(Tmax, 1), "burnt_cells": int(tot[1]),
+            "mean_radius": {"T_iso": T_iso, "steps": ts, "radius": rs}, "fit_from_step": fit_from,
+            "growth_exponent": round(alpha, 4), "radius_rate_cells_per_step": round(rate, 7),
+            "anomaly_bits": anomaly}
 
 
 def error_vs_f64_full(lbm, W, storage, n, steps):
