@@ -17,6 +17,7 @@ import pytest
 from paper_2101_01702_amd import workloads as W
 from gpu_cases import check_fp64, field_errors, oracle_run, pop_errors, zeta_of, TOL64
 from test_gpu_random_cases import random_case
+from test_gpu_species_counts import problem as species_problem
 from test_gpu_symmetry import sym_problem
 
 pytestmark = pytest.mark.gpu
@@ -109,6 +110,18 @@ def test_marching_shapes_on_random_lattices(lbm_mod, monkeypatch):
             _same(_run(lbm_mod, prob, W.STORE_F64, tile, 10, monkeypatch), ref, (prob.name, tile))
         n += 1
     assert n >= 30
+
+
+@pytest.mark.parametrize("M", range(2, 11))
+def test_marching_shape_every_species_count(lbm_mod, M, monkeypatch):
+    """Every species count the library builds (its own instance of the marching kernel,
+    with M mass-fraction planes in LDS), on the ragged 7x5x4 lattice with open,
+    zero-velocity and symmetry faces: the same bits as k_psi + k_corr, FP64 and FP32."""
+    prob = species_problem(M)
+    for storage in (W.STORE_F64, W.STORE_F32):
+        ref = _run(lbm_mod, prob, storage, 0, 20, monkeypatch)
+        for tile in MARCH:
+            _same(_run(lbm_mod, prob, storage, tile, 20, monkeypatch), ref, (prob.name, storage, tile))
 
 
 @pytest.mark.parametrize("tile", MARCH)
